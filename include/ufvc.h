@@ -1,0 +1,157 @@
+/*
+ * ufvc.h - C ABI of the MI355X chunk video codec hot path.
+ *
+ * The codec follows the chunk coding of "Ultra-Fast Neural Video Compression"
+ * (DCVC-UF): a chunk of T frames is patch-embedded to 1/8 resolution, encoded
+ * by one chunk encoder into a single latent y, and decoded by a shared chunk
+ * decoder followed by T frame-specific decoders (Sec. 3.1, 3.2).  Entropy
+ * coding is single-step (Sec. 3.4): one pass predicts the mean mu and scale
+ * sigma of every latent element from the hyper prior z_hat, the residual
+ * r_hat = round(y - mu) is coded with tables chosen by sigma alone, and the
+ * decoder recovers all of r_hat in one bit-stream interaction before adding
+ * mu back.  The networks are a stand-in (plain 3x3 convolutions, weights
+ * supplied by the caller); the arithmetic coder is 32-lane interleaved rANS.
+ *
+ * Conventions shared by every entry point
+ *  - Device pointers: frames, bit-streams, symbol and index arrays passed to
+ *    the coding calls are device (HBM) memory allocated and owned by the
+ *    caller.  The library owns only its context, weights, tables and
+ *    workspaces, all freed by ufvc_destroy.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Work is enqueued in stream order.
+ *  - Frames: float32, layout [T][3][H][W] contiguous, values in [0, 1].
+ *    H and W are multiples of 8 and at least 16; internally they are padded
+ *    up to multiples of 16 by edge replication and cropped on output.
+ *  - Errors: every call returns a ufvc_status.  Host-checkable argument
+ *    errors return immediately without enqueuing work.  Errors found on the
+ *    device while decoding (bad header, corrupt stream) are accumulated in a
+ *    per-context device status word, read and cleared by ufvc_sync_status.
+ *  - Threads: a context may be used by one host thread at a time.
+ */
+#ifndef UFVC_H
+#define UFVC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  UFVC_OK = 0,
+  UFVC_E_INVAL = -1,       /* bad argument or header mismatch */
+  UFVC_E_NOSPC = -2,       /* output capacity too small; *out_len = size needed */
+  UFVC_E_CORRUPT = -3,     /* bit-stream failed its integrity checks */
+  UFVC_E_DEVICE = -4,      /* a HIP runtime call failed */
+  UFVC_E_NOMEM = -5,       /* device allocation failed */
+  UFVC_E_UNSUPPORTED = -6  /* configuration outside what the kernels support */
+} ufvc_status;
+
+typedef enum {
+  UFVC_FP32 = 0,      /* every convolution in float32 (MFMA f32) */
+  UFVC_BF16 = 1,      /* analysis and synthesis convs bf16 MFMA, fp32 accumulate */
+  UFVC_BF16_FP8 = 2   /* as BF16, synthesis convs in FP8 E4M3 */
+} ufvc_precision;
+
+typedef struct {
+  int T;               /* frames per chunk, 1..8 (one model per T, Sec. 4.1) */
+  int C;               /* latent channels: 64 or 128 */
+  int precision;       /* ufvc_precision */
+  int seg_log2;        /* y symbols per rANS segment = 2^seg_log2, 5..24 */
+  int seg_log2_z;      /* z symbols per rANS segment = 2^seg_log2_z, 5..24 */
+  uint32_t model_tag;  /* written to and checked against every bit-stream */
+} ufvc_config;
+
+typedef struct ufvc_ctx ufvc_ctx;
+
+/* Number of float32 weights ufvc_create expects for (T, C): the layers
+ * a1 (C x 192T x 3 x 3), a2, a3 (C x C), h (32 x C), p (2C x 32), d1, d2, d3
+ * (C x C), then for t = 0..T-1: k1_t, k2_t (C x C), k3_t (192 x C), each
+ * OIHW, concatenated in that order.  Returns 0 for unsupported (T, C). */
+size_t ufvc_weight_count(int T, int C);
+
+/* Creates a context on the current HIP device: validates cfg, repacks the
+ * host float32 `weights` (n_weights values, layout above; read only during
+ * the call, still owned by the caller) into the kernels' layouts, and builds
+ * the Gaussian CDF tables in FP64 on the device.  Blocks until done.
+ * Errors: INVAL (cfg or n_weights), UNSUPPORTED, NOMEM, DEVICE. */
+int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights,
+                ufvc_ctx** out);
+
+/* Frees every device allocation of the context (after a device sync). */
+void ufvc_destroy(ufvc_ctx* ctx);
+
+/* Upper bound on the coded size of one T x H x W chunk (every symbol at
+ * 16 bits, plus states, padding, header and segment table). */
+size_t ufvc_max_bitstream_bytes(const ufvc_ctx* ctx, int H, int W);
+
+/* Encodes one chunk (Sec. 3.1 chunk encoder + Sec. 3.4 entropy coding).
+ * frames: device [T][3][H][W] float32 with T equal to the context's T.
+ * bitstream: device buffer of `capacity` bytes.  On success *out_len is the
+ * coded size.  The call is stream-ordered and synchronises `stream` once at
+ * the end to read the size.  NOSPC: nothing is written past the header and
+ * *out_len holds the size needed. */
+int ufvc_encode_chunk(ufvc_ctx* ctx, const float* frames, int T, int H, int W,
+                      uint8_t* bitstream, size_t capacity, size_t* out_len,
+                      void* stream);
+
+/* Decodes one chunk into device frames_out [T][3][H][W] float32 (Sec. 3.1,
+ * 3.2; r_hat decoded in one step from sigma alone, then y_hat = r_hat + mu,
+ * Sec. 3.4).  bitstream: device, `len` bytes.  Asynchronous: returns after
+ * enqueuing.  The header must match (T, H, W), the context's C, segment
+ * sizes and model tag; mismatches set INVAL and integrity failures set
+ * CORRUPT in the device status (read with ufvc_sync_status).  The kernels
+ * never read outside [bitstream, bitstream + len) and always terminate; on
+ * error the frames hold unspecified but finite values. */
+int ufvc_decode_chunk(ufvc_ctx* ctx, const uint8_t* bitstream, size_t len,
+                      int T, int H, int W, float* frames_out, void* stream);
+
+/* Synchronises `stream`, returns the first device-side error recorded since
+ * the last call (UFVC_OK if none) and clears it. */
+int ufvc_sync_status(ufvc_ctx* ctx, void* stream);
+
+/* ---- Stage-level entry points (same kernels; used for parity testing) ---- */
+
+/* Copies the device-built tables to host memory: freq and cum as 64 x 65
+ * uint16 each (row = scale index, column = symbol r + 32), thresholds as 63
+ * float32 (scale index = number of thresholds <= sigma).  Synchronous. */
+int ufvc_get_tables(ufvc_ctx* ctx, uint16_t* freq, uint16_t* cum, float* thresholds);
+
+/* rANS-encodes n symbols (device uint8, values 0..64) with per-symbol table
+ * rows idx (device uint8, 0..63) in segments of 2^seg_log2 symbols.  Output
+ * (device, `capacity` bytes): uint32 seg_bytes[n_seg] then the segments, in
+ * the container's segment format.  *out_len = bytes written (or needed, with
+ * NOSPC).  Synchronises `stream`. */
+int ufvc_rans_encode(ufvc_ctx* ctx, const uint8_t* sym, const uint8_t* idx, size_t n,
+                     int seg_log2, uint8_t* out, size_t capacity, size_t* out_len,
+                     void* stream);
+
+/* Inverse of ufvc_rans_encode: `in` (device, len bytes) -> sym (device, n
+ * bytes).  Asynchronous; integrity failures set CORRUPT in the status. */
+int ufvc_rans_decode(ufvc_ctx* ctx, const uint8_t* in, size_t len, const uint8_t* idx,
+                     size_t n, int seg_log2, uint8_t* sym, void* stream);
+
+/* Runs the chunk decoder and frame decoders on a caller-provided latent
+ * y_hat (device float32, channels innermost [h][w][C], h = Hp/8, w = Wp/8)
+ * and writes frames_out.  Asynchronous. */
+int ufvc_synthesize(ufvc_ctx* ctx, const float* y_hat, int T, int H, int W,
+                    float* frames_out, void* stream);
+
+/* Workspace views left by the last encode / decode, copied to host memory
+ * (synchronises the context's last stream).  Element types and layouts
+ * (channels innermost, [h][w][c]):
+ *   UFVC_BUF_Y      float32 [h][w][C]    analysis output y (encoder)
+ *   UFVC_BUF_ZSYM   uint8   [hz][wz][32] z_hat + 32
+ *   UFVC_BUF_PARAMS float32 [h][w][2C]   mu (first C) and raw scale logits
+ *   UFVC_BUF_IDX    uint8   [h][w][C]    table index from sigma
+ *   UFVC_BUF_SYM    uint8   [h][w][C]    r_hat + 32
+ * `bytes` must equal the buffer size for the last (H, W). */
+enum { UFVC_BUF_Y = 0, UFVC_BUF_ZSYM = 1, UFVC_BUF_PARAMS = 2, UFVC_BUF_IDX = 3,
+       UFVC_BUF_SYM = 4 };
+int ufvc_copy_buffer(ufvc_ctx* ctx, int which, void* host_dst, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UFVC_H */

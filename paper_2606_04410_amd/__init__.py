@@ -1,0 +1,213 @@
+"""MI355X chunk video codec (DCVC-UF hot path) - Python binding of libufvc.
+
+Argument marshalling only: every step of encode / decode runs in the HIP
+kernels of ``libufvc.so``.  PyTorch provides device memory and streams; tensors
+are passed to the C ABI as raw device pointers.  Importing this package loads
+the library and raises if it is missing (build it with
+``python -m paper_2606_04410_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libufvc.so")
+
+FP32, BF16, BF16_FP8 = 0, 1, 2
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "bf16_fp8": BF16_FP8}
+STATUS = {0: "OK", -1: "INVAL", -2: "NOSPC", -3: "CORRUPT", -4: "DEVICE", -5: "NOMEM",
+          -6: "UNSUPPORTED"}
+BUF_Y, BUF_ZSYM, BUF_PARAMS, BUF_IDX, BUF_SYM = range(5)
+Z_CHANNELS = 32
+
+
+class UfvcError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+        self.code = code
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int), ("C", ctypes.c_int), ("precision", ctypes.c_int),
+                ("seg_log2", ctypes.c_int), ("seg_log2_z", ctypes.c_int),
+                ("model_tag", ctypes.c_uint32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with python -m paper_2606_04410_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, S, I, U = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_uint32
+    sigs = {
+        "ufvc_weight_count": (S, [I, I]),
+        "ufvc_create": (I, [ctypes.POINTER(_Config), P, S, ctypes.POINTER(P)]),
+        "ufvc_destroy": (None, [P]),
+        "ufvc_max_bitstream_bytes": (S, [P, I, I]),
+        "ufvc_encode_chunk": (I, [P, P, I, I, I, P, S, ctypes.POINTER(S), P]),
+        "ufvc_decode_chunk": (I, [P, P, S, I, I, I, P, P]),
+        "ufvc_sync_status": (I, [P, P]),
+        "ufvc_get_tables": (I, [P, P, P, P]),
+        "ufvc_rans_encode": (I, [P, P, P, S, I, P, S, ctypes.POINTER(S), P]),
+        "ufvc_rans_decode": (I, [P, P, S, P, S, I, P, P]),
+        "ufvc_synthesize": (I, [P, P, I, I, I, P, P]),
+        "ufvc_copy_buffer": (I, [P, I, P, S]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    del U
+    return lib
+
+
+lib = _load()
+
+# Names of the exported entry points (what include/ufvc.h declares).
+EXPORTS = ("ufvc_weight_count", "ufvc_create", "ufvc_destroy", "ufvc_max_bitstream_bytes",
+           "ufvc_encode_chunk", "ufvc_decode_chunk", "ufvc_sync_status", "ufvc_get_tables",
+           "ufvc_rans_encode", "ufvc_rans_decode", "ufvc_synthesize", "ufvc_copy_buffer")
+
+
+def layer_order(T: int) -> list[str]:
+    """Layer names in the order ufvc_create expects them."""
+    names = ["a1", "a2", "a3", "h", "p", "d1", "d2", "d3"]
+    for t in range(T):
+        names += [f"k1_{t}", f"k2_{t}", f"k3_{t}"]
+    return names
+
+
+def flatten_weights(weights: dict, T: int) -> np.ndarray:
+    return np.ascontiguousarray(
+        np.concatenate([np.asarray(weights[n], np.float32).reshape(-1) for n in layer_order(T)]))
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise UfvcError(code, what)
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Codec:
+    """One codec context (one model: fixed T and C) on the current device."""
+
+    def __init__(self, T: int, C: int, weights: dict, precision: str = "bf16",
+                 seg_log2: int = 15, seg_log2_z: int = 11, model_tag: int = 0):
+        self.T, self.C = T, C
+        self.precision = precision
+        self.seg_log2, self.seg_log2_z, self.model_tag = seg_log2, seg_log2_z, model_tag
+        flat = flatten_weights(weights, T)
+        cfg = _Config(T, C, PRECISIONS[precision], seg_log2, seg_log2_z, model_tag & 0xFFFFFFFF)
+        h = ctypes.c_void_p()
+        _check(lib.ufvc_create(ctypes.byref(cfg), flat.ctypes.data, flat.size, ctypes.byref(h)),
+               "ufvc_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.ufvc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- sizes
+    def latent_size(self, H: int, W: int):
+        Hp, Wp = -(-H // 16) * 16, -(-W // 16) * 16
+        h, w = Hp // 8, Wp // 8
+        return h, w, -(-h // 2), -(-w // 2)
+
+    def max_bitstream_bytes(self, H: int, W: int) -> int:
+        return int(lib.ufvc_max_bitstream_bytes(self._h, H, W))
+
+    # ----------------------------------------------------------- coding API
+    def encode(self, frames, out=None, stream=None):
+        """frames: cuda float32 (T, 3, H, W).  Returns (uint8 cuda buffer, nbytes)."""
+        import torch
+        T, _, H, W = frames.shape
+        assert frames.is_cuda and frames.dtype == torch.float32 and frames.is_contiguous()
+        if out is None:
+            out = torch.empty(self.max_bitstream_bytes(H, W), dtype=torch.uint8, device=frames.device)
+        n = ctypes.c_size_t(0)
+        code = lib.ufvc_encode_chunk(self._h, _ptr(frames), T, H, W, _ptr(out), out.numel(),
+                                     ctypes.byref(n), _stream(stream))
+        _check(code, "ufvc_encode_chunk")
+        return out, n.value
+
+    def decode(self, bitstream, nbytes: int, H: int, W: int, out=None, stream=None, check=True):
+        """bitstream: cuda uint8.  Returns cuda float32 (T, 3, H, W)."""
+        import torch
+        if out is None:
+            out = torch.empty((self.T, 3, H, W), dtype=torch.float32, device=bitstream.device)
+        _check(lib.ufvc_decode_chunk(self._h, _ptr(bitstream), nbytes, self.T, H, W, _ptr(out),
+                                     _stream(stream)), "ufvc_decode_chunk")
+        if check:
+            self.sync_status(stream)
+        return out
+
+    def sync_status(self, stream=None):
+        _check(lib.ufvc_sync_status(self._h, _stream(stream)), "decode status")
+
+    def status(self, stream=None) -> int:
+        return int(lib.ufvc_sync_status(self._h, _stream(stream)))
+
+    def synthesize(self, y_hat_hwc, H: int, W: int, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.T, 3, H, W), dtype=torch.float32, device=y_hat_hwc.device)
+        _check(lib.ufvc_synthesize(self._h, _ptr(y_hat_hwc), self.T, H, W, _ptr(out),
+                                   _stream(stream)), "ufvc_synthesize")
+        return out
+
+    # ------------------------------------------------------- stage access
+    def tables(self):
+        freq = np.zeros((64, 65), np.uint16)
+        cum = np.zeros((64, 65), np.uint16)
+        thr = np.zeros(63, np.float32)
+        _check(lib.ufvc_get_tables(self._h, freq.ctypes.data, cum.ctypes.data, thr.ctypes.data),
+               "ufvc_get_tables")
+        return freq, cum, thr
+
+    def rans_encode(self, sym, idx, seg_log2: int, stream=None):
+        """sym, idx: cuda uint8 (n,).  Returns bytes: u32 seg_bytes[n_seg] + segments."""
+        import torch
+        n = sym.numel()
+        nseg = -(-n // (1 << seg_log2))
+        cap = 4 * nseg + nseg * 132 + 2 * n + 16
+        out = torch.empty(cap, dtype=torch.uint8, device=sym.device)
+        ln = ctypes.c_size_t(0)
+        _check(lib.ufvc_rans_encode(self._h, _ptr(sym), _ptr(idx), n, seg_log2, _ptr(out), cap,
+                                    ctypes.byref(ln), _stream(stream)), "ufvc_rans_encode")
+        return out[:ln.value]
+
+    def rans_decode(self, data, idx, seg_log2: int, stream=None):
+        import torch
+        n = idx.numel()
+        sym = torch.empty(n, dtype=torch.uint8, device=idx.device)
+        _check(lib.ufvc_rans_decode(self._h, _ptr(data), data.numel(), _ptr(idx), n, seg_log2,
+                                    _ptr(sym), _stream(stream)), "ufvc_rans_decode")
+        return sym
+
+    def buffer(self, which: int, H: int, W: int) -> np.ndarray:
+        h, w, hz, wz = self.latent_size(H, W)
+        C = self.C
+        shape, dt = {BUF_Y: ((h, w, C), np.float32), BUF_ZSYM: ((hz, wz, Z_CHANNELS), np.uint8),
+                     BUF_PARAMS: ((h, w, 2 * C), np.float32), BUF_IDX: ((h, w, C), np.uint8),
+                     BUF_SYM: ((h, w, C), np.uint8)}[which]
+        a = np.zeros(shape, dt)
+        _check(lib.ufvc_copy_buffer(self._h, which, a.ctypes.data, a.nbytes), "ufvc_copy_buffer")
+        return a

@@ -1,0 +1,536 @@
+// C ABI of libufvc: context, weight repacking, workspaces, and the encode /
+// decode pipelines of one chunk (see include/ufvc.h for the contract).
+#include "../../include/ufvc.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ufvc_common.h"
+
+using namespace ufvc;
+
+namespace {
+
+constexpr int ZC = 32;   // hyper-latent channels
+constexpr int K_Z = 22;  // table row of every z symbol (sigma ~ 1)
+
+struct Layer {
+  void* w = nullptr;   // packed [group][slice][tap][cout][32 bytes]
+  long gstride = 0;    // bytes per group
+  int cin = 0, cout = 0, groups = 0, prec = 0;
+};
+
+struct Workspace {
+  int h = 0, w = 0;               // latent size the buffers are sized for
+  void* act0 = nullptr;           // [h][w][C], compute type
+  void* act1 = nullptr;
+  float* y = nullptr;             // [h][w][C]
+  uint8_t* zsym = nullptr;        // [hz][wz][32]
+  float* P = nullptr;             // [h][w][2C]
+  uint8_t* idx = nullptr;         // [h][w][C]
+  uint8_t* sym = nullptr;         // [h][w][C]
+  void* big0 = nullptr;           // [h][w][T C]
+  void* big1 = nullptr;
+};
+
+struct RansWs {
+  size_t scratch_bytes = 0;
+  uint8_t* scratch = nullptr;
+  int nseg_cap = 0;
+  SegInfo* info = nullptr;
+  uint32_t* seg_off = nullptr;
+  uint32_t* seg_len = nullptr;
+};
+
+}  // namespace
+
+struct ufvc_ctx {
+  ufvc_config cfg{};
+  int device = 0;
+  Tables tab{};
+  Layer a1, a2, a3, h, p, d1, d2, d3, k1, k2, k3;
+  Workspace ws;
+  RansWs rw;
+  unsigned long long* result = nullptr;      // device
+  unsigned long long* result_host = nullptr; // pinned
+  uint32_t* status = nullptr;                // device
+  uint32_t* status_host = nullptr;           // pinned
+  hipStream_t last_stream = nullptr;
+  int last_h = 0, last_w = 0;
+};
+
+#define CK(x)                                   \
+  do {                                          \
+    if ((x) != hipSuccess) return UFVC_E_DEVICE; \
+  } while (0)
+
+static int act_elem_size(int prec) { return prec == UFVC_FP32 ? 4 : 2; }
+static int conv_prec(int prec) { return prec == UFVC_FP32 ? P_F32 : P_BF16; }
+
+static size_t weight_count_tc(int T, int C) {
+  const size_t k9 = 9;
+  size_t n = (size_t)C * 192 * T * k9 + 2 * (size_t)C * C * k9 + (size_t)ZC * C * k9 +
+             (size_t)2 * C * ZC * k9 + 3 * (size_t)C * C * k9;
+  n += (size_t)T * ((size_t)C * C * k9 * 2 + (size_t)192 * C * k9);
+  return n;
+}
+
+// Repacks OIHW float32 weights of `groups` groups into the conv kernels'
+// layout: [g][slice][tap][cout][32 bytes], a slice holding 16 bf16 or 8 f32
+// consecutive input channels.
+static int upload_layer(Layer& L, const std::vector<const float*>& src, int cout, int cin,
+                        int prec_conv) {
+  const int E = prec_conv == P_BF16 ? 16 : 8;
+  const int esz = prec_conv == P_BF16 ? 2 : 4;
+  if (cin % E) return UFVC_E_UNSUPPORTED;
+  const int groups = (int)src.size();
+  const int nsl = cin / E;
+  const size_t gbytes = (size_t)nsl * 9 * cout * 32;
+  std::vector<uint8_t> buf(gbytes * groups);
+  for (int g = 0; g < groups; ++g) {
+    const float* W = src[g];
+    for (int s = 0; s < nsl; ++s)
+      for (int tap = 0; tap < 9; ++tap)
+        for (int n = 0; n < cout; ++n)
+          for (int e = 0; e < E; ++e) {
+            const int ci = s * E + e;
+            const float v = W[((size_t)n * cin + ci) * 9 + tap];
+            uint8_t* d = buf.data() + g * gbytes + ((((size_t)s * 9 + tap) * cout + n) * 32 + e * esz);
+            if (esz == 4) {
+              std::memcpy(d, &v, 4);
+            } else {
+              const __bf16 b = (__bf16)v;
+              std::memcpy(d, &b, 2);
+            }
+          }
+  }
+  if (hipMalloc(&L.w, buf.size()) != hipSuccess) return UFVC_E_NOMEM;
+  CK(hipMemcpy(L.w, buf.data(), buf.size(), hipMemcpyHostToDevice));
+  L.gstride = (long)gbytes;
+  L.cin = cin;
+  L.cout = cout;
+  L.groups = groups;
+  L.prec = prec_conv;
+  return UFVC_OK;
+}
+
+static void free_ws(ufvc_ctx* c) {
+  Workspace& w = c->ws;
+  void* ptrs[] = {w.act0, w.act1, w.y, w.zsym, w.P, w.idx, w.sym, w.big0, w.big1};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  c->ws = Workspace{};
+}
+
+static int ensure_ws(ufvc_ctx* c, int h, int w) {
+  if (c->ws.act0 && c->ws.h >= h && c->ws.w >= w) return UFVC_OK;
+  (void)hipDeviceSynchronize();
+  free_ws(c);
+  const int C = c->cfg.C, T = c->cfg.T;
+  const size_t npos = (size_t)h * w;
+  const size_t hz = (h + 1) / 2, wz = (w + 1) / 2;
+  const int es = act_elem_size(c->cfg.precision);
+  Workspace& W = c->ws;
+  if (hipMalloc(&W.act0, npos * C * es) != hipSuccess) return UFVC_E_NOMEM;
+  if (hipMalloc(&W.act1, npos * C * es) != hipSuccess) return UFVC_E_NOMEM;
+  if (hipMalloc(&W.y, npos * C * 4) != hipSuccess) return UFVC_E_NOMEM;
+  if (hipMalloc(&W.zsym, hz * wz * ZC + 16) != hipSuccess) return UFVC_E_NOMEM;
+  if (hipMalloc(&W.P, npos * 2 * C * 4) != hipSuccess) return UFVC_E_NOMEM;
+  if (hipMalloc(&W.idx, npos * C) != hipSuccess) return UFVC_E_NOMEM;
+  if (hipMalloc(&W.sym, npos * C) != hipSuccess) return UFVC_E_NOMEM;
+  if (hipMalloc(&W.big0, npos * C * T * es) != hipSuccess) return UFVC_E_NOMEM;
+  if (hipMalloc(&W.big1, npos * C * T * es) != hipSuccess) return UFVC_E_NOMEM;
+  W.h = h;
+  W.w = w;
+  return UFVC_OK;
+}
+
+static int ensure_rans(ufvc_ctx* c, size_t scratch_bytes, int nseg) {
+  RansWs& r = c->rw;
+  if (r.scratch_bytes < scratch_bytes) {
+    (void)hipDeviceSynchronize();
+    if (r.scratch) (void)hipFree(r.scratch);
+    r.scratch = nullptr;
+    r.scratch_bytes = 0;
+    if (hipMalloc(&r.scratch, scratch_bytes) != hipSuccess) return UFVC_E_NOMEM;
+    r.scratch_bytes = scratch_bytes;
+  }
+  if (r.nseg_cap < nseg) {
+    (void)hipDeviceSynchronize();
+    if (r.info) (void)hipFree(r.info);
+    if (r.seg_off) (void)hipFree(r.seg_off);
+    if (r.seg_len) (void)hipFree(r.seg_len);
+    r.info = nullptr;
+    r.seg_off = r.seg_len = nullptr;
+    r.nseg_cap = 0;
+    if (hipMalloc(&r.info, sizeof(SegInfo) * nseg) != hipSuccess) return UFVC_E_NOMEM;
+    if (hipMalloc(&r.seg_off, 4 * (size_t)nseg) != hipSuccess) return UFVC_E_NOMEM;
+    if (hipMalloc(&r.seg_len, 4 * (size_t)nseg) != hipSuccess) return UFVC_E_NOMEM;
+    r.nseg_cap = nseg;
+  }
+  return UFVC_OK;
+}
+
+static int nseg_of(long n, int sl) { return n == 0 ? 0 : (int)((n + (1L << sl) - 1) >> sl); }
+static size_t slot_bytes(int sl) { return (size_t)SEG_STATE_BYTES + 2 * ((size_t)1 << sl); }
+
+struct Geom {
+  int Hp, Wp, h, w, hz, wz;
+  long ny, nz;
+  int nseg_y, nseg_z;
+};
+
+static bool geom(const ufvc_ctx* c, int H, int W, Geom& g) {
+  if (H < 16 || W < 16 || (H & 7) || (W & 7) || H > 65535 || W > 65535) return false;
+  g.Hp = (H + 15) / 16 * 16;
+  g.Wp = (W + 15) / 16 * 16;
+  g.h = g.Hp / 8;
+  g.w = g.Wp / 8;
+  g.hz = (g.h + 1) / 2;
+  g.wz = (g.w + 1) / 2;
+  g.ny = (long)g.h * g.w * c->cfg.C;
+  g.nz = (long)g.hz * g.wz * ZC;
+  g.nseg_y = nseg_of(g.ny, c->cfg.seg_log2);
+  g.nseg_z = nseg_of(g.nz, c->cfg.seg_log2_z);
+  return true;
+}
+
+static ConvArgs conv_args(int Hin, int Win, int Hout, int Wout, const Layer& L) {
+  ConvArgs a{};
+  a.Hin = Hin;
+  a.Win = Win;
+  a.Hout = Hout;
+  a.Wout = Wout;
+  a.cin = L.cin;
+  a.cout = L.cout;
+  a.wpk = L.w;
+  a.w_gstride = L.gstride;
+  return a;
+}
+
+// Tile configuration: the widest channel tile that divides the layer's outputs.
+static int cfg_for(int cout) { return cout % 128 == 0 ? 0 : (cout % 64 == 0 ? 4 : 1); }
+
+static hipError_t run_synthesis(ufvc_ctx* c, const Geom& g, const uint8_t* sym, const float* mu,
+                                long mu_pitch, const float* yhat, int H, int W, float* frames,
+                                hipStream_t s) {
+  const int C = c->cfg.C, T = c->cfg.T;
+  const int cp = conv_prec(c->cfg.precision);
+  const int act_st = cp == P_BF16 ? ST_BF16 : ST_F32;
+  hipError_t e;
+  // d1: loads y_hat = r_hat + mu (or a caller-provided float32 y_hat)
+  ConvArgs a = conv_args(g.h, g.w, g.h, g.w, c->d1);
+  int ld = LD_DEQUANT;
+  if (yhat) {
+    a.in = yhat;
+    a.in_pitch = C;
+    ld = cp == P_BF16 ? LD_F32 : LD_NHWC;
+  } else {
+    a.in = sym;
+    a.mu = mu;
+    a.mu_pitch = mu_pitch;
+  }
+  a.out = c->ws.act0;
+  a.out_pitch = C;
+  a.relu = 1;
+  e = launch_conv(cp, ld, act_st, 1, cfg_for(a.cout), a, 1, s);
+  if (e != hipSuccess) return e;
+  a = conv_args(g.h, g.w, g.h, g.w, c->d2);
+  a.in = c->ws.act0; a.in_pitch = C; a.out = c->ws.act1; a.out_pitch = C; a.relu = 1;
+  if ((e = launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s)) != hipSuccess) return e;
+  a = conv_args(g.h, g.w, g.h, g.w, c->d3);
+  a.in = c->ws.act1; a.in_pitch = C; a.out = c->ws.act0; a.out_pitch = C; a.relu = 1;
+  if ((e = launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s)) != hipSuccess) return e;
+  // k1 of all heads as one GEMM with T*C outputs
+  a = conv_args(g.h, g.w, g.h, g.w, c->k1);
+  a.in = c->ws.act0; a.in_pitch = C; a.out = c->ws.big0; a.out_pitch = (long)T * C; a.relu = 1;
+  if ((e = launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s)) != hipSuccess) return e;
+  // k2 per head: group t reads channels [tC, tC + C) and writes the same range
+  a = conv_args(g.h, g.w, g.h, g.w, c->k2);
+  a.in = c->ws.big0; a.in_pitch = (long)T * C; a.in_goff = C;
+  a.out = c->ws.big1; a.out_pitch = (long)T * C; a.out_goff = C; a.relu = 1;
+  if ((e = launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, T, s)) != hipSuccess) return e;
+  // k3 per head with the pixel-shuffle store into frame t
+  a = conv_args(g.h, g.w, g.h, g.w, c->k3);
+  a.in = c->ws.big1; a.in_pitch = (long)T * C; a.in_goff = C;
+  a.out = frames; a.T = T; a.H = H; a.W = W;
+  return launch_conv(cp, LD_NHWC, ST_SHUFFLE, 1, 2, a, T, s);
+}
+
+extern "C" {
+
+size_t ufvc_weight_count(int T, int C) {
+  if (T < 1 || T > 8 || (C != 64 && C != 128)) return 0;
+  return weight_count_tc(T, C);
+}
+
+int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, ufvc_ctx** out) {
+  if (!cfg || !weights || !out) return UFVC_E_INVAL;
+  *out = nullptr;
+  if (cfg->T < 1 || cfg->T > 8 || (cfg->C != 64 && cfg->C != 128)) return UFVC_E_INVAL;
+  if (cfg->seg_log2 < 5 || cfg->seg_log2 > 24 || cfg->seg_log2_z < 5 || cfg->seg_log2_z > 24)
+    return UFVC_E_INVAL;
+  if (cfg->precision != UFVC_FP32 && cfg->precision != UFVC_BF16) return UFVC_E_UNSUPPORTED;
+  if (n_weights != weight_count_tc(cfg->T, cfg->C)) return UFVC_E_INVAL;
+  ufvc_ctx* c = new (std::nothrow) ufvc_ctx();
+  if (!c) return UFVC_E_NOMEM;
+  c->cfg = *cfg;
+  (void)hipGetDevice(&c->device);
+  const int T = cfg->T, C = cfg->C;
+  const int cp = conv_prec(cfg->precision);
+  // blob offsets in the documented order
+  const float* p = weights;
+  const float* wa1 = p; p += (size_t)C * 192 * T * 9;
+  const float* wa2 = p; p += (size_t)C * C * 9;
+  const float* wa3 = p; p += (size_t)C * C * 9;
+  const float* wh = p; p += (size_t)ZC * C * 9;
+  const float* wp = p; p += (size_t)2 * C * ZC * 9;
+  const float* wd1 = p; p += (size_t)C * C * 9;
+  const float* wd2 = p; p += (size_t)C * C * 9;
+  const float* wd3 = p; p += (size_t)C * C * 9;
+  std::vector<const float*> k1s, k2s, k3s;
+  for (int t = 0; t < T; ++t) {
+    k1s.push_back(p); p += (size_t)C * C * 9;
+    k2s.push_back(p); p += (size_t)C * C * 9;
+    k3s.push_back(p); p += (size_t)192 * C * 9;
+  }
+  // k1 of all heads stacked along output channels
+  std::vector<float> k1cat((size_t)T * C * C * 9);
+  for (int t = 0; t < T; ++t)
+    std::memcpy(k1cat.data() + (size_t)t * C * C * 9, k1s[t], sizeof(float) * C * C * 9);
+  int rc = UFVC_OK;
+  if (!rc) rc = upload_layer(c->a1, {wa1}, C, 192 * T, cp);
+  if (!rc) rc = upload_layer(c->a2, {wa2}, C, C, cp);
+  if (!rc) rc = upload_layer(c->a3, {wa3}, C, C, cp);
+  if (!rc) rc = upload_layer(c->h, {wh}, ZC, C, P_F32);
+  if (!rc) rc = upload_layer(c->p, {wp}, 2 * C, ZC, P_F32);
+  if (!rc) rc = upload_layer(c->d1, {wd1}, C, C, cp);
+  if (!rc) rc = upload_layer(c->d2, {wd2}, C, C, cp);
+  if (!rc) rc = upload_layer(c->d3, {wd3}, C, C, cp);
+  if (!rc) rc = upload_layer(c->k1, {k1cat.data()}, T * C, C, cp);
+  if (!rc) rc = upload_layer(c->k2, k2s, C, C, cp);
+  if (!rc) rc = upload_layer(c->k3, k3s, 192, C, cp);
+  if (!rc) {
+    Tables& t = c->tab;
+    if (hipMalloc(&t.fc, 4 * NSCALES * NSYM) || hipMalloc(&t.magic, 4 * NSCALES * NSYM) ||
+        hipMalloc(&t.shift, NSCALES * NSYM) || hipMalloc(&t.lut, NSCALES * 256) ||
+        hipMalloc(&t.thresholds, 4 * 64) || hipMalloc(&c->result, 16) ||
+        hipMalloc(&c->status, 16) || hipHostMalloc(&c->result_host, 16) ||
+        hipHostMalloc(&c->status_host, 16))
+      rc = UFVC_E_NOMEM;
+  }
+  if (!rc && hipMemset(c->status, 0, 16) != hipSuccess) rc = UFVC_E_DEVICE;
+  if (!rc && launch_build_tables(c->tab, nullptr) != hipSuccess) rc = UFVC_E_DEVICE;
+  if (!rc && hipDeviceSynchronize() != hipSuccess) rc = UFVC_E_DEVICE;
+  if (rc) {
+    ufvc_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return UFVC_OK;
+}
+
+void ufvc_destroy(ufvc_ctx* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  Layer* ls[] = {&c->a1, &c->a2, &c->a3, &c->h, &c->p, &c->d1, &c->d2, &c->d3, &c->k1, &c->k2, &c->k3};
+  for (Layer* l : ls)
+    if (l->w) (void)hipFree(l->w);
+  free_ws(c);
+  void* dp[] = {c->tab.fc, c->tab.magic, c->tab.shift, c->tab.lut, c->tab.thresholds, c->result,
+                c->status, c->rw.scratch, c->rw.info, c->rw.seg_off, c->rw.seg_len};
+  for (void* q : dp)
+    if (q) (void)hipFree(q);
+  if (c->result_host) (void)hipHostFree(c->result_host);
+  if (c->status_host) (void)hipHostFree(c->status_host);
+  delete c;
+}
+
+size_t ufvc_max_bitstream_bytes(const ufvc_ctx* c, int H, int W) {
+  Geom g;
+  if (!c || !geom(c, H, W, g)) return 0;
+  return 28 + 4 * (size_t)(g.nseg_y + g.nseg_z) + (size_t)(g.nseg_y + g.nseg_z) * (SEG_STATE_BYTES + 4) +
+         2 * (size_t)(g.ny + g.nz);
+}
+
+int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uint8_t* bs,
+                      size_t capacity, size_t* out_len, void* stream) {
+  if (!c || !frames || !bs || !out_len) return UFVC_E_INVAL;
+  Geom g;
+  if (T != c->cfg.T || !geom(c, H, W, g)) return UFVC_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = ensure_ws(c, g.h, g.w);
+  if (rc) return rc;
+  const size_t sbz = slot_bytes(c->cfg.seg_log2_z), sby = slot_bytes(c->cfg.seg_log2);
+  rc = ensure_rans(c, sbz * g.nseg_z + sby * g.nseg_y, g.nseg_z + g.nseg_y);
+  if (rc) return rc;
+  const int C = c->cfg.C;
+  const int cp = conv_prec(c->cfg.precision);
+  const int act_st = cp == P_BF16 ? ST_BF16 : ST_F32;
+  Workspace& ws = c->ws;
+  // analysis: patchify fused into a1's loader
+  ConvArgs a = conv_args(g.h, g.w, g.h, g.w, c->a1);
+  a.in = frames; a.T = T; a.H = H; a.W = W;
+  a.out = ws.act0; a.out_pitch = C; a.relu = 1;
+  CK(launch_conv(cp, LD_UNSHUFFLE, act_st, 1, cfg_for(a.cout), a, 1, s));
+  a = conv_args(g.h, g.w, g.h, g.w, c->a2);
+  a.in = ws.act0; a.in_pitch = C; a.out = ws.act1; a.out_pitch = C; a.relu = 1;
+  CK(launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s));
+  a = conv_args(g.h, g.w, g.h, g.w, c->a3);
+  a.in = ws.act1; a.in_pitch = C; a.out = ws.y; a.out_pitch = C; a.relu = 0;
+  CK(launch_conv(cp, LD_NHWC, ST_F32, 1, cfg_for(a.cout), a, 1, s));
+  // hyper prior: stride-2 conv, z_hat = clamp(rint(z)) stored as symbols
+  a = conv_args(g.h, g.w, g.hz, g.wz, c->h);
+  a.in = ws.y; a.in_pitch = C; a.out = ws.zsym; a.out_pitch = ZC;
+  CK(launch_conv(P_F32, LD_NHWC, ST_ZSYM, 2, 1, a, 1, s));
+  // entropy parameters in one pass from up2(z_hat)
+  a = conv_args(g.h, g.w, g.h, g.w, c->p);
+  a.in = ws.zsym; a.out = ws.P; a.out_pitch = 2 * C;
+  CK(launch_conv(P_F32, LD_UP2, ST_F32, 1, cfg_for(a.cout), a, 1, s));
+  CK(launch_params_epilogue(ws.P, ws.y, c->tab.thresholds, ws.idx, ws.sym, (long)g.h * g.w, C, s));
+  // rANS: z with the fixed row, y with per-element rows
+  EncStream ez{ws.zsym, nullptr, K_Z, g.nz, c->cfg.seg_log2_z, g.nseg_z};
+  EncStream ey{ws.sym, ws.idx, 0, g.ny, c->cfg.seg_log2, g.nseg_y};
+  CK(launch_rans_encode(c->tab, ez, ey, c->rw.scratch, sbz, sby, c->rw.info, s));
+  HeaderFields hf{(uint16_t)T, (uint16_t)C, (uint16_t)H, (uint16_t)W, (uint8_t)c->cfg.seg_log2,
+                  (uint8_t)c->cfg.seg_log2_z, (uint8_t)K_Z, c->cfg.model_tag};
+  CK(launch_compact(c->rw.scratch, sbz, sby, c->rw.info, g.nseg_z, g.nseg_y, 1, hf, bs, capacity,
+                    c->result, s));
+  CK(hipMemcpyAsync(c->result_host, c->result, 8, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  c->last_stream = s;
+  c->last_h = g.h;
+  c->last_w = g.w;
+  *out_len = (size_t)c->result_host[0];
+  return *out_len > capacity ? UFVC_E_NOSPC : UFVC_OK;
+}
+
+int ufvc_decode_chunk(ufvc_ctx* c, const uint8_t* bs, size_t len, int T, int H, int W,
+                      float* frames, void* stream) {
+  if (!c || !bs || !frames) return UFVC_E_INVAL;
+  Geom g;
+  if (T != c->cfg.T || !geom(c, H, W, g)) return UFVC_E_INVAL;
+  if (len > 0xFFFFFFF0ull) return UFVC_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = ensure_ws(c, g.h, g.w);
+  if (rc) return rc;
+  rc = ensure_rans(c, 0, g.nseg_z + g.nseg_y);
+  if (rc) return rc;
+  const int C = c->cfg.C;
+  Workspace& ws = c->ws;
+  HeaderFields ex{(uint16_t)T, (uint16_t)C, (uint16_t)H, (uint16_t)W, (uint8_t)c->cfg.seg_log2,
+                  (uint8_t)c->cfg.seg_log2_z, (uint8_t)K_Z, c->cfg.model_tag};
+  CK(launch_parse(bs, len, 1, ex, g.nseg_z, g.nseg_y, c->rw.seg_off, c->rw.seg_len, c->status, s));
+  DecStream dz{nullptr, K_Z, g.nz, c->cfg.seg_log2_z, g.nseg_z, 0, ws.zsym};
+  CK(launch_rans_decode(c->tab, bs, c->rw.seg_off, c->rw.seg_len, dz, c->status, s));
+  ConvArgs a = conv_args(g.h, g.w, g.h, g.w, c->p);
+  a.in = ws.zsym; a.out = ws.P; a.out_pitch = 2 * C;
+  CK(launch_conv(P_F32, LD_UP2, ST_F32, 1, cfg_for(a.cout), a, 1, s));
+  CK(launch_params_epilogue(ws.P, nullptr, c->tab.thresholds, ws.idx, nullptr, (long)g.h * g.w, C, s));
+  // all of r_hat in one launch: its tables depend on sigma only
+  DecStream dy{ws.idx, 0, g.ny, c->cfg.seg_log2, g.nseg_y, g.nseg_z, ws.sym};
+  CK(launch_rans_decode(c->tab, bs, c->rw.seg_off, c->rw.seg_len, dy, c->status, s));
+  CK(run_synthesis(c, g, ws.sym, ws.P, 2 * C, nullptr, H, W, frames, s));
+  c->last_stream = s;
+  c->last_h = g.h;
+  c->last_w = g.w;
+  return UFVC_OK;
+}
+
+int ufvc_sync_status(ufvc_ctx* c, void* stream) {
+  if (!c) return UFVC_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  CK(hipMemcpyAsync(c->status_host, c->status, 4, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  const uint32_t st = c->status_host[0];
+  CK(hipMemsetAsync(c->status, 0, 4, s));
+  CK(hipStreamSynchronize(s));
+  if (st & ST_BAD_HEADER) return UFVC_E_INVAL;
+  if (st & ST_CORRUPT) return UFVC_E_CORRUPT;
+  return UFVC_OK;
+}
+
+int ufvc_get_tables(ufvc_ctx* c, uint16_t* freq, uint16_t* cum, float* thr) {
+  if (!c || !freq || !cum || !thr) return UFVC_E_INVAL;
+  std::vector<uint32_t> fc(NSCALES * NSYM);
+  CK(hipDeviceSynchronize());
+  CK(hipMemcpy(fc.data(), c->tab.fc, 4 * fc.size(), hipMemcpyDeviceToHost));
+  CK(hipMemcpy(thr, c->tab.thresholds, 4 * 63, hipMemcpyDeviceToHost));
+  for (int i = 0; i < NSCALES * NSYM; ++i) {
+    freq[i] = (uint16_t)(fc[i] & 0xFFFF);
+    cum[i] = (uint16_t)(fc[i] >> 16);
+  }
+  return UFVC_OK;
+}
+
+int ufvc_rans_encode(ufvc_ctx* c, const uint8_t* sym, const uint8_t* idx, size_t n, int sl,
+                     uint8_t* out, size_t capacity, size_t* out_len, void* stream) {
+  if (!c || !sym || !idx || !out || !out_len || sl < 5 || sl > 24) return UFVC_E_INVAL;
+  if (n > ((size_t)1 << 32)) return UFVC_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int nseg = nseg_of((long)n, sl);
+  int rc = ensure_rans(c, slot_bytes(sl) * (nseg > 0 ? nseg : 1), nseg > 0 ? nseg : 1);
+  if (rc) return rc;
+  EncStream ez{nullptr, nullptr, 0, 0, 5, 0};
+  EncStream ey{sym, idx, 0, (long)n, sl, nseg};
+  CK(launch_rans_encode(c->tab, ez, ey, c->rw.scratch, 0, slot_bytes(sl), c->rw.info, s));
+  HeaderFields hf{};
+  CK(launch_compact(c->rw.scratch, 0, slot_bytes(sl), c->rw.info, 0, nseg, 0, hf, out, capacity,
+                    c->result, s));
+  CK(hipMemcpyAsync(c->result_host, c->result, 8, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  *out_len = (size_t)c->result_host[0];
+  return *out_len > capacity ? UFVC_E_NOSPC : UFVC_OK;
+}
+
+int ufvc_rans_decode(ufvc_ctx* c, const uint8_t* in, size_t len, const uint8_t* idx, size_t n,
+                     int sl, uint8_t* sym, void* stream) {
+  if (!c || !in || !idx || !sym || sl < 5 || sl > 24 || len > 0xFFFFFFF0ull) return UFVC_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int nseg = nseg_of((long)n, sl);
+  int rc = ensure_rans(c, 0, nseg > 0 ? nseg : 1);
+  if (rc) return rc;
+  HeaderFields ex{};
+  CK(launch_parse(in, len, 0, ex, 0, nseg, c->rw.seg_off, c->rw.seg_len, c->status, s));
+  DecStream d{idx, 0, (long)n, sl, nseg, 0, sym};
+  CK(launch_rans_decode(c->tab, in, c->rw.seg_off, c->rw.seg_len, d, c->status, s));
+  c->last_stream = s;
+  return UFVC_OK;
+}
+
+int ufvc_synthesize(ufvc_ctx* c, const float* y_hat, int T, int H, int W, float* frames, void* stream) {
+  if (!c || !y_hat || !frames) return UFVC_E_INVAL;
+  Geom g;
+  if (T != c->cfg.T || !geom(c, H, W, g)) return UFVC_E_INVAL;
+  int rc = ensure_ws(c, g.h, g.w);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  CK(run_synthesis(c, g, nullptr, nullptr, 0, y_hat, H, W, frames, s));
+  c->last_stream = s;
+  return UFVC_OK;
+}
+
+int ufvc_copy_buffer(ufvc_ctx* c, int which, void* dst, size_t bytes) {
+  if (!c || !dst || !c->ws.act0) return UFVC_E_INVAL;
+  const size_t npos = (size_t)c->last_h * c->last_w;
+  const size_t nz = (size_t)((c->last_h + 1) / 2) * ((c->last_w + 1) / 2) * ZC;
+  const int C = c->cfg.C;
+  const void* src = nullptr;
+  size_t need = 0;
+  switch (which) {
+    case UFVC_BUF_Y: src = c->ws.y; need = npos * C * 4; break;
+    case UFVC_BUF_ZSYM: src = c->ws.zsym; need = nz; break;
+    case UFVC_BUF_PARAMS: src = c->ws.P; need = npos * 2 * C * 4; break;
+    case UFVC_BUF_IDX: src = c->ws.idx; need = npos * C; break;
+    case UFVC_BUF_SYM: src = c->ws.sym; need = npos * C; break;
+    default: return UFVC_E_INVAL;
+  }
+  if (bytes != need) return UFVC_E_INVAL;
+  CK(hipStreamSynchronize(c->last_stream));
+  CK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+  return UFVC_OK;
+}
+
+}  // extern "C"

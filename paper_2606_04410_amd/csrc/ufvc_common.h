@@ -1,0 +1,132 @@
+// Internal declarations shared by the HIP translation units of libufvc.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ufvc {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------- conv ----
+enum Prec { P_F32 = 0, P_BF16 = 1 };
+enum Loader {
+  LD_NHWC = 0,       // activation tensor, channels innermost, compute type
+  LD_UNSHUFFLE = 1,  // float32 frames [T][3][H][W], pixel-unshuffle x8 + replicate pad
+  LD_DEQUANT = 2,    // y_hat = (sym - 32) + mu from uint8 symbols and float32 mu
+  LD_UP2 = 3,        // nearest x2 upsampling of uint8 z symbols (value sym - 32)
+  LD_F32 = 4         // float32 tensor, channels innermost, feeding a bf16 conv
+};
+enum Store {
+  ST_BF16 = 0,     // bf16 [pos][pitch], optional ReLU
+  ST_F32 = 1,      // float32 [pos][pitch], optional ReLU
+  ST_ZSYM = 2,     // z_hat = clamp(rint(z), -32, 32) stored as uint8 z_hat + 32
+  ST_SHUFFLE = 3   // pixel-shuffle x8 into frame `group`, crop, clamp to [0, 1]
+};
+
+struct ConvArgs {
+  int Hin, Win;       // input grid (latent) size used for zero padding
+  int Hout, Wout;     // output grid size
+  int cin, cout;      // channels per group
+  // input
+  const void* in;     // activation / frames / symbols
+  long in_pitch;      // elements between positions
+  long in_goff;       // elements between groups
+  const float* mu;    // LD_DEQUANT: mean, [pos][mu_pitch]
+  long mu_pitch;
+  int T, H, W;        // frames (LD_UNSHUFFLE / ST_SHUFFLE): unpadded size
+  // weights: packed [group][slice][tap][cout][32 bytes]
+  const void* wpk;
+  long w_gstride;     // bytes per group
+  // output
+  void* out;
+  long out_pitch;
+  long out_goff;
+  int relu;
+};
+
+// Launches one conv layer.  `cfg` selects a tile configuration (see
+// conv_tile_configs); returns hipErrorInvalidValue for unsupported combos.
+hipError_t launch_conv(int prec, int loader, int store, int stride, int cfg,
+                       const ConvArgs& a, int groups, hipStream_t s);
+
+// Tile configurations: output rows x cols per workgroup and channel tile.
+struct TileCfg { int th, tw, bn; };
+int conv_num_cfgs();
+TileCfg conv_cfg(int cfg);
+
+// ------------------------------------------------------------- entropy ----
+constexpr int NSCALES = 64;
+constexpr int NSYM = 65;
+constexpr int LANES = 32;
+constexpr int SEG_STATE_BYTES = 4 * LANES;
+
+// Device tables built once per context.
+struct Tables {
+  uint32_t* fc;      // [64][65] freq | cum << 16
+  uint32_t* magic;   // [64][65] division multiplier for freq
+  uint8_t* shift;    // [64][65] ceil(log2(freq))
+  uint8_t* lut;      // [64][256] first symbol whose range reaches slot >> 8
+  float* thresholds; // [64] (63 used, [63] = +inf)
+};
+
+hipError_t launch_build_tables(const Tables& t, hipStream_t s);
+
+// Encoder epilogue of the parameter net: idx (and symbols if y != null).
+hipError_t launch_params_epilogue(const float* P, const float* y, const float* thr,
+                                  uint8_t* idx, uint8_t* sym, long npos, int C,
+                                  hipStream_t s);
+
+struct SegInfo { uint32_t start_word; uint32_t nwords; };
+
+// Encodes two symbol streams (z with a fixed row k_z, y with per-symbol rows)
+// into per-segment scratch slots.
+struct EncStream {
+  const uint8_t* sym;
+  const uint8_t* idx;   // null: every symbol uses row `fixed_row`
+  int fixed_row;
+  long n;
+  int seg_log2;
+  int n_seg;
+};
+hipError_t launch_rans_encode(const Tables& t, EncStream z, EncStream y, uint8_t* scratch,
+                              size_t slot_bytes_z, size_t slot_bytes_y, SegInfo* info,
+                              hipStream_t s);
+
+// Writes header + segment table + segments; result[0] = total bytes.  When
+// `with_header` is 0 the output is the bare table + segments.
+struct HeaderFields {
+  uint16_t T, C, H, W;
+  uint8_t seg_log2, seg_log2_z, k_z;
+  uint32_t model_tag;
+};
+hipError_t launch_compact(const uint8_t* scratch, size_t slot_bytes_z, size_t slot_bytes_y,
+                          const SegInfo* info, int n_seg_z, int n_seg_y, int with_header,
+                          HeaderFields hf, uint8_t* out, size_t capacity,
+                          unsigned long long* result, hipStream_t s);
+
+// Validates the stream (header if with_header) and computes segment byte
+// offsets into seg_off[n_seg_z + n_seg_y] (0xFFFFFFFF marks unusable).
+hipError_t launch_parse(const uint8_t* bs, size_t len, int with_header, HeaderFields expect,
+                        int n_seg_z, int n_seg_y, uint32_t* seg_off, uint32_t* seg_len,
+                        uint32_t* status, hipStream_t s);
+
+struct DecStream {
+  const uint8_t* idx;   // null: fixed row
+  int fixed_row;
+  long n;
+  int seg_log2;
+  int n_seg;
+  int seg_base;         // index of the first segment in seg_off/seg_len
+  uint8_t* sym_out;
+};
+hipError_t launch_rans_decode(const Tables& t, const uint8_t* bs, const uint32_t* seg_off,
+                              const uint32_t* seg_len, DecStream d, uint32_t* status,
+                              hipStream_t s);
+
+// Device status bits.
+constexpr uint32_t ST_BAD_HEADER = 1u;
+constexpr uint32_t ST_CORRUPT = 2u;
+
+}  // namespace ufvc

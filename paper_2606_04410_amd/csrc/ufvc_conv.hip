@@ -1,0 +1,384 @@
+// 3x3 convolution as implicit GEMM on CDNA4 matrix cores.
+//
+// GEMM view: M = output positions of a spatial tile (TH x TW), N = output
+// channels (BN per workgroup), K = 9 taps x input channels.  Activations are
+// channels-innermost, so one input position's channel run is contiguous.
+//
+// Per workgroup and per K slice of 32 bytes of input channels (16 bf16 or 8
+// f32 channels) the kernel stages into LDS
+//   * the input halo of the tile, (TH+2) x (TW+2) positions (stride 1) or
+//     (2TH+1) x (2TW+1) (stride 2), 48-byte rows (32 data + 16 pad so that
+//     16 consecutive rows hit disjoint banks), and
+//   * the packed weights of that slice for all 9 taps and BN channels,
+// then every wave runs 9 taps of 32x32 MFMA blocks (bf16 32x32x16 or four
+// f32 32x32x2) reading A (positions x channels) from the halo shifted by the
+// tap and B (channels x outputs) from the weight rows.  The next slice is
+// fetched into registers while the current one is multiplied.  Reduction
+// order is fixed: slice, then tap, then the MFMA's own order, and does not
+// depend on the tile configuration's M extent, so results do not depend on
+// how many workgroups cover the output.
+//
+// Loaders fuse the producer's layout change into the halo fetch: the x8
+// pixel-unshuffle of the patch embedding with edge-replicated padding
+// (Sec. 3.1), y_hat = r_hat + mu dequantisation (Sec. 3.4), and nearest x2
+// upsampling of the hyper latent.  Epilogues fuse ReLU, the float32 or bf16
+// store, rounding of z, and the x8 pixel-shuffle store of the frame
+// decoders with crop and clamp (Sec. 3.2).
+#include "ufvc_common.h"
+
+namespace ufvc {
+
+template <int PREC> struct PT;
+template <> struct PT<P_BF16> { static constexpr int ESZ = 2; static constexpr int E = 16; };
+template <> struct PT<P_F32> { static constexpr int ESZ = 4; static constexpr int E = 8; };
+
+union V16 {
+  uint4 u;
+  bf16x8 b;
+  float f[4];
+  __bf16 h[8];
+};
+
+__device__ __forceinline__ uint4 zero16() { return make_uint4(0, 0, 0, 0); }
+
+__device__ __forceinline__ uint4 cvt8(const float* v) {
+  V16 r;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r.h[i] = (__bf16)v[i];
+  return r.u;
+}
+
+// 16 bytes of compute-type input for channels [slice*E + ch*E/2, +E/2) at
+// input position (iy, ix); zero outside the input grid (conv zero padding).
+template <int PREC, int LD>
+__device__ __forceinline__ uint4 load_chunk(const ConvArgs& a, const unsigned char* inb,
+                                            int slice, int ch, int iy, int ix) {
+  constexpr int E = PT<PREC>::E;
+  constexpr int ESZ = PT<PREC>::ESZ;
+  if (iy < 0 || ix < 0 || iy >= a.Hin || ix >= a.Win) return zero16();
+  const long pos = (long)iy * a.Win + ix;
+  if constexpr (LD == LD_NHWC) {
+    return *reinterpret_cast<const uint4*>(inb + (pos * a.in_pitch + slice * E + ch * (E / 2)) * ESZ);
+  } else if constexpr (LD == LD_F32) {
+    // float32 tensor feeding a bf16 conv (8 channels -> 8 bf16)
+    static_assert(PREC == P_BF16, "use LD_NHWC for float32 compute");
+    const float* fp = reinterpret_cast<const float*>(inb) + pos * a.in_pitch + slice * E + ch * (E / 2);
+    const float4 u0 = *reinterpret_cast<const float4*>(fp);
+    const float4 u1 = *reinterpret_cast<const float4*>(fp + 4);
+    const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+    return cvt8(v);
+  } else if constexpr (LD == LD_UNSHUFFLE) {
+    // channel cb = t*192 + c*64 + i*8 + j  <->  pixel (8 iy + i, 8 ix + j) of plane t*3 + c
+    const int cb = slice * E + ch * (E / 2);
+    const int plane = cb >> 6;             // t*3 + c
+    const int i = (cb >> 3) & 7;
+    const int j0 = cb & 7;                 // 0 for bf16 (8 pixels), 0 or 4 for f32
+    const int py = min(8 * iy + i, a.H - 1);
+    const int px = 8 * ix + j0;
+    const float* row = reinterpret_cast<const float*>(a.in) + ((long)plane * a.H + py) * a.W;
+    if constexpr (PREC == P_BF16) {
+      float v[8];
+      if (px + 8 <= a.W) {
+        float4 u0 = *reinterpret_cast<const float4*>(row + px);
+        float4 u1 = *reinterpret_cast<const float4*>(row + px + 4);
+        v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
+        v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = row[min(px + k, a.W - 1)];
+      }
+      return cvt8(v);
+    } else {
+      V16 r;
+      if (px + 4 <= a.W) {
+        r.u = *reinterpret_cast<const uint4*>(row + px);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r.f[k] = row[min(px + k, a.W - 1)];
+      }
+      return r.u;
+    }
+  } else if constexpr (LD == LD_DEQUANT) {
+    const int c0 = slice * E + ch * (E / 2);
+    const unsigned char* sp = reinterpret_cast<const unsigned char*>(a.in) + pos * a.cin + c0;
+    const float* mp = a.mu + pos * a.mu_pitch + c0;
+    if constexpr (PREC == P_BF16) {
+      uint2 sb = *reinterpret_cast<const uint2*>(sp);
+      float4 m0 = *reinterpret_cast<const float4*>(mp);
+      float4 m1 = *reinterpret_cast<const float4*>(mp + 4);
+      float v[8];
+      v[0] = (float)((int)(sb.x & 255) - 32) + m0.x;
+      v[1] = (float)((int)((sb.x >> 8) & 255) - 32) + m0.y;
+      v[2] = (float)((int)((sb.x >> 16) & 255) - 32) + m0.z;
+      v[3] = (float)((int)(sb.x >> 24) - 32) + m0.w;
+      v[4] = (float)((int)(sb.y & 255) - 32) + m1.x;
+      v[5] = (float)((int)((sb.y >> 8) & 255) - 32) + m1.y;
+      v[6] = (float)((int)((sb.y >> 16) & 255) - 32) + m1.z;
+      v[7] = (float)((int)(sb.y >> 24) - 32) + m1.w;
+      return cvt8(v);
+    } else {
+      uint32_t sb = *reinterpret_cast<const uint32_t*>(sp);
+      float4 m = *reinterpret_cast<const float4*>(mp);
+      V16 r;
+      r.f[0] = (float)((int)(sb & 255) - 32) + m.x;
+      r.f[1] = (float)((int)((sb >> 8) & 255) - 32) + m.y;
+      r.f[2] = (float)((int)((sb >> 16) & 255) - 32) + m.z;
+      r.f[3] = (float)((int)(sb >> 24) - 32) + m.w;
+      return r.u;
+    }
+  } else {  // LD_UP2, float32 compute
+    static_assert(PREC == P_F32, "up2 loader is float32 only");
+    const int c0 = slice * E + ch * (E / 2);
+    const int wz = (a.Win + 1) >> 1;
+    const unsigned char* sp = reinterpret_cast<const unsigned char*>(a.in) +
+                              ((long)(iy >> 1) * wz + (ix >> 1)) * a.cin + c0;
+    uint32_t sb = *reinterpret_cast<const uint32_t*>(sp);
+    V16 r;
+    r.f[0] = (float)((int)(sb & 255) - 32);
+    r.f[1] = (float)((int)((sb >> 8) & 255) - 32);
+    r.f[2] = (float)((int)((sb >> 16) & 255) - 32);
+    r.f[3] = (float)((int)(sb >> 24) - 32);
+    return r.u;
+  }
+}
+
+template <int ST>
+__device__ __forceinline__ void store_out(const ConvArgs& a, int grp, int oy, int ox, int n, float v) {
+  const long pos = (long)oy * a.Wout + ox;
+  if constexpr (ST == ST_BF16) {
+    if (a.relu) v = fmaxf(v, 0.f);
+    reinterpret_cast<__bf16*>(a.out)[pos * a.out_pitch + grp * a.out_goff + n] = (__bf16)v;
+  } else if constexpr (ST == ST_F32) {
+    if (a.relu) v = fmaxf(v, 0.f);
+    reinterpret_cast<float*>(a.out)[pos * a.out_pitch + grp * a.out_goff + n] = v;
+  } else if constexpr (ST == ST_ZSYM) {
+    float z = fminf(fmaxf(rintf(v), -32.f), 32.f);
+    reinterpret_cast<unsigned char*>(a.out)[pos * a.out_pitch + n] = (unsigned char)((int)z + 32);
+  } else {  // ST_SHUFFLE: channel n = c*64 + i*8 + j -> pixel (8 oy + i, 8 ox + j)
+    const int c = n >> 6, i = (n >> 3) & 7, j = n & 7;
+    const int py = 8 * oy + i, px = 8 * ox + j;
+    if (py < a.H && px < a.W)
+      reinterpret_cast<float*>(a.out)[(((long)grp * 3 + c) * a.H + py) * a.W + px] =
+          fminf(fmaxf(v, 0.f), 1.f);
+  }
+}
+
+constexpr int LDS_ROW = 48;
+
+template <int STRIDE, int TH, int TW, int BN>
+constexpr int conv_lds_bytes() {
+  return ((STRIDE == 1 ? (TH + 2) * (TW + 2) : (2 * TH + 1) * (2 * TW + 1)) + 9 * BN) * LDS_ROW;
+}
+
+template <int PREC, int LD, int ST, int STRIDE, int TH, int TW, int WM, int WN, int FM, int FN>
+__global__ void __launch_bounds__(WM * WN * 64)
+conv3x3_kernel(ConvArgs a) {
+  constexpr int NT = WM * WN * 64;
+  constexpr int BM = TH * TW;
+  static_assert(BM == WM * FM * 32, "tile rows must match the wave grid");
+  constexpr int BN = WN * FN * 32;
+  constexpr int HH = STRIDE == 1 ? TH + 2 : 2 * TH + 1;
+  constexpr int HW = STRIDE == 1 ? TW + 2 : 2 * TW + 1;
+  constexpr int HP = HH * HW;
+  constexpr int HCH = HP * 2;
+  constexpr int WCH = 9 * BN * 2;
+  constexpr int HIT = (HCH + NT - 1) / NT;
+  constexpr int WIT = (WCH + NT - 1) / NT;
+  constexpr int E = PT<PREC>::E;
+  constexpr int ESZ = PT<PREC>::ESZ;
+
+  extern __shared__ __attribute__((aligned(16))) unsigned char sh[];
+  unsigned char* lds_h = sh;
+  unsigned char* lds_w = sh + HP * LDS_ROW;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN;
+  const int wn = wave - wm * WN;
+  const int grp = blockIdx.z;
+  const int tiles_x = (a.Wout + TW - 1) / TW;
+  const int oy0 = (blockIdx.x / tiles_x) * TH;
+  const int ox0 = (blockIdx.x % tiles_x) * TW;
+  const int n0 = blockIdx.y * BN;
+  const int iy0 = STRIDE * oy0 - 1;
+  const int ix0 = STRIDE * ox0 - 1;
+  const int nslices = a.cin / E;
+
+  const unsigned char* wbase = reinterpret_cast<const unsigned char*>(a.wpk) + grp * a.w_gstride;
+  const unsigned char* inb = reinterpret_cast<const unsigned char*>(a.in) +
+                            grp * a.in_goff * (LD == LD_F32 ? 4 : ESZ);
+
+  uint4 hreg[HIT];
+  uint4 wreg[WIT];
+
+  auto gload = [&](int s) {
+#pragma unroll
+    for (int i = 0; i < HIT; ++i) {
+      const int q = tid + i * NT;
+      if (HCH % NT == 0 || q < HCH) {
+        int pos, ch;
+        if constexpr (LD == LD_UNSHUFFLE) { ch = q / HP; pos = q - ch * HP; }
+        else { pos = q >> 1; ch = q & 1; }
+        const int hy = pos / HW, hx = pos - hy * HW;
+        hreg[i] = load_chunk<PREC, LD>(a, inb, s, ch, iy0 + hy, ix0 + hx);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < WIT; ++i) {
+      const int q = tid + i * NT;
+      if (WCH % NT == 0 || q < WCH) {
+        const int row = q >> 1, ch = q & 1;
+        const int tap = row / BN, n = row - tap * BN;
+        wreg[i] = *reinterpret_cast<const uint4*>(
+            wbase + (((long)(s * 9 + tap) * a.cout + n0 + n) * 32 + ch * 16));
+      }
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int i = 0; i < HIT; ++i) {
+      const int q = tid + i * NT;
+      if (HCH % NT == 0 || q < HCH) {
+        int pos, ch;
+        if constexpr (LD == LD_UNSHUFFLE) { ch = q / HP; pos = q - ch * HP; }
+        else { pos = q >> 1; ch = q & 1; }
+        *reinterpret_cast<uint4*>(lds_h + pos * LDS_ROW + ch * 16) = hreg[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < WIT; ++i) {
+      const int q = tid + i * NT;
+      if (WCH % NT == 0 || q < WCH)
+        *reinterpret_cast<uint4*>(lds_w + (q >> 1) * LDS_ROW + (q & 1) * 16) = wreg[i];
+    }
+  };
+
+  int arow[FM];
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm) {
+    const int M = (wm * FM + fm) * 32 + (lane & 31);
+    const int r = M / TW, c = M - (M / TW) * TW;
+    arow[fm] = STRIDE == 1 ? r * HW + c : 2 * r * HW + 2 * c;
+  }
+  const int koff = (lane >> 5) * 16;
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[fm][fn][r] = 0.f;
+
+  gload(0);
+  for (int s = 0; s < nslices; ++s) {
+    lstore();
+    __syncthreads();
+    if (s + 1 < nslices) gload(s + 1);
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int toff = (tap / 3) * HW + (tap % 3);
+      V16 av[FM], bv[FN];
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+        av[fm].u = *reinterpret_cast<const uint4*>(lds_h + (arow[fm] + toff) * LDS_ROW + koff);
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+        bv[fn].u = *reinterpret_cast<const uint4*>(
+            lds_w + (tap * BN + (wn * FN + fn) * 32 + (lane & 31)) * LDS_ROW + koff);
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+          if constexpr (PREC == P_BF16) {
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[fm].b, bv[fn].b, acc[fm][fn], 0, 0, 0);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[fm].f[e], bv[fn].f[e], acc[fm][fn], 0, 0, 0);
+          }
+        }
+    }
+    __syncthreads();
+  }
+
+  // 32x32 accumulator block: register r of lane l holds row 8(r/4) + 4(l/32) + r%4, column l%32.
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int M = (wm * FM + fm) * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int oy = oy0 + M / TW, ox = ox0 + M % TW;
+        const int n = n0 + (wn * FN + fn) * 32 + (lane & 31);
+        if (oy < a.Hout && ox < a.Wout) store_out<ST>(a, grp, oy, ox, n, acc[fm][fn][r]);
+      }
+}
+
+// ------------------------------------------------------------ dispatch ----
+// cfg: 0 = 8x16 tile, 128 channels, 2x2 waves of 64x64
+//      1 = 8x16 tile,  32 channels, 4x1 waves of 32x32 (narrow outputs)
+//      2 = 8x16 tile, 192 channels, 2x2 waves of 64x96
+//      3 = 4x16 tile, 128 channels, 2x2 waves of 32x64 (more workgroups)
+//      4 = 8x16 tile,  64 channels, 2x2 waves of 64x32
+static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32}, {8, 16, 192}, {4, 16, 128}, {8, 16, 64}};
+int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
+TileCfg conv_cfg(int c) { return kCfgs[c]; }
+
+template <int PREC, int LD, int ST, int STRIDE, int TH, int TW, int WM, int WN, int FM, int FN>
+static hipError_t run_conv(const ConvArgs& a, int groups, hipStream_t s) {
+  constexpr int BN = WN * FN * 32;
+  constexpr int lds = conv_lds_bytes<STRIDE, TH, TW, BN>();
+  auto kern = conv3x3_kernel<PREC, LD, ST, STRIDE, TH, TW, WM, WN, FM, FN>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  if (a.cout % BN || a.cin % PT<PREC>::E) return hipErrorInvalidValue;
+  const int tiles = ((a.Hout + TH - 1) / TH) * ((a.Wout + TW - 1) / TW);
+  dim3 grid(tiles, a.cout / BN, groups);
+  hipLaunchKernelGGL(kern, grid, dim3(WM * WN * 64), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int PREC, int LD, int ST, int STRIDE>
+static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, hipStream_t s) {
+  switch (cfg) {
+    case 0: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 2>(a, groups, s);
+    case 1: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 4, 1, 1, 1>(a, groups, s);
+    case 2: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 3>(a, groups, s);
+    case 3: return run_conv<PREC, LD, ST, STRIDE, 4, 16, 2, 2, 1, 2>(a, groups, s);
+    case 4: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 1>(a, groups, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_conv(int prec, int loader, int store, int stride, int cfg,
+                       const ConvArgs& a, int groups, hipStream_t s) {
+#define UFVC_CONV(P, L, S, STR)                                         \
+  if (prec == P && loader == L && store == S && stride == STR)          \
+    return run_cfg<P, L, S, STR>(cfg, a, groups, s);
+  // bf16 analysis / synthesis
+  UFVC_CONV(P_BF16, LD_UNSHUFFLE, ST_BF16, 1)
+  UFVC_CONV(P_BF16, LD_NHWC, ST_BF16, 1)
+  UFVC_CONV(P_BF16, LD_NHWC, ST_F32, 1)
+  UFVC_CONV(P_BF16, LD_DEQUANT, ST_BF16, 1)
+  UFVC_CONV(P_BF16, LD_NHWC, ST_SHUFFLE, 1)
+  UFVC_CONV(P_BF16, LD_F32, ST_BF16, 1)
+  // float32 everything, plus hyper prior and entropy parameters
+  UFVC_CONV(P_F32, LD_UNSHUFFLE, ST_F32, 1)
+  UFVC_CONV(P_F32, LD_NHWC, ST_F32, 1)
+  UFVC_CONV(P_F32, LD_DEQUANT, ST_F32, 1)
+  UFVC_CONV(P_F32, LD_NHWC, ST_SHUFFLE, 1)
+  UFVC_CONV(P_F32, LD_UP2, ST_F32, 1)
+  UFVC_CONV(P_F32, LD_NHWC, ST_ZSYM, 2)
+#undef UFVC_CONV
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ufvc

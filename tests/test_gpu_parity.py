@@ -1,0 +1,284 @@
+"""GPU parity: the HIP path against the CPU oracle on identical seeded inputs.
+
+Bars
+  * rANS, tables, container: bit-exact.
+  * Scale index and symbols: identical except at provable near-ties (the
+    oracle works in float64, the kernels in float32): a scale within 1e-4
+    (relative) of a threshold, a value within 1e-3 of a half-integer.
+  * Encoder and decoder indices on the GPU: identical, always.
+  * Float32 reconstruction on an identical y_hat: max abs <= 1e-3 on [0, 1].
+  * BF16 vs float32 reconstruction: |PSNR delta| <= 0.05 dB.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from oracle import codec as ocodec  # noqa: E402
+from oracle import container, entropy, nets, rans  # noqa: E402
+from synthetic import stand_in_weights, video_chunk  # noqa: E402
+
+FREQ, CUM = entropy.cdf_tables()
+THR = entropy.thresholds().astype(np.float64)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def pkg():
+    import paper_2606_04410_amd as p
+    return p
+
+
+_CODECS = {}
+
+
+def codec(T, C, prec, seg_log2=14, seg_log2_z=10, tag=0x55F00401):
+    key = (T, C, prec, seg_log2, seg_log2_z, tag)
+    if key not in _CODECS:
+        _CODECS[key] = pkg().Codec(T, C, stand_in_weights(T, C), precision=prec,
+                                   seg_log2=seg_log2, seg_log2_z=seg_log2_z, model_tag=tag)
+    return _CODECS[key]
+
+
+def to_hwc(a):
+    return np.ascontiguousarray(np.transpose(a, (1, 2, 0)))
+
+
+def near_half(v, tol=1e-3):
+    f = np.abs(v - np.floor(v) - 0.5)
+    return f < tol
+
+
+def near_threshold(sigma, tol=1e-4):
+    rel = np.abs(sigma[..., None] - THR) / THR
+    return (rel < tol).any(axis=-1)
+
+
+# ------------------------------------------------------------------ tables
+def test_tables_match_oracle():
+    say("tables: C1 fp32 context")
+    c = codec(4, 64, "fp32")
+    freq, cum, thr = c.tables()
+    np.testing.assert_array_equal(freq.astype(np.int64), FREQ)
+    np.testing.assert_array_equal(cum.astype(np.int64), CUM)
+    np.testing.assert_array_equal(thr, entropy.thresholds())
+
+
+# -------------------------------------------------------------------- rANS
+def _oracle_bare(sym, idx, sl):
+    segs = rans.encode(sym, idx, FREQ, CUM, 1 << sl)
+    return np.frombuffer(np.array([len(s) for s in segs], "<u4").tobytes() + b"".join(segs), np.uint8)
+
+
+@pytest.mark.parametrize("n,sl,kind", [(1, 5, "rand"), (31, 5, "rand"), (32, 5, "rand"),
+                                       (33, 5, "rand"), (1000, 8, "rand"), (70000, 12, "rand"),
+                                       (40000, 14, "gauss"), (5000, 10, "tails"),
+                                       (5000, 10, "centre"), (9000, 9, "uniform")])
+def test_rans_bit_exact_and_round_trip(n, sl, kind):
+    say(f"rans n={n} seg_log2={sl} kind={kind}")
+    rng = np.random.default_rng(n + sl)
+    if kind == "tails":
+        idx = np.zeros(n, np.uint8)
+        sym = rng.choice([0, 64], n).astype(np.uint8)
+    elif kind == "centre":
+        idx = np.zeros(n, np.uint8)
+        sym = np.full(n, 32, np.uint8)
+    elif kind == "uniform":
+        idx = np.full(n, 63, np.uint8)
+        sym = rng.integers(0, 65, n).astype(np.uint8)
+    elif kind == "gauss":
+        idx = rng.integers(0, 64, n).astype(np.uint8)
+        s = entropy.scales()[idx]
+        sym = (np.clip(np.rint(rng.standard_normal(n) * s), -32, 32) + 32).astype(np.uint8)
+    else:
+        idx = rng.integers(0, 64, n).astype(np.uint8)
+        sym = rng.integers(0, 65, n).astype(np.uint8)
+    c = codec(4, 64, "fp32")
+    dsym = torch.from_numpy(sym).cuda()
+    didx = torch.from_numpy(idx).cuda()
+    out = c.rans_encode(dsym, didx, sl)
+    want = _oracle_bare(sym, idx, sl)
+    got = out.cpu().numpy()
+    assert got.size == want.size
+    np.testing.assert_array_equal(got, want)
+    back = c.rans_decode(out, didx, sl)
+    assert c.status() == 0
+    np.testing.assert_array_equal(back.cpu().numpy(), sym)
+    # oracle bytes decode on the GPU
+    back2 = c.rans_decode(torch.from_numpy(want.copy()).cuda(), didx, sl)
+    assert c.status() == 0
+    np.testing.assert_array_equal(back2.cpu().numpy(), sym)
+
+
+def test_rans_rejects_corruption():
+    say("rans corruption")
+    rng = np.random.default_rng(9)
+    n, sl = 20000, 12
+    idx = rng.integers(0, 64, n).astype(np.uint8)
+    sym = (np.clip(np.rint(rng.standard_normal(n) * 3), -32, 32) + 32).astype(np.uint8)
+    c = codec(4, 64, "fp32")
+    didx = torch.from_numpy(idx).cuda()
+    good = _oracle_bare(sym, idx, sl)
+    trunc = torch.from_numpy(good[:-4].copy()).cuda()
+    c.rans_decode(trunc, didx, sl)
+    assert c.status() == -3
+    for pos in (0, 21, 500, 3000, good.size - 9):
+        bad = good.copy()
+        bad[pos] ^= 0x5A
+        c.rans_decode(torch.from_numpy(bad).cuda(), didx, sl)
+        assert c.status() == -3, pos
+    c.rans_decode(torch.from_numpy(good.copy()).cuda(), didx, sl)
+    assert c.status() == 0
+
+
+# ------------------------------------------------------------- end to end
+def _check_stages(c, fr, w, H, W, y_tol):
+    """Compare GPU encoder stages with the oracle, isolating each stage."""
+    T = fr.shape[0]
+    C = c.C
+    h, ww, hz, wz = c.latent_size(H, W)
+    g_y = c.buffer(pkg().BUF_Y, H, W)
+    g_z = c.buffer(pkg().BUF_ZSYM, H, W).astype(np.int64) - 32
+    g_idx = c.buffer(pkg().BUF_IDX, H, W)
+    g_sym = c.buffer(pkg().BUF_SYM, H, W)
+    g_P = c.buffer(pkg().BUF_PARAMS, H, W)
+    o_y = nets.analysis(fr, w)
+    err = float(np.abs(g_y - to_hwc(o_y)).max())
+    say(f"  y max abs {err:.3e} (|y| max {np.abs(o_y).max():.2f})")
+    assert err <= y_tol
+    # hyper on the GPU's y: identical except near half-integers of z
+    o_z = nets.conv(np.transpose(g_y, (2, 0, 1)).astype(np.float64), w["h"], stride=2)
+    zmis = g_z != to_hwc(nets.rint_clamp(o_z))
+    assert not (zmis & ~near_half(to_hwc(o_z))).any()
+    # params from the GPU's z_hat
+    z_hat = np.transpose(g_z, (2, 0, 1)).astype(np.float64)
+    mu, sigma = nets.params(z_hat, w, h, ww)
+    assert float(np.abs(g_P[..., :C] - to_hwc(mu)).max()) < 1e-4
+    o_idx = to_hwc(entropy.scale_index(sigma))
+    imis = g_idx != o_idx
+    say(f"  idx mismatches {int(imis.sum())} (near-threshold allowed)")
+    assert not (imis & ~near_threshold(to_hwc(sigma))).any()
+    # symbols from the GPU's y and mean
+    r = g_y.astype(np.float64) - g_P[..., :C].astype(np.float64)
+    o_sym = np.clip(np.rint(r), -32, 32) + 32
+    smis = g_sym != o_sym
+    assert not (smis & ~near_half(r)).any()
+    return g_sym, g_idx, g_z, mu
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_c1_chunk_end_to_end(prec):
+    say(f"C1 end to end {prec}")
+    T, H, W, C = 4, 64, 64, 64
+    fr = video_chunk(T, H, W, 3, seed=1)
+    w = stand_in_weights(T, C)
+    c = codec(T, C, prec)
+    dfr = torch.from_numpy(fr).cuda()
+    bs, n = c.encode(dfr)
+    g_bs = bs[:n].cpu().numpy().tobytes()
+    y_tol = 1e-3 if prec == "fp32" else 0.25
+    g_sym, g_idx, g_z, _ = _check_stages(c, fr, w, H, W, y_tol)
+    # the container is bit-exact with the oracle coding the GPU's symbols
+    zs = (g_z + 32).astype(np.uint8).reshape(-1)
+    z_segs = rans.encode(zs, np.full(zs.size, entropy.K_Z), FREQ, CUM, 1 << 10)
+    y_segs = rans.encode(g_sym.reshape(-1), g_idx.reshape(-1), FREQ, CUM, 1 << 14)
+    want = container.pack(T, C, H, W, 14, 10, entropy.K_Z, 0x55F00401, z_segs, y_segs)
+    assert g_bs == want
+    # GPU decode: indices equal the encoder's, symbols recovered exactly
+    out = c.decode(bs, n, H, W)
+    d_idx = c.buffer(pkg().BUF_IDX, H, W)
+    d_sym = c.buffer(pkg().BUF_SYM, H, W)
+    np.testing.assert_array_equal(d_idx, g_idx)
+    np.testing.assert_array_equal(d_sym, g_sym)
+    # the oracle decodes the GPU stream to the same symbols
+    _, od = ocodec.decode_latent(g_bs, w)
+    if np.array_equal(od["y_idx"], g_idx.reshape(-1)):
+        np.testing.assert_array_equal(od["y_sym"], g_sym.reshape(-1))
+    x_hat = out.cpu().numpy()
+    assert x_hat.shape == fr.shape and np.isfinite(x_hat).all()
+    assert x_hat.min() >= 0 and x_hat.max() <= 1
+    say(f"  bytes {n}, PSNR {ocodec.psnr(fr, x_hat):.3f} dB")
+
+
+def test_fp32_synthesis_matches_oracle_on_identical_latent():
+    say("synthesis fp32 vs oracle")
+    T, H, W, C = 4, 64, 64, 64
+    w = stand_in_weights(T, C)
+    c = codec(T, C, "fp32")
+    rng = np.random.default_rng(3)
+    y_hat = rng.standard_normal((C, 8, 8)) * 1.5
+    g = c.synthesize(torch.from_numpy(to_hwc(y_hat).astype(np.float32)).cuda(), H, W).cpu().numpy()
+    o = nets.synthesis(y_hat.astype(np.float32).astype(np.float64), w, T, H, W)
+    err = float(np.abs(g - o).max())
+    say(f"  max abs {err:.3e}")
+    assert err <= 1e-3
+
+
+def test_bf16_synthesis_error_is_stated():
+    say("synthesis bf16 vs oracle")
+    T, H, W, C = 4, 64, 64, 64
+    w = stand_in_weights(T, C)
+    c = codec(T, C, "bf16")
+    rng = np.random.default_rng(3)
+    y_hat = rng.standard_normal((C, 8, 8)) * 1.5
+    g = c.synthesize(torch.from_numpy(to_hwc(y_hat).astype(np.float32)).cuda(), H, W).cpu().numpy()
+    o = nets.synthesis(y_hat.astype(np.float32).astype(np.float64), w, T, H, W)
+    err = float(np.abs(g - o).max())
+    say(f"  bf16 max abs {err:.3e}, PSNR vs oracle {ocodec.psnr(o, g):.2f} dB")
+    assert err < 0.1 and ocodec.psnr(o, g) > 35
+
+
+def test_decoder_rejects_mismatch_and_corruption():
+    say("decoder header / corruption checks")
+    T, H, W, C = 4, 64, 64, 64
+    fr = torch.from_numpy(video_chunk(T, H, W, 3, seed=2)).cuda()
+    c = codec(T, C, "fp32")
+    bs, n = c.encode(fr)
+    c.decode(bs, n, H, W)
+    with pytest.raises(pkg().UfvcError) as e:
+        c.decode(bs, n, H, W + 8)          # header says another width
+    assert e.value.code == -1
+    other = codec(T, C, "fp32", tag=0x1234)
+    with pytest.raises(pkg().UfvcError) as e:
+        other.decode(bs, n, H, W)          # another model's stream
+    assert e.value.code == -1
+    with pytest.raises(pkg().UfvcError) as e:
+        c.decode(bs, n - 4, H, W)          # truncated
+    assert e.value.code == -3
+    bad = bs[:n].clone()
+    bad[n // 2] ^= 0x77
+    with pytest.raises(pkg().UfvcError) as e:
+        c.decode(bad, n, H, W)
+    assert e.value.code == -3
+    c.decode(bs, n, H, W)                  # and the good stream still decodes
+
+
+def test_encode_reports_needed_capacity():
+    T, H, W, C = 4, 64, 64, 64
+    fr = torch.from_numpy(video_chunk(T, H, W, 3, seed=1)).cuda()
+    c = codec(T, C, "fp32")
+    _, n = c.encode(fr)
+    small = torch.empty(100, dtype=torch.uint8, device="cuda")
+    with pytest.raises(pkg().UfvcError) as e:
+        c.encode(fr, out=small)
+    assert e.value.code == -2
+
+
+def test_bf16_psnr_within_005db_of_fp32_c1():
+    T, H, W, C = 4, 64, 64, 64
+    fr = video_chunk(T, H, W, 3, seed=1)
+    dfr = torch.from_numpy(fr).cuda()
+    ps = {}
+    for prec in ("fp32", "bf16"):
+        c = codec(T, C, prec)
+        bs, n = c.encode(dfr)
+        ps[prec] = ocodec.psnr(fr, c.decode(bs, n, H, W).cpu().numpy())
+    say(f"  PSNR fp32 {ps['fp32']:.4f} bf16 {ps['bf16']:.4f}")
+    assert abs(ps["fp32"] - ps["bf16"]) <= 0.05
