@@ -151,6 +151,19 @@ enum { UFVC_BUF_Y = 0, UFVC_BUF_ZSYM = 1, UFVC_BUF_PARAMS = 2, UFVC_BUF_IDX = 3,
        UFVC_BUF_SYM = 4 };
 int ufvc_copy_buffer(ufvc_ctx* ctx, int which, void* host_dst, size_t bytes);
 
+/* ---- Per-stage timing ----
+ * With profiling enabled, every kernel launch of the coding calls is
+ * bracketed by two HIP events recorded on the caller's stream (the stream
+ * the kernel runs on).  ufvc_profile_enable synchronises the device and
+ * clears earlier records.  ufvc_profile_read synchronises the device, writes
+ * per stage the summed elapsed milliseconds and the number of launches
+ * (arrays of n >= ufvc_profile_stage_count() entries), and clears the
+ * records.  Stage names are static strings owned by the library. */
+int ufvc_profile_enable(ufvc_ctx* ctx, int on);
+int ufvc_profile_stage_count(void);
+const char* ufvc_profile_stage_name(int i);
+int ufvc_profile_read(ufvc_ctx* ctx, double* total_ms, int* count, int n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,7 +4,7 @@ Argument marshalling only: every step of encode / decode runs in the HIP
 kernels of ``libufvc.so``.  PyTorch provides device memory and streams; tensors
 are passed to the C ABI as raw device pointers.  Importing this package loads
 the library and raises if it is missing (build it with
-``python -m paper_2606_04410_amd.build``).
+``python paper_2606_04410_amd/build.py``).
 """
 from __future__ import annotations
 
@@ -38,7 +38,7 @@ class _Config(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing; build it with python -m paper_2606_04410_amd.build")
+        raise ImportError(f"{LIB_PATH} is missing; build it with python paper_2606_04410_amd/build.py")
     lib = ctypes.CDLL(LIB_PATH)
     P, S, I, U = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_uint32
     sigs = {
@@ -54,6 +54,10 @@ def _load():
         "ufvc_rans_decode": (I, [P, P, S, P, S, I, P, P]),
         "ufvc_synthesize": (I, [P, P, I, I, I, P, P]),
         "ufvc_copy_buffer": (I, [P, I, P, S]),
+        "ufvc_profile_enable": (I, [P, I]),
+        "ufvc_profile_stage_count": (I, []),
+        "ufvc_profile_stage_name": (ctypes.c_char_p, [I]),
+        "ufvc_profile_read": (I, [P, P, P, I]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -68,7 +72,9 @@ lib = _load()
 # Names of the exported entry points (what include/ufvc.h declares).
 EXPORTS = ("ufvc_weight_count", "ufvc_create", "ufvc_destroy", "ufvc_max_bitstream_bytes",
            "ufvc_encode_chunk", "ufvc_decode_chunk", "ufvc_sync_status", "ufvc_get_tables",
-           "ufvc_rans_encode", "ufvc_rans_decode", "ufvc_synthesize", "ufvc_copy_buffer")
+           "ufvc_rans_encode", "ufvc_rans_decode", "ufvc_synthesize", "ufvc_copy_buffer",
+           "ufvc_profile_enable", "ufvc_profile_stage_count", "ufvc_profile_stage_name",
+           "ufvc_profile_read")
 
 
 def layer_order(T: int) -> list[str]:
@@ -201,6 +207,19 @@ class Codec:
         _check(lib.ufvc_rans_decode(self._h, _ptr(data), data.numel(), _ptr(idx), n, seg_log2,
                                     _ptr(sym), _stream(stream)), "ufvc_rans_decode")
         return sym
+
+    # ------------------------------------------------------------ timing
+    def profile(self, on: bool = True):
+        _check(lib.ufvc_profile_enable(self._h, 1 if on else 0), "ufvc_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{stage name: (total ms, launches)} since the last read / enable."""
+        n = lib.ufvc_profile_stage_count()
+        tot = np.zeros(n, np.float64)
+        cnt = np.zeros(n, np.int32)
+        _check(lib.ufvc_profile_read(self._h, tot.ctypes.data, cnt.ctypes.data, n), "ufvc_profile_read")
+        return {lib.ufvc_profile_stage_name(i).decode(): (float(tot[i]), int(cnt[i]))
+                for i in range(n) if cnt[i]}
 
     def buffer(self, which: int, H: int, W: int) -> np.ndarray:
         h, w, hz, wz = self.latent_size(H, W)

@@ -1,6 +1,8 @@
 """Builds libufvc.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_2606_04410_amd.build
+    python paper_2606_04410_amd/build.py
+
+(run as a script: importing the package needs the library this builds)
 """
 from __future__ import annotations
 

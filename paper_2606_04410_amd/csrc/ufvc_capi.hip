@@ -42,6 +42,11 @@ struct RansWs {
   SegInfo* info = nullptr;
   uint32_t* seg_off = nullptr;
   uint32_t* seg_len = nullptr;
+  // padded copies of caller-provided symbol / index arrays (the coders read
+  // 32-byte windows that may run past the end of an array)
+  size_t pad_cap = 0;
+  uint8_t* pad_a = nullptr;
+  uint8_t* pad_b = nullptr;
 };
 
 }  // namespace
@@ -59,12 +64,53 @@ struct ufvc_ctx {
   uint32_t* status_host = nullptr;           // pinned
   hipStream_t last_stream = nullptr;
   int last_h = 0, last_w = 0;
+  // per-stage timing (events recorded on the caller's stream around kernels)
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Rec { int stage; hipEvent_t e0, e1; };
+  std::vector<Rec> prof_rec;
 };
 
 #define CK(x)                                   \
   do {                                          \
     if ((x) != hipSuccess) return UFVC_E_DEVICE; \
   } while (0)
+
+enum Stage {
+  S_A1, S_A2, S_A3, S_HYPER, S_PARAMS_ENC, S_EPI_ENC, S_RANS_ENC, S_COMPACT, S_PARSE,
+  S_RANS_DEC_Z, S_PARAMS_DEC, S_EPI_DEC, S_RANS_DEC_Y, S_D1, S_D2, S_D3, S_K1, S_K2, S_K3,
+  S_COUNT
+};
+static const char* kStageNames[S_COUNT] = {
+    "a1_conv", "a2_conv", "a3_conv", "hyper_conv", "params_conv_enc", "params_epilogue_enc",
+    "rans_encode", "compact", "parse", "rans_decode_z", "params_conv_dec", "params_epilogue_dec",
+    "rans_decode_y", "d1_conv", "d2_conv", "d3_conv", "k1_conv", "k2_conv", "k3_conv"};
+
+static hipEvent_t prof_event(ufvc_ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+// Runs one kernel launch; with profiling on, brackets it with events.
+template <class F>
+static hipError_t stage(ufvc_ctx* c, int id, hipStream_t s, F&& launch) {
+  hipEvent_t e0 = nullptr;
+  if (c->prof_on && (e0 = prof_event(c)) != nullptr) (void)hipEventRecord(e0, s);
+  const hipError_t r = launch();
+  if (e0 && r == hipSuccess) {
+    hipEvent_t e1 = prof_event(c);
+    if (e1) {
+      (void)hipEventRecord(e1, s);
+      c->prof_rec.push_back({id, e0, e1});
+    }
+  }
+  return r;
+}
 
 static int act_elem_size(int prec) { return prec == UFVC_FP32 ? 4 : 2; }
 static int conv_prec(int prec) { return prec == UFVC_FP32 ? P_F32 : P_BF16; }
@@ -136,10 +182,10 @@ static int ensure_ws(ufvc_ctx* c, int h, int w) {
   if (hipMalloc(&W.act0, npos * C * es) != hipSuccess) return UFVC_E_NOMEM;
   if (hipMalloc(&W.act1, npos * C * es) != hipSuccess) return UFVC_E_NOMEM;
   if (hipMalloc(&W.y, npos * C * 4) != hipSuccess) return UFVC_E_NOMEM;
-  if (hipMalloc(&W.zsym, hz * wz * ZC + 16) != hipSuccess) return UFVC_E_NOMEM;
+  if (hipMalloc(&W.zsym, hz * wz * ZC + CODER_PAD) != hipSuccess) return UFVC_E_NOMEM;
   if (hipMalloc(&W.P, npos * 2 * C * 4) != hipSuccess) return UFVC_E_NOMEM;
-  if (hipMalloc(&W.idx, npos * C) != hipSuccess) return UFVC_E_NOMEM;
-  if (hipMalloc(&W.sym, npos * C) != hipSuccess) return UFVC_E_NOMEM;
+  if (hipMalloc(&W.idx, npos * C + CODER_PAD) != hipSuccess) return UFVC_E_NOMEM;
+  if (hipMalloc(&W.sym, npos * C + CODER_PAD) != hipSuccess) return UFVC_E_NOMEM;
   if (hipMalloc(&W.big0, npos * C * T * es) != hipSuccess) return UFVC_E_NOMEM;
   if (hipMalloc(&W.big1, npos * C * T * es) != hipSuccess) return UFVC_E_NOMEM;
   W.h = h;
@@ -170,6 +216,20 @@ static int ensure_rans(ufvc_ctx* c, size_t scratch_bytes, int nseg) {
     if (hipMalloc(&r.seg_len, 4 * (size_t)nseg) != hipSuccess) return UFVC_E_NOMEM;
     r.nseg_cap = nseg;
   }
+  return UFVC_OK;
+}
+
+static int ensure_pad(ufvc_ctx* c, size_t n) {
+  RansWs& r = c->rw;
+  if (r.pad_cap >= n + CODER_PAD) return UFVC_OK;
+  (void)hipDeviceSynchronize();
+  if (r.pad_a) (void)hipFree(r.pad_a);
+  if (r.pad_b) (void)hipFree(r.pad_b);
+  r.pad_a = r.pad_b = nullptr;
+  r.pad_cap = 0;
+  if (hipMalloc(&r.pad_a, n + CODER_PAD) != hipSuccess || hipMalloc(&r.pad_b, n + CODER_PAD) != hipSuccess)
+    return UFVC_E_NOMEM;
+  r.pad_cap = n + CODER_PAD;
   return UFVC_OK;
 }
 
@@ -235,28 +295,28 @@ static hipError_t run_synthesis(ufvc_ctx* c, const Geom& g, const uint8_t* sym, 
   a.out = c->ws.act0;
   a.out_pitch = C;
   a.relu = 1;
-  e = launch_conv(cp, ld, act_st, 1, cfg_for(a.cout), a, 1, s);
+  e = stage(c, S_D1, s, [&] { return launch_conv(cp, ld, act_st, 1, cfg_for(a.cout), a, 1, s); });
   if (e != hipSuccess) return e;
   a = conv_args(g.h, g.w, g.h, g.w, c->d2);
   a.in = c->ws.act0; a.in_pitch = C; a.out = c->ws.act1; a.out_pitch = C; a.relu = 1;
-  if ((e = launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s)) != hipSuccess) return e;
+  if ((e = stage(c, S_D2, s, [&] { return launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s); })) != hipSuccess) return e;
   a = conv_args(g.h, g.w, g.h, g.w, c->d3);
   a.in = c->ws.act1; a.in_pitch = C; a.out = c->ws.act0; a.out_pitch = C; a.relu = 1;
-  if ((e = launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s)) != hipSuccess) return e;
+  if ((e = stage(c, S_D3, s, [&] { return launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s); })) != hipSuccess) return e;
   // k1 of all heads as one GEMM with T*C outputs
   a = conv_args(g.h, g.w, g.h, g.w, c->k1);
   a.in = c->ws.act0; a.in_pitch = C; a.out = c->ws.big0; a.out_pitch = (long)T * C; a.relu = 1;
-  if ((e = launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s)) != hipSuccess) return e;
+  if ((e = stage(c, S_K1, s, [&] { return launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s); })) != hipSuccess) return e;
   // k2 per head: group t reads channels [tC, tC + C) and writes the same range
   a = conv_args(g.h, g.w, g.h, g.w, c->k2);
   a.in = c->ws.big0; a.in_pitch = (long)T * C; a.in_goff = C;
   a.out = c->ws.big1; a.out_pitch = (long)T * C; a.out_goff = C; a.relu = 1;
-  if ((e = launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, T, s)) != hipSuccess) return e;
+  if ((e = stage(c, S_K2, s, [&] { return launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, T, s); })) != hipSuccess) return e;
   // k3 per head with the pixel-shuffle store into frame t
   a = conv_args(g.h, g.w, g.h, g.w, c->k3);
   a.in = c->ws.big1; a.in_pitch = (long)T * C; a.in_goff = C;
   a.out = frames; a.T = T; a.H = H; a.W = W;
-  return launch_conv(cp, LD_NHWC, ST_SHUFFLE, 1, 2, a, T, s);
+  return stage(c, S_K3, s, [&] { return launch_conv(cp, LD_NHWC, ST_SHUFFLE, 1, 2, a, T, s); });
 }
 
 extern "C" {
@@ -315,8 +375,8 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
   if (!rc) {
     Tables& t = c->tab;
     if (hipMalloc(&t.fc, 4 * NSCALES * NSYM) || hipMalloc(&t.magic, 4 * NSCALES * NSYM) ||
-        hipMalloc(&t.shift, NSCALES * NSYM) || hipMalloc(&t.lut, NSCALES * 256) ||
-        hipMalloc(&t.thresholds, 4 * 64) || hipMalloc(&c->result, 16) ||
+        hipMalloc(&t.shift, NSCALES * NSYM) || hipMalloc(&t.lut, NSCALES * 1024) ||
+        hipMalloc(&t.thresholds, 4 * 64) || hipMalloc(&t.tail, 64) || hipMalloc(&c->result, 16) ||
         hipMalloc(&c->status, 16) || hipHostMalloc(&c->result_host, 16) ||
         hipHostMalloc(&c->status_host, 16))
       rc = UFVC_E_NOMEM;
@@ -339,10 +399,12 @@ void ufvc_destroy(ufvc_ctx* c) {
   for (Layer* l : ls)
     if (l->w) (void)hipFree(l->w);
   free_ws(c);
-  void* dp[] = {c->tab.fc, c->tab.magic, c->tab.shift, c->tab.lut, c->tab.thresholds, c->result,
+  void* dp[] = {c->tab.fc, c->tab.magic, c->tab.shift, c->tab.lut, c->tab.thresholds, c->tab.tail,
+                c->rw.pad_a, c->rw.pad_b, c->result,
                 c->status, c->rw.scratch, c->rw.info, c->rw.seg_off, c->rw.seg_len};
   for (void* q : dp)
     if (q) (void)hipFree(q);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->result_host) (void)hipHostFree(c->result_host);
   if (c->status_host) (void)hipHostFree(c->status_host);
   delete c;
@@ -374,30 +436,30 @@ int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uin
   ConvArgs a = conv_args(g.h, g.w, g.h, g.w, c->a1);
   a.in = frames; a.T = T; a.H = H; a.W = W;
   a.out = ws.act0; a.out_pitch = C; a.relu = 1;
-  CK(launch_conv(cp, LD_UNSHUFFLE, act_st, 1, cfg_for(a.cout), a, 1, s));
+  CK(stage(c, S_A1, s, [&] { return launch_conv(cp, LD_UNSHUFFLE, act_st, 1, cfg_for(a.cout), a, 1, s); }));
   a = conv_args(g.h, g.w, g.h, g.w, c->a2);
   a.in = ws.act0; a.in_pitch = C; a.out = ws.act1; a.out_pitch = C; a.relu = 1;
-  CK(launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s));
+  CK(stage(c, S_A2, s, [&] { return launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s); }));
   a = conv_args(g.h, g.w, g.h, g.w, c->a3);
   a.in = ws.act1; a.in_pitch = C; a.out = ws.y; a.out_pitch = C; a.relu = 0;
-  CK(launch_conv(cp, LD_NHWC, ST_F32, 1, cfg_for(a.cout), a, 1, s));
+  CK(stage(c, S_A3, s, [&] { return launch_conv(cp, LD_NHWC, ST_F32, 1, cfg_for(a.cout), a, 1, s); }));
   // hyper prior: stride-2 conv, z_hat = clamp(rint(z)) stored as symbols
   a = conv_args(g.h, g.w, g.hz, g.wz, c->h);
   a.in = ws.y; a.in_pitch = C; a.out = ws.zsym; a.out_pitch = ZC;
-  CK(launch_conv(P_F32, LD_NHWC, ST_ZSYM, 2, 1, a, 1, s));
+  CK(stage(c, S_HYPER, s, [&] { return launch_conv(P_F32, LD_NHWC, ST_ZSYM, 2, 1, a, 1, s); }));
   // entropy parameters in one pass from up2(z_hat)
   a = conv_args(g.h, g.w, g.h, g.w, c->p);
   a.in = ws.zsym; a.out = ws.P; a.out_pitch = 2 * C;
-  CK(launch_conv(P_F32, LD_UP2, ST_F32, 1, cfg_for(a.cout), a, 1, s));
-  CK(launch_params_epilogue(ws.P, ws.y, c->tab.thresholds, ws.idx, ws.sym, (long)g.h * g.w, C, s));
+  CK(stage(c, S_PARAMS_ENC, s, [&] { return launch_conv(P_F32, LD_UP2, ST_F32, 1, cfg_for(a.cout), a, 1, s); }));
+  CK(stage(c, S_EPI_ENC, s, [&] { return launch_params_epilogue(ws.P, ws.y, c->tab.thresholds, ws.idx, ws.sym, (long)g.h * g.w, C, s); }));
   // rANS: z with the fixed row, y with per-element rows
   EncStream ez{ws.zsym, nullptr, K_Z, g.nz, c->cfg.seg_log2_z, g.nseg_z};
   EncStream ey{ws.sym, ws.idx, 0, g.ny, c->cfg.seg_log2, g.nseg_y};
-  CK(launch_rans_encode(c->tab, ez, ey, c->rw.scratch, sbz, sby, c->rw.info, s));
+  CK(stage(c, S_RANS_ENC, s, [&] { return launch_rans_encode(c->tab, ez, ey, c->rw.scratch, sbz, sby, c->rw.info, s); }));
   HeaderFields hf{(uint16_t)T, (uint16_t)C, (uint16_t)H, (uint16_t)W, (uint8_t)c->cfg.seg_log2,
                   (uint8_t)c->cfg.seg_log2_z, (uint8_t)K_Z, c->cfg.model_tag};
-  CK(launch_compact(c->rw.scratch, sbz, sby, c->rw.info, g.nseg_z, g.nseg_y, 1, hf, bs, capacity,
-                    c->result, s));
+  CK(stage(c, S_COMPACT, s, [&] { return launch_compact(c->rw.scratch, sbz, sby, c->rw.info, g.nseg_z, g.nseg_y, 1, hf, bs, capacity,
+                    c->result, s); }));
   CK(hipMemcpyAsync(c->result_host, c->result, 8, hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
   c->last_stream = s;
@@ -412,7 +474,7 @@ int ufvc_decode_chunk(ufvc_ctx* c, const uint8_t* bs, size_t len, int T, int H, 
   if (!c || !bs || !frames) return UFVC_E_INVAL;
   Geom g;
   if (T != c->cfg.T || !geom(c, H, W, g)) return UFVC_E_INVAL;
-  if (len > 0xFFFFFFF0ull) return UFVC_E_INVAL;
+  if (len > 0xFFFFFFF0ull || len < 28) return UFVC_E_INVAL;
   hipStream_t s = (hipStream_t)stream;
   int rc = ensure_ws(c, g.h, g.w);
   if (rc) return rc;
@@ -422,16 +484,16 @@ int ufvc_decode_chunk(ufvc_ctx* c, const uint8_t* bs, size_t len, int T, int H, 
   Workspace& ws = c->ws;
   HeaderFields ex{(uint16_t)T, (uint16_t)C, (uint16_t)H, (uint16_t)W, (uint8_t)c->cfg.seg_log2,
                   (uint8_t)c->cfg.seg_log2_z, (uint8_t)K_Z, c->cfg.model_tag};
-  CK(launch_parse(bs, len, 1, ex, g.nseg_z, g.nseg_y, c->rw.seg_off, c->rw.seg_len, c->status, s));
-  DecStream dz{nullptr, K_Z, g.nz, c->cfg.seg_log2_z, g.nseg_z, 0, ws.zsym};
-  CK(launch_rans_decode(c->tab, bs, c->rw.seg_off, c->rw.seg_len, dz, c->status, s));
+  CK(stage(c, S_PARSE, s, [&] { return launch_parse(bs, len, 1, ex, g.nseg_z, g.nseg_y, c->rw.seg_off, c->rw.seg_len, c->status, s); }));
+  DecStream dz{nullptr, K_Z, g.nz, c->cfg.seg_log2_z, g.nseg_z, 0, ws.zsym, len};
+  CK(stage(c, S_RANS_DEC_Z, s, [&] { return launch_rans_decode(c->tab, bs, c->rw.seg_off, c->rw.seg_len, dz, c->status, s); }));
   ConvArgs a = conv_args(g.h, g.w, g.h, g.w, c->p);
   a.in = ws.zsym; a.out = ws.P; a.out_pitch = 2 * C;
-  CK(launch_conv(P_F32, LD_UP2, ST_F32, 1, cfg_for(a.cout), a, 1, s));
-  CK(launch_params_epilogue(ws.P, nullptr, c->tab.thresholds, ws.idx, nullptr, (long)g.h * g.w, C, s));
+  CK(stage(c, S_PARAMS_DEC, s, [&] { return launch_conv(P_F32, LD_UP2, ST_F32, 1, cfg_for(a.cout), a, 1, s); }));
+  CK(stage(c, S_EPI_DEC, s, [&] { return launch_params_epilogue(ws.P, nullptr, c->tab.thresholds, ws.idx, nullptr, (long)g.h * g.w, C, s); }));
   // all of r_hat in one launch: its tables depend on sigma only
-  DecStream dy{ws.idx, 0, g.ny, c->cfg.seg_log2, g.nseg_y, g.nseg_z, ws.sym};
-  CK(launch_rans_decode(c->tab, bs, c->rw.seg_off, c->rw.seg_len, dy, c->status, s));
+  DecStream dy{ws.idx, 0, g.ny, c->cfg.seg_log2, g.nseg_y, g.nseg_z, ws.sym, len};
+  CK(stage(c, S_RANS_DEC_Y, s, [&] { return launch_rans_decode(c->tab, bs, c->rw.seg_off, c->rw.seg_len, dy, c->status, s); }));
   CK(run_synthesis(c, g, ws.sym, ws.P, 2 * C, nullptr, H, W, frames, s));
   c->last_stream = s;
   c->last_h = g.h;
@@ -472,9 +534,14 @@ int ufvc_rans_encode(ufvc_ctx* c, const uint8_t* sym, const uint8_t* idx, size_t
   hipStream_t s = (hipStream_t)stream;
   const int nseg = nseg_of((long)n, sl);
   int rc = ensure_rans(c, slot_bytes(sl) * (nseg > 0 ? nseg : 1), nseg > 0 ? nseg : 1);
+  if (!rc) rc = ensure_pad(c, n);
   if (rc) return rc;
+  if (n) {
+    CK(hipMemcpyAsync(c->rw.pad_a, sym, n, hipMemcpyDeviceToDevice, s));
+    CK(hipMemcpyAsync(c->rw.pad_b, idx, n, hipMemcpyDeviceToDevice, s));
+  }
   EncStream ez{nullptr, nullptr, 0, 0, 5, 0};
-  EncStream ey{sym, idx, 0, (long)n, sl, nseg};
+  EncStream ey{c->rw.pad_a, c->rw.pad_b, 0, (long)n, sl, nseg};
   CK(launch_rans_encode(c->tab, ez, ey, c->rw.scratch, 0, slot_bytes(sl), c->rw.info, s));
   HeaderFields hf{};
   CK(launch_compact(c->rw.scratch, 0, slot_bytes(sl), c->rw.info, 0, nseg, 0, hf, out, capacity,
@@ -490,11 +557,14 @@ int ufvc_rans_decode(ufvc_ctx* c, const uint8_t* in, size_t len, const uint8_t* 
   if (!c || !in || !idx || !sym || sl < 5 || sl > 24 || len > 0xFFFFFFF0ull) return UFVC_E_INVAL;
   hipStream_t s = (hipStream_t)stream;
   const int nseg = nseg_of((long)n, sl);
+  if (len < 4 * (size_t)nseg + 4) return UFVC_E_INVAL;
   int rc = ensure_rans(c, 0, nseg > 0 ? nseg : 1);
+  if (!rc) rc = ensure_pad(c, n);
   if (rc) return rc;
+  if (n) CK(hipMemcpyAsync(c->rw.pad_b, idx, n, hipMemcpyDeviceToDevice, s));
   HeaderFields ex{};
   CK(launch_parse(in, len, 0, ex, 0, nseg, c->rw.seg_off, c->rw.seg_len, c->status, s));
-  DecStream d{idx, 0, (long)n, sl, nseg, 0, sym};
+  DecStream d{c->rw.pad_b, 0, (long)n, sl, nseg, 0, sym, len};
   CK(launch_rans_decode(c->tab, in, c->rw.seg_off, c->rw.seg_len, d, c->status, s));
   c->last_stream = s;
   return UFVC_OK;
@@ -509,6 +579,34 @@ int ufvc_synthesize(ufvc_ctx* c, const float* y_hat, int T, int H, int W, float*
   hipStream_t s = (hipStream_t)stream;
   CK(run_synthesis(c, g, nullptr, nullptr, 0, y_hat, H, W, frames, s));
   c->last_stream = s;
+  return UFVC_OK;
+}
+
+int ufvc_profile_enable(ufvc_ctx* c, int on) {
+  if (!c) return UFVC_E_INVAL;
+  CK(hipDeviceSynchronize());
+  c->prof_rec.clear();
+  c->ev_used = 0;
+  c->prof_on = on != 0;
+  return UFVC_OK;
+}
+
+int ufvc_profile_stage_count(void) { return S_COUNT; }
+
+const char* ufvc_profile_stage_name(int i) { return (i >= 0 && i < S_COUNT) ? kStageNames[i] : nullptr; }
+
+int ufvc_profile_read(ufvc_ctx* c, double* total_ms, int* count, int n) {
+  if (!c || !total_ms || !count || n < S_COUNT) return UFVC_E_INVAL;
+  CK(hipDeviceSynchronize());
+  for (int i = 0; i < n; ++i) { total_ms[i] = 0.0; count[i] = 0; }
+  for (const auto& r : c->prof_rec) {
+    float ms = 0.f;
+    CK(hipEventElapsedTime(&ms, r.e0, r.e1));
+    total_ms[r.stage] += ms;
+    count[r.stage] += 1;
+  }
+  c->prof_rec.clear();
+  c->ev_used = 0;
   return UFVC_OK;
 }
 

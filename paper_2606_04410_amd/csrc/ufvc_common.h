@@ -67,8 +67,9 @@ struct Tables {
   uint32_t* fc;      // [64][65] freq | cum << 16
   uint32_t* magic;   // [64][65] division multiplier for freq
   uint8_t* shift;    // [64][65] ceil(log2(freq))
-  uint8_t* lut;      // [64][256] first symbol whose range reaches slot >> 8
+  uint8_t* lut;      // [64][1024] symbol at slot 64 b, bit 7: bucket inside it
   float* thresholds; // [64] (63 used, [63] = +inf)
+  uint8_t* tail;     // [64] length of the leading run of frequency-1 symbols
 };
 
 hipError_t launch_build_tables(const Tables& t, hipStream_t s);
@@ -112,6 +113,10 @@ hipError_t launch_parse(const uint8_t* bs, size_t len, int with_header, HeaderFi
                         int n_seg_z, int n_seg_y, uint32_t* seg_off, uint32_t* seg_len,
                         uint32_t* status, hipStream_t s);
 
+// Symbol / index arrays read by the rANS coders must have CODER_PAD readable
+// bytes past their end: the coders fetch whole epochs (1024 symbols of a
+// segment) without branching.
+constexpr size_t CODER_PAD = 2048;
 struct DecStream {
   const uint8_t* idx;   // null: fixed row
   int fixed_row;
@@ -120,6 +125,7 @@ struct DecStream {
   int n_seg;
   int seg_base;         // index of the first segment in seg_off/seg_len
   uint8_t* sym_out;
+  size_t len;           // bytes of the stream (reads are clamped into it)
 };
 hipError_t launch_rans_decode(const Tables& t, const uint8_t* bs, const uint32_t* seg_off,
                               const uint32_t* seg_len, DecStream d, uint32_t* status,

@@ -5,7 +5,7 @@
 //   scale-index thresholds, the multiplier/shift pairs that turn the
 //   encoder's division by a frequency into a multiply-high (Granlund and
 //   Montgomery 1994, "Division by invariant integers using multiplication"),
-//   and a 256-bucket slot -> symbol lookup for the decoder.
+//   and a 1024-bucket slot -> symbol lookup for the decoder.
 // * params_epilogue: sigma = clamp(softplus(.), 0.11, 64) in float32 and its
 //   table index for every latent element; in the encoder also the residual
 //   symbol r_hat = round(y - mu).  The mean is never needed for coding.
@@ -13,9 +13,7 @@
 //   2014), state in [2^16, 2^32), 16-bit renormalisation.  One half-wave
 //   (32 lanes of a wave64) owns one segment, so a wave codes two segments.
 //   The lanes of a step find their word slots with a ballot + popcount
-//   prefix count; the encoder writes words backwards from the end of a
-//   per-segment slot, the decoder reads them forwards through a two-chunk
-//   register window with lane permutes.
+//   prefix count; all per-step traffic goes through LDS (see below).
 // * compact / parse: container assembly with coalesced copies, and the
 //   decoder's header validation and segment offset scan.
 #include "ufvc_common.h"
@@ -66,13 +64,26 @@ __global__ void build_tables_kernel(Tables t) {
     t.shift[k * NSYM + i] = (uint8_t)l;
     cum += fi;
   }
-  // lut[b] = last symbol whose cumulative count is <= 256 b
+  // Tails: the leading run of frequency-1 symbols (and its mirror) maps slot
+  // -> symbol in closed form, so the lookup only covers the middle slots
+  // [tail, 65536 - tail).  lut[b]: bits 0..6 the symbol containing the first
+  // middle slot of bucket [64 b, 64 b + 63]; bit 7 set when the bucket's middle
+  // part lies inside that one symbol.
+  uint32_t tail = 0;
+  while (tail < 32 && f[tail] == 1u) ++tail;
+  t.tail[k] = (uint8_t)tail;
+  const uint32_t mid_end = 65536u - tail;
   int sidx = 0;
   uint32_t c = 0;
-  for (int b = 0; b < 256; ++b) {
-    const uint32_t slot = (uint32_t)b << 8;
-    while (sidx + 1 < NSYM && c + f[sidx] <= slot) { c += f[sidx]; ++sidx; }
-    t.lut[k * 256 + b] = (uint8_t)sidx;
+  for (int b = 0; b < 1024; ++b) {
+    const uint32_t first = max((uint32_t)b << 6, tail);
+    uint32_t entry = 0;
+    if (first < mid_end) {
+      while (sidx + 1 < NSYM && c + f[sidx] <= first) { c += f[sidx]; ++sidx; }
+      const uint32_t last = min(((uint32_t)b << 6) + 64u, mid_end);
+      entry = (uint32_t)sidx | ((c + f[sidx] >= last) ? 128u : 0u);
+    }
+    t.lut[k * 1024 + b] = (uint8_t)entry;
   }
 }
 
@@ -124,94 +135,156 @@ hipError_t launch_params_epilogue(const float* P, const float* y, const float* t
 }
 
 // --------------------------------------------------------- rANS encode ----
-constexpr int PF = 16;  // steps of symbols/indices fetched ahead
+// One wave per block, one segment per half-wave.  A segment is processed in
+// epochs of EP steps, last epoch first.  The symbols and table rows of the
+// next epoch are fetched into registers while the current one is coded and
+// committed to LDS at the epoch boundary; the words a step pushes are placed
+// with a ballot + popcount prefix into an LDS staging buffer and written to
+// the segment slot with coalesced stores once per epoch.  The serial loop
+// itself only touches LDS and registers.
+constexpr int EP = 32;                 // steps per epoch
+constexpr int EPB = EP * LANES;        // symbols per epoch and segment
 
-__global__ void __launch_bounds__(256)
+struct EncSegLds {
+  uint8_t sym[2][EPB];
+  uint8_t idx[2][EPB];
+  uint16_t words[EPB];                 // at most one word per symbol
+};
+constexpr size_t ENC_TAB_BYTES = NSCALES * NSYM * 9;  // fc + magic (u32) + shift (u8)
+constexpr size_t ENC_LDS_BYTES = ((ENC_TAB_BYTES + 15) & ~(size_t)15) + 2 * sizeof(EncSegLds);
+
+// 32 bytes at p + pos.  Symbol and index arrays handed to the coders carry
+// CODER_PAD readable bytes past their end (more than one epoch), so this
+// never branches: the loads stay in flight until the values are committed to
+// LDS.  Positions past the segment's end are masked by the callers.
+__device__ __forceinline__ void load32(const uint8_t* __restrict__ p, long pos, uint4& a, uint4& b) {
+  a = *reinterpret_cast<const uint4*>(p + pos);
+  b = *reinterpret_cast<const uint4*>(p + pos + 16);
+}
+
+__global__ void __launch_bounds__(64)
 rans_encode_kernel(Tables t, EncStream z, EncStream y, uint8_t* __restrict__ scratch,
                    size_t slot_z, size_t slot_y, SegInfo* __restrict__ info) {
-  __shared__ uint32_t s_fc[NSCALES * NSYM];
-  __shared__ uint32_t s_mg[NSCALES * NSYM];
-  __shared__ uint8_t s_sh[NSCALES * NSYM];
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  uint32_t* s_fc = reinterpret_cast<uint32_t*>(lds);
+  uint32_t* s_mg = s_fc + NSCALES * NSYM;
+  uint8_t* s_sh = reinterpret_cast<uint8_t*>(s_mg + NSCALES * NSYM);
+  EncSegLds* segs = reinterpret_cast<EncSegLds*>(lds + ((ENC_TAB_BYTES + 15) & ~(size_t)15));
   for (int i = threadIdx.x; i < NSCALES * NSYM; i += blockDim.x) {
     s_fc[i] = t.fc[i];
     s_mg[i] = t.magic[i];
     s_sh[i] = t.shift[i];
   }
-  __syncthreads();
 
   const int half = threadIdx.x >> 5;
   const int lane = threadIdx.x & 31;
-  const int seg = blockIdx.x * 8 + half;
-  if (seg >= z.n_seg + y.n_seg) return;
+  const int shsel = threadIdx.x & 32;
+  const int nseg = z.n_seg + y.n_seg;
+  const int seg0 = blockIdx.x * 2;
+  const int seg = seg0 + half;
+  const bool active = seg < nseg;
+  auto seg_n = [&](int sg) -> int {
+    const bool iz = sg < z.n_seg;
+    const int si = iz ? sg : sg - z.n_seg;
+    const int sl = iz ? z.seg_log2 : y.seg_log2;
+    const long n = iz ? z.n : y.n;
+    return (int)min((long)1 << sl, n - ((long)si << sl));
+  };
+  // both halves run the larger epoch count of the pair, so barriers stay uniform
+  const int n0 = seg_n(seg0);
+  const int n1 = seg0 + 1 < nseg ? seg_n(seg0 + 1) : 0;
+  const int nep = (max(n0, n1) + EPB - 1) / EPB;
   const bool isz = seg < z.n_seg;
   const int sidx = isz ? seg : seg - z.n_seg;
   const uint8_t* __restrict__ sym = isz ? z.sym : y.sym;
   const uint8_t* __restrict__ idxp = isz ? z.idx : y.idx;
   const int fixed = isz ? z.fixed_row : y.fixed_row;
   const int sl = isz ? z.seg_log2 : y.seg_log2;
-  const long n = isz ? z.n : y.n;
-  const long base = (long)sidx << sl;
-  const int nsym = (int)min((long)1 << sl, n - base);
-  const int steps = (nsym + LANES - 1) / LANES;
+  const long base = active ? (long)sidx << sl : 0;
+  const int nsym = active ? seg_n(seg) : 0;
   uint8_t* slot = isz ? scratch + (size_t)sidx * slot_z
                       : scratch + (size_t)z.n_seg * slot_z + (size_t)sidx * slot_y;
-  uint16_t* words = reinterpret_cast<uint16_t*>(slot + SEG_STATE_BYTES);
+  uint16_t* __restrict__ words = reinterpret_cast<uint16_t*>(slot + SEG_STATE_BYTES);
+  EncSegLds& L = segs[half];
   const uint32_t cap = 1u << sl;
   uint32_t cursor = cap;
   uint32_t x = RANS_L;
-  const int shsel = threadIdx.x & 32;
 
-  uint8_t cs[PF], ci[PF], ns[PF], ni[PF];
-  auto fetch = [&](int blk, uint8_t* ds, uint8_t* di) {
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int j = (blk * PF + u) * LANES + lane;
-      const bool v = blk >= 0 && j < nsym;
-      ds[u] = v ? sym[base + j] : 0;
-      di[u] = v ? (idxp ? idxp[base + j] : (uint8_t)fixed) : 0;
+  uint4 ps0, ps1, pi0, pi1;
+  const uint32_t f4 = (uint32_t)fixed * 0x01010101u;
+  const int nep_own = (nsym + EPB - 1) / EPB;
+  auto prefetch = [&](int ep) {
+    // epochs outside this segment's own [0, nep_own) and inactive halves
+    // re-read epoch 0, which is in bounds
+    const long pos = (ep >= 0 && ep < nep_own ? (long)ep * EPB : 0) + lane * 32;
+    load32(sym + base, pos, ps0, ps1);
+    if (idxp) {
+      load32(idxp + base, pos, pi0, pi1);
+    } else {
+      pi0 = make_uint4(f4, f4, f4, f4);
+      pi1 = pi0;
     }
   };
-  const int nblk = (steps + PF - 1) / PF;
-  fetch(nblk - 1, cs, ci);
-  for (int blk = nblk - 1; blk >= 0; --blk) {
-    fetch(blk - 1, ns, ni);
-#pragma unroll
-    for (int u = PF - 1; u >= 0; --u) {
-      const int step = blk * PF + u;
-      if (step < steps) {
-        const int j = step * LANES + lane;
-        const bool valid = j < nsym;
-        const int e = (int)min((uint32_t)ci[u], 63u) * NSYM + (int)min((uint32_t)cs[u], 64u);
-        const uint32_t fc = s_fc[e];
-        const uint32_t f = fc & 0xFFFFu, c = fc >> 16;
-        const bool emit = valid && x >= (f << 16);
-        const unsigned long long bal = __ballot(emit);
-        const uint32_t m = (uint32_t)(bal >> shsel);
-        const uint32_t cnt = __popc(m);
-        const uint32_t rank = __popc(m & ((1u << lane) - 1u));
-        if (emit) {
-          words[cursor - cnt + rank] = (uint16_t)(x & 0xFFFFu);
-          x >>= 16;
-        }
-        cursor -= cnt;
-        if (valid) {
-          const uint32_t mg = s_mg[e];
-          const uint32_t l = s_sh[e];
-          const uint32_t t1 = __umulhi(mg, x);
-          const uint32_t q = (t1 + ((x - t1) >> (l > 0 ? 1u : 0u))) >> (l > 0 ? l - 1u : 0u);
-          x = (q << 16) + (x - q * f) + c;
-        }
+  auto commit = [&](int buf) {
+    if (active) {
+      *reinterpret_cast<uint4*>(&L.sym[buf][lane * 32]) = ps0;
+      *reinterpret_cast<uint4*>(&L.sym[buf][lane * 32 + 16]) = ps1;
+      *reinterpret_cast<uint4*>(&L.idx[buf][lane * 32]) = pi0;
+      *reinterpret_cast<uint4*>(&L.idx[buf][lane * 32 + 16]) = pi1;
+    }
+  };
+
+  prefetch(nep - 1);
+  for (int ep = nep - 1; ep >= 0; --ep) {
+    const int buf = ep & 1;
+    commit(buf);
+    __syncthreads();
+    prefetch(ep - 1);
+    const uint32_t cstart = cursor;
+#pragma unroll 4
+    for (int u = EP - 1; u >= 0; --u) {
+      const int j = ep * EPB + u * LANES + lane;
+      const bool valid = active && j < nsym;
+      const uint32_t sv = min((uint32_t)L.sym[buf][u * LANES + lane], 64u);
+      const uint32_t kv = min((uint32_t)L.idx[buf][u * LANES + lane], 63u);
+      const int e = (int)kv * NSYM + (int)sv;
+      const uint32_t fc = s_fc[e];
+      const uint32_t mg = s_mg[e];
+      const uint32_t l = s_sh[e];
+      const uint32_t f = fc & 0xFFFFu, c = fc >> 16;
+      const bool emit = valid && x >= (f << 16);
+      const unsigned long long bal = __ballot(emit);
+      const uint32_t m = (uint32_t)(bal >> shsel);
+      const uint32_t cnt = __popc(m);
+      const uint32_t rank = __popc(m & ((1u << lane) - 1u));
+      if (emit) {
+        // word goes to slot position cursor - cnt + rank; staged in reverse
+        L.words[cstart - 1u - (cursor - cnt + rank)] = (uint16_t)(x & 0xFFFFu);
+        x >>= 16;
+      }
+      cursor -= cnt;
+      if (valid) {
+        const uint32_t t1 = __umulhi(mg, x);
+        const uint32_t q = (t1 + ((x - t1) >> (l > 0 ? 1u : 0u))) >> (l > 0 ? l - 1u : 0u);
+        x = (q << 16) + (x - q * f) + c;
       }
     }
-#pragma unroll
-    for (int u = 0; u < PF; ++u) { cs[u] = ns[u]; ci[u] = ni[u]; }
+    __syncthreads();
+    // flush this epoch's words [cursor, cstart) with coalesced stores
+    if (active) {
+      const uint32_t nep_words = cstart - cursor;
+      for (uint32_t i = lane; i < nep_words; i += LANES)
+        words[cursor + i] = L.words[cstart - 1u - (cursor + i)];
+    }
   }
-  reinterpret_cast<uint32_t*>(slot)[lane] = x;
-  if (lane == 0) {
-    SegInfo si;
-    si.start_word = cursor;
-    si.nwords = cap - cursor;
-    info[seg] = si;
+  if (active) {
+    reinterpret_cast<uint32_t*>(slot)[lane] = x;
+    if (lane == 0) {
+      SegInfo si;
+      si.start_word = cursor;
+      si.nwords = cap - cursor;
+      info[seg] = si;
+    }
   }
 }
 
@@ -220,7 +293,14 @@ hipError_t launch_rans_encode(const Tables& t, EncStream z, EncStream y, uint8_t
                               hipStream_t s) {
   const int nseg = z.n_seg + y.n_seg;
   if (nseg == 0) return hipSuccess;
-  hipLaunchKernelGGL(rans_encode_kernel, dim3((nseg + 7) / 8), dim3(256), 0, s, t, z, y,
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rans_encode_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)ENC_LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(rans_encode_kernel, dim3((nseg + 1) / 2), dim3(64), ENC_LDS_BYTES, s, t, z, y,
                      scratch, slot_bytes_z, slot_bytes_y, info);
   return hipGetLastError();
 }
@@ -375,101 +455,181 @@ hipError_t launch_parse(const uint8_t* bs, size_t len, int with_header, HeaderFi
 }
 
 // --------------------------------------------------------- rANS decode ----
-__global__ void __launch_bounds__(256)
+// One wave per block, one segment per half-wave, epochs of EP steps.  Per
+// segment the LDS holds a ring of RING words of the stream, the table rows
+// of two epochs and the decoded symbols of one epoch.  Refill rule: at each
+// epoch start the ring must hold the worst case of the epoch (EPB words past
+// the cursor); 1024 more words are fetched in the background whenever fewer
+// than two epochs' worth are buffered.  With at most EPB words consumed per
+// epoch this keeps the invariant and never overwrites unread words
+// (buffered - consumed < 3 EPB <= RING).  The serial loop itself only
+// touches LDS and registers.
+constexpr int RING = 4096;   // words
+constexpr int LUTB = 1024;   // decoder lookup buckets per table row (slot >> 6)
+
+struct DecSegLds {
+  uint16_t ring[RING];
+  uint8_t idx[2][EPB];
+  uint8_t out[EPB];
+};
+constexpr size_t DEC_TAB_BYTES = NSCALES * NSYM * 4 + NSCALES * LUTB + NSCALES;
+constexpr size_t DEC_LDS_BYTES = DEC_TAB_BYTES + 2 * sizeof(DecSegLds);
+
+__global__ void __launch_bounds__(64)
 rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs, const uint32_t* __restrict__ seg_off,
                    const uint32_t* __restrict__ seg_len, DecStream d, uint32_t* __restrict__ status) {
-  __shared__ uint32_t s_fc[NSCALES * NSYM];
-  __shared__ uint8_t s_lut[NSCALES * 256];
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  uint32_t* s_fc = reinterpret_cast<uint32_t*>(lds);
+  uint8_t* s_lut = lds + NSCALES * NSYM * 4;
+  uint8_t* s_tail = s_lut + NSCALES * LUTB;
+  DecSegLds* segs = reinterpret_cast<DecSegLds*>(lds + DEC_TAB_BYTES);
   for (int i = threadIdx.x; i < NSCALES * NSYM; i += blockDim.x) s_fc[i] = t.fc[i];
-  for (int i = threadIdx.x; i < NSCALES * 256; i += blockDim.x) s_lut[i] = t.lut[i];
-  __syncthreads();
+  for (int i = threadIdx.x; i < NSCALES * LUTB / 16; i += blockDim.x)
+    reinterpret_cast<uint4*>(s_lut)[i] = reinterpret_cast<const uint4*>(t.lut)[i];
+  s_tail[threadIdx.x] = t.tail[threadIdx.x];
 
   const int half = threadIdx.x >> 5;
   const int lane = threadIdx.x & 31;
-  const int sidx = blockIdx.x * 8 + half;
-  if (sidx >= d.n_seg) return;
-  const long base = (long)sidx << d.seg_log2;
-  const int nsym = (int)min((long)1 << d.seg_log2, d.n - base);
-  const int steps = (nsym + LANES - 1) / LANES;
-  const uint32_t off = seg_off[d.seg_base + sidx];
-  const uint32_t slen = seg_len[d.seg_base + sidx];
-  uint8_t* __restrict__ out = d.sym_out + base;
-  if (off == 0xFFFFFFFFu) {
-    for (int j = lane; j < nsym; j += LANES) out[j] = 32;
-    return;
-  }
-  uint32_t x = reinterpret_cast<const uint32_t*>(bs + off)[lane];
-  const uint16_t* __restrict__ words = reinterpret_cast<const uint16_t*>(bs + off + SEG_STATE_BYTES);
-  const uint32_t nw = (slen - SEG_STATE_BYTES) >> 1;
-  uint32_t wbase = 0, cursor = 0;
-  uint32_t w0 = lane < nw ? words[lane] : 0u;
-  uint32_t w1 = (uint32_t)(LANES + lane) < nw ? words[LANES + lane] : 0u;
   const int shsel = threadIdx.x & 32;
+  const int seg0 = blockIdx.x * 2;
+  const int sidx = seg0 + half;
+  auto seg_n = [&](int si) -> int {
+    return (int)min((long)1 << d.seg_log2, d.n - ((long)si << d.seg_log2));
+  };
+  const int nep = (seg_n(seg0) + EPB - 1) / EPB;  // the first segment of a pair is the larger
+  const uint32_t off = sidx < d.n_seg ? seg_off[d.seg_base + sidx] : 0xFFFFFFFFu;
+  const bool usable = off != 0xFFFFFFFFu;
+  const bool active = sidx < d.n_seg;
+  const long base = active ? (long)sidx << d.seg_log2 : 0;
+  const int nsym = active ? seg_n(sidx) : 0;
+  const uint32_t slen = usable ? seg_len[d.seg_base + sidx] : (uint32_t)SEG_STATE_BYTES;
+  const uint32_t nw = (slen - SEG_STATE_BYTES) >> 1;    // words including a pad word
+  const uint32_t ndw = nw >> 1;                          // dwords of the word area
+  const uint32_t* __restrict__ wdw =
+      reinterpret_cast<const uint32_t*>(bs + (usable ? off : 0) + SEG_STATE_BYTES);
+  // last readable dword of the stream, for clamped background fetches
+  const long last_dw = ((long)(d.len & ~(size_t)3) - 4) / 4;
+  const long wdw0 = ((usable ? (long)off : 0) + SEG_STATE_BYTES) / 4;
+  uint8_t* __restrict__ out = d.sym_out + base;
+  DecSegLds& L = segs[half];
 
-  uint8_t ci[PF], ni[PF];
-  auto fetch = [&](int blk, uint8_t* di) {
+  uint32_t x = usable ? reinterpret_cast<const uint32_t*>(bs + off)[lane] : RANS_L;
+  uint32_t cursor = 0, loaded = 0;
+
+  // background word fetch: 512 dwords (1024 words) starting at `loaded`
+  uint32_t wreg[16];
+  bool wpend = false;
+  const uint32_t* __restrict__ bsdw = reinterpret_cast<const uint32_t*>(bs);
+  auto fetch_words = [&]() {
+    // unconditional loads clamped into the stream; dwords past the segment's
+    // end are never consumed by a valid stream
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int j = (blk * PF + u) * LANES + lane;
-      const bool v = j < nsym;
-      di[u] = v ? (d.idx ? d.idx[base + j] : (uint8_t)d.fixed_row) : 0;
+    for (int i = 0; i < 16; ++i) {
+      const long dw = wdw0 + (long)((loaded >> 1) + lane + 32u * i);
+      wreg[i] = bsdw[min(dw, last_dw)];
+    }
+    wpend = true;
+  };
+  auto commit_words = [&]() {
+    if (wpend) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const uint32_t w = loaded + 2u * (lane + 32u * i);
+        *reinterpret_cast<uint32_t*>(&L.ring[w & (RING - 1)]) = wreg[i];
+      }
+      loaded += 2u * 512u;
+      wpend = false;
     }
   };
-  const int nblk = (steps + PF - 1) / PF;
-  fetch(0, ci);
-  for (int blk = 0; blk < nblk; ++blk) {
-    fetch(blk + 1, ni);
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int step = blk * PF + u;
-      if (step < steps) {
-        const int j = step * LANES + lane;
-        const bool valid = j < nsym;
-        const int row = (int)min((uint32_t)ci[u], 63u);
-        const int rowb = row * NSYM;
-        const uint32_t slot = x & 0xFFFFu;
-        uint32_t sy = s_lut[row * 256 + (slot >> 8)];
-        uint32_t fc = s_fc[rowb + sy];
+  uint4 pi0, pi1;
+  const uint32_t f4 = (uint32_t)d.fixed_row * 0x01010101u;
+  const int nep_own = (nsym + EPB - 1) / EPB;
+  auto fetch_idx = [&](int ep) {
+    if (d.idx) {
+      // epochs past this segment's own count re-read epoch 0 (in bounds)
+      load32(d.idx + base, (long)(ep < nep_own ? ep : 0) * EPB + lane * 32, pi0, pi1);
+    } else {
+      pi0 = make_uint4(f4, f4, f4, f4);
+      pi1 = pi0;
+    }
+  };
+
+  fetch_words();
+  commit_words();
+  fetch_idx(0);
+  for (int ep = 0; ep < nep; ++ep) {
+    const int buf = ep & 1;
+    *reinterpret_cast<uint4*>(&L.idx[buf][lane * 32]) = pi0;
+    *reinterpret_cast<uint4*>(&L.idx[buf][lane * 32 + 16]) = pi1;
+    commit_words();
+    __syncthreads();
+    fetch_idx(ep + 1);
+    if (loaded - cursor < 2u * EPB) fetch_words();
+#pragma unroll 4
+    for (int u = 0; u < EP; ++u) {
+      const int j = ep * EPB + u * LANES + lane;
+      const bool valid = active && j < nsym;
+      const int row = (int)min((uint32_t)L.idx[buf][u * LANES + lane], 63u);
+      const int rowb = row * NSYM;
+      const uint32_t tl = s_tail[row];
+      const uint32_t slot = x & 0xFFFFu;
+      const bool ltail = slot < tl;
+      const bool rtail = slot >= 65536u - tl;
+      const uint32_t le = s_lut[row * LUTB + (slot >> 6)];
+      uint32_t sy = le & 127u;
+      uint32_t fc = s_fc[rowb + sy];
+      if (!(le & 128u) && !ltail && !rtail) {
         while (sy < NSYM - 1) {
           const uint32_t nfc = s_fc[rowb + sy + 1];
           if ((nfc >> 16) > slot) break;
           ++sy;
           fc = nfc;
         }
-        const uint32_t f = fc & 0xFFFFu, c = fc >> 16;
-        uint32_t xn = f * (x >> 16) + slot - c;
-        const bool need = valid && xn < RANS_L;
-        const unsigned long long bal = __ballot(need);
-        const uint32_t m = (uint32_t)(bal >> shsel);
-        const uint32_t cnt = __popc(m);
-        const uint32_t rank = __popc(m & ((1u << lane) - 1u));
-        const uint32_t widx = cursor + rank - wbase;  // < 64 by the window invariant
-        const int src = shsel + (int)(widx & 31u);
-        const uint32_t v0 = __shfl(w0, src, 64);
-        const uint32_t v1 = __shfl(w1, src, 64);
-        if (need) xn = (xn << 16) | (widx < 32u ? v0 : v1);
-        if (valid) {
-          x = xn;
-          out[j] = (uint8_t)sy;
-        }
-        cursor += cnt;
-        if (cursor - wbase >= 32u) {
-          wbase += 32u;
-          w0 = w1;
-          const uint32_t wi = wbase + LANES + lane;
-          w1 = wi < nw ? words[wi] : 0u;
-        }
+      }
+      // frequency-1 tails: symbol = slot (left) or 64 - (65535 - slot) (right)
+      if (ltail | rtail) {
+        sy = ltail ? slot : slot - (65536u - NSYM);
+        fc = 1u | (slot << 16);
+      }
+      const uint32_t f = fc & 0xFFFFu, c = fc >> 16;
+      uint32_t xn = f * (x >> 16) + slot - c;
+      const bool need = valid && xn < RANS_L;
+      const unsigned long long bal = __ballot(need);
+      const uint32_t m = (uint32_t)(bal >> shsel);
+      const uint32_t cnt = __popc(m);
+      const uint32_t rank = __popc(m & ((1u << lane) - 1u));
+      if (need) xn = (xn << 16) | L.ring[(cursor + rank) & (RING - 1)];
+      if (valid) x = xn;
+      L.out[u * LANES + lane] = (uint8_t)sy;
+      cursor += cnt;
+    }
+    __syncthreads();
+    // decoded symbols of the epoch, 32 contiguous bytes per lane
+    const long pos = (long)ep * EPB + lane * 32;
+    if (active) {
+      if (pos + 32 <= nsym) {
+        *reinterpret_cast<uint4*>(out + pos) = *reinterpret_cast<const uint4*>(&L.out[lane * 32]);
+        *reinterpret_cast<uint4*>(out + pos + 16) =
+            *reinterpret_cast<const uint4*>(&L.out[lane * 32 + 16]);
+      } else {
+        for (int i = 0; i < 32; ++i)
+          if (pos + i < nsym) out[pos + i] = usable ? L.out[lane * 32 + i] : 32;
       }
     }
-#pragma unroll
-    for (int u = 0; u < PF; ++u) ci[u] = ni[u];
+  }
+  if (!active) return;
+  if (!usable) {
+    if (lane == 0) atomicOr(status, ST_CORRUPT);
+    return;
   }
   // integrity: every lane back at L, every word consumed (one zero pad word
   // may follow an odd count)
   bool bad = x != RANS_L;
-  if (cursor > nw) bad = true;
-  else if (cursor < nw) {
-    const bool pad_ok = (cursor + 1u == nw) && (cursor & 1u) && words[cursor] == 0;
+  if (cursor > nw) {
+    bad = true;
+  } else if (cursor < nw) {
+    const bool pad_ok = (cursor + 1u == nw) && (cursor & 1u) &&
+                        reinterpret_cast<const uint16_t*>(wdw)[cursor] == 0;
     if (!pad_ok) bad = true;
   }
   const unsigned long long anybad = __ballot(bad);
@@ -480,7 +640,14 @@ hipError_t launch_rans_decode(const Tables& t, const uint8_t* bs, const uint32_t
                               const uint32_t* seg_len, DecStream d, uint32_t* status,
                               hipStream_t s) {
   if (d.n_seg == 0) return hipSuccess;
-  hipLaunchKernelGGL(rans_decode_kernel, dim3((d.n_seg + 7) / 8), dim3(256), 0, s, t, bs,
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rans_decode_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)DEC_LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(rans_decode_kernel, dim3((d.n_seg + 1) / 2), dim3(64), DEC_LDS_BYTES, s, t, bs,
                      seg_off, seg_len, d, status);
   return hipGetLastError();
 }
