@@ -32,39 +32,39 @@ template <int PREC> struct PT;
 template <> struct PT<P_BF16> { static constexpr int ESZ = 2; static constexpr int E = 16; };
 template <> struct PT<P_F32> { static constexpr int ESZ = 4; static constexpr int E = 8; };
 
-union V16 {
-  uint4 u;
-  bf16x8 b;
-  float f[4];
-  __bf16 h[8];
-};
+// 16 bytes as a native vector (HIP's uint4 is a struct whose copies lower to
+// memcpy and can pin staging arrays in scratch memory).
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint4 zero16() { return make_uint4(0, 0, 0, 0); }
+__device__ __forceinline__ v4u zero16() { return v4u{0u, 0u, 0u, 0u}; }
 
-__device__ __forceinline__ uint4 cvt8(const float* v) {
-  V16 r;
+__device__ __forceinline__ v4u cvt8(const float* v) {
+  bf16x8 r;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) r.h[i] = (__bf16)v[i];
-  return r.u;
+  for (int i = 0; i < 8; ++i) r[i] = (__bf16)v[i];
+  return __builtin_bit_cast(v4u, r);
 }
+
+__device__ __forceinline__ v4u ld16(const void* p) { return *reinterpret_cast<const v4u*>(p); }
 
 // 16 bytes of compute-type input for channels [slice*E + ch*E/2, +E/2) at
 // input position (iy, ix); zero outside the input grid (conv zero padding).
 template <int PREC, int LD>
-__device__ __forceinline__ uint4 load_chunk(const ConvArgs& a, const unsigned char* inb,
+__device__ __forceinline__ v4u load_chunk(const ConvArgs& a, const unsigned char* inb,
                                             int slice, int ch, int iy, int ix) {
   constexpr int E = PT<PREC>::E;
   constexpr int ESZ = PT<PREC>::ESZ;
   if (iy < 0 || ix < 0 || iy >= a.Hin || ix >= a.Win) return zero16();
   const long pos = (long)iy * a.Win + ix;
   if constexpr (LD == LD_NHWC) {
-    return *reinterpret_cast<const uint4*>(inb + (pos * a.in_pitch + slice * E + ch * (E / 2)) * ESZ);
+    return ld16(inb + (pos * a.in_pitch + slice * E + ch * (E / 2)) * ESZ);
   } else if constexpr (LD == LD_F32) {
     // float32 tensor feeding a bf16 conv (8 channels -> 8 bf16)
     static_assert(PREC == P_BF16, "use LD_NHWC for float32 compute");
     const float* fp = reinterpret_cast<const float*>(inb) + pos * a.in_pitch + slice * E + ch * (E / 2);
-    const float4 u0 = *reinterpret_cast<const float4*>(fp);
-    const float4 u1 = *reinterpret_cast<const float4*>(fp + 4);
+    const v4f u0 = *reinterpret_cast<const v4f*>(fp);
+    const v4f u1 = *reinterpret_cast<const v4f*>(fp + 4);
     const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
     return cvt8(v);
   } else if constexpr (LD == LD_UNSHUFFLE) {
@@ -79,8 +79,8 @@ __device__ __forceinline__ uint4 load_chunk(const ConvArgs& a, const unsigned ch
     if constexpr (PREC == P_BF16) {
       float v[8];
       if (px + 8 <= a.W) {
-        float4 u0 = *reinterpret_cast<const float4*>(row + px);
-        float4 u1 = *reinterpret_cast<const float4*>(row + px + 4);
+        const v4f u0 = *reinterpret_cast<const v4f*>(row + px);
+        const v4f u1 = *reinterpret_cast<const v4f*>(row + px + 4);
         v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
         v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w;
       } else {
@@ -89,23 +89,23 @@ __device__ __forceinline__ uint4 load_chunk(const ConvArgs& a, const unsigned ch
       }
       return cvt8(v);
     } else {
-      V16 r;
+      v4f r;
       if (px + 4 <= a.W) {
-        r.u = *reinterpret_cast<const uint4*>(row + px);
+        r = *reinterpret_cast<const v4f*>(row + px);
       } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) r.f[k] = row[min(px + k, a.W - 1)];
+        for (int k = 0; k < 4; ++k) r[k] = row[min(px + k, a.W - 1)];
       }
-      return r.u;
+      return __builtin_bit_cast(v4u, r);
     }
   } else if constexpr (LD == LD_DEQUANT) {
     const int c0 = slice * E + ch * (E / 2);
     const unsigned char* sp = reinterpret_cast<const unsigned char*>(a.in) + pos * a.cin + c0;
     const float* mp = a.mu + pos * a.mu_pitch + c0;
     if constexpr (PREC == P_BF16) {
-      uint2 sb = *reinterpret_cast<const uint2*>(sp);
-      float4 m0 = *reinterpret_cast<const float4*>(mp);
-      float4 m1 = *reinterpret_cast<const float4*>(mp + 4);
+      const uint2 sb = *reinterpret_cast<const uint2*>(sp);
+      const v4f m0 = *reinterpret_cast<const v4f*>(mp);
+      const v4f m1 = *reinterpret_cast<const v4f*>(mp + 4);
       float v[8];
       v[0] = (float)((int)(sb.x & 255) - 32) + m0.x;
       v[1] = (float)((int)((sb.x >> 8) & 255) - 32) + m0.y;
@@ -117,14 +117,14 @@ __device__ __forceinline__ uint4 load_chunk(const ConvArgs& a, const unsigned ch
       v[7] = (float)((int)(sb.y >> 24) - 32) + m1.w;
       return cvt8(v);
     } else {
-      uint32_t sb = *reinterpret_cast<const uint32_t*>(sp);
-      float4 m = *reinterpret_cast<const float4*>(mp);
-      V16 r;
-      r.f[0] = (float)((int)(sb & 255) - 32) + m.x;
-      r.f[1] = (float)((int)((sb >> 8) & 255) - 32) + m.y;
-      r.f[2] = (float)((int)((sb >> 16) & 255) - 32) + m.z;
-      r.f[3] = (float)((int)(sb >> 24) - 32) + m.w;
-      return r.u;
+      const uint32_t sb = *reinterpret_cast<const uint32_t*>(sp);
+      const v4f m = *reinterpret_cast<const v4f*>(mp);
+      v4f r;
+      r[0] = (float)((int)(sb & 255) - 32) + m.x;
+      r[1] = (float)((int)((sb >> 8) & 255) - 32) + m.y;
+      r[2] = (float)((int)((sb >> 16) & 255) - 32) + m.z;
+      r[3] = (float)((int)(sb >> 24) - 32) + m.w;
+      return __builtin_bit_cast(v4u, r);
     }
   } else {  // LD_UP2, float32 compute
     static_assert(PREC == P_F32, "up2 loader is float32 only");
@@ -132,13 +132,13 @@ __device__ __forceinline__ uint4 load_chunk(const ConvArgs& a, const unsigned ch
     const int wz = (a.Win + 1) >> 1;
     const unsigned char* sp = reinterpret_cast<const unsigned char*>(a.in) +
                               ((long)(iy >> 1) * wz + (ix >> 1)) * a.cin + c0;
-    uint32_t sb = *reinterpret_cast<const uint32_t*>(sp);
-    V16 r;
-    r.f[0] = (float)((int)(sb & 255) - 32);
-    r.f[1] = (float)((int)((sb >> 8) & 255) - 32);
-    r.f[2] = (float)((int)((sb >> 16) & 255) - 32);
-    r.f[3] = (float)((int)(sb >> 24) - 32);
-    return r.u;
+    const uint32_t sb = *reinterpret_cast<const uint32_t*>(sp);
+    v4f r;
+    r[0] = (float)((int)(sb & 255) - 32);
+    r[1] = (float)((int)((sb >> 8) & 255) - 32);
+    r[2] = (float)((int)((sb >> 16) & 255) - 32);
+    r[3] = (float)((int)(sb >> 24) - 32);
+    return __builtin_bit_cast(v4u, r);
   }
 }
 
@@ -209,50 +209,45 @@ conv3x3_kernel(ConvArgs a) {
   const unsigned char* inb = reinterpret_cast<const unsigned char*>(a.in) +
                             grp * a.in_goff * (LD == LD_F32 ? 4 : ESZ);
 
-  uint4 hreg[HIT];
-  uint4 wreg[WIT];
-
-  auto gload = [&](int s) {
-#pragma unroll
-    for (int i = 0; i < HIT; ++i) {
-      const int q = tid + i * NT;
-      if (HCH % NT == 0 || q < HCH) {
-        int pos, ch;
-        if constexpr (LD == LD_UNSHUFFLE) { ch = q / HP; pos = q - ch * HP; }
-        else { pos = q >> 1; ch = q & 1; }
-        const int hy = pos / HW, hx = pos - hy * HW;
-        hreg[i] = load_chunk<PREC, LD>(a, inb, s, ch, iy0 + hy, ix0 + hx);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < WIT; ++i) {
-      const int q = tid + i * NT;
-      if (WCH % NT == 0 || q < WCH) {
-        const int row = q >> 1, ch = q & 1;
-        const int tap = row / BN, n = row - tap * BN;
-        wreg[i] = *reinterpret_cast<const uint4*>(
-            wbase + (((long)(s * 9 + tap) * a.cout + n0 + n) * 32 + ch * 16));
-      }
-    }
-  };
-  auto lstore = [&]() {
-#pragma unroll
-    for (int i = 0; i < HIT; ++i) {
-      const int q = tid + i * NT;
-      if (HCH % NT == 0 || q < HCH) {
-        int pos, ch;
-        if constexpr (LD == LD_UNSHUFFLE) { ch = q / HP; pos = q - ch * HP; }
-        else { pos = q >> 1; ch = q & 1; }
-        *reinterpret_cast<uint4*>(lds_h + pos * LDS_ROW + ch * 16) = hreg[i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < WIT; ++i) {
-      const int q = tid + i * NT;
-      if (WCH % NT == 0 || q < WCH)
-        *reinterpret_cast<uint4*>(lds_w + (q >> 1) * LDS_ROW + (q & 1) * 16) = wreg[i];
-    }
-  };
+  // Staging registers for the next slice.  Written and read only through
+  // fully unrolled loops with constant indices so they live in VGPRs.
+  v4u hreg[HIT];
+  v4u wreg[WIT];
+#define UFVC_GLOAD(S_)                                                                   \
+  do {                                                                                   \
+    _Pragma("unroll") for (int i = 0; i < HIT; ++i) {                                    \
+      const int q = tid + i * NT;                                                        \
+      int pos, ch;                                                                       \
+      if (LD == LD_UNSHUFFLE) { ch = q / HP; pos = q - ch * HP; }                        \
+      else { pos = q >> 1; ch = q & 1; }                                                 \
+      const int hy = pos / HW, hx = pos - (pos / HW) * HW;                               \
+      hreg[i] = (HCH % NT == 0 || q < HCH)                                               \
+                    ? load_chunk<PREC, LD>(a, inb, (S_), ch, iy0 + hy, ix0 + hx)         \
+                    : zero16();                                                          \
+    }                                                                                    \
+    _Pragma("unroll") for (int i = 0; i < WIT; ++i) {                                    \
+      const int q = min(tid + i * NT, WCH - 1);                                          \
+      const int row = q >> 1, ch = q & 1;                                                \
+      const int tap = row / BN, n = row - (row / BN) * BN;                               \
+      wreg[i] = ld16(wbase + (((long)((S_) * 9 + tap) * a.cout + n0 + n) * 32 + ch * 16)); \
+    }                                                                                    \
+  } while (0)
+#define UFVC_LSTORE()                                                                    \
+  do {                                                                                   \
+    _Pragma("unroll") for (int i = 0; i < HIT; ++i) {                                    \
+      const int q = tid + i * NT;                                                        \
+      int pos, ch;                                                                       \
+      if (LD == LD_UNSHUFFLE) { ch = q / HP; pos = q - ch * HP; }                        \
+      else { pos = q >> 1; ch = q & 1; }                                                 \
+      if (HCH % NT == 0 || q < HCH)                                                      \
+        *reinterpret_cast<v4u*>(lds_h + pos * LDS_ROW + ch * 16) = hreg[i];              \
+    }                                                                                    \
+    _Pragma("unroll") for (int i = 0; i < WIT; ++i) {                                    \
+      const int q = tid + i * NT;                                                        \
+      if (WCH % NT == 0 || q < WCH)                                                      \
+        *reinterpret_cast<v4u*>(lds_w + (q >> 1) * LDS_ROW + (q & 1) * 16) = wreg[i];    \
+    }                                                                                    \
+  } while (0)
 
   int arow[FM];
 #pragma unroll
@@ -271,37 +266,41 @@ conv3x3_kernel(ConvArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[fm][fn][r] = 0.f;
 
-  gload(0);
+  UFVC_GLOAD(0);
   for (int s = 0; s < nslices; ++s) {
-    lstore();
+    UFVC_LSTORE();
     __syncthreads();
-    if (s + 1 < nslices) gload(s + 1);
+    UFVC_GLOAD(min(s + 1, nslices - 1));
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int toff = (tap / 3) * HW + (tap % 3);
-      V16 av[FM], bv[FN];
+      v4u av[FM], bv[FN];
 #pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-        av[fm].u = *reinterpret_cast<const uint4*>(lds_h + (arow[fm] + toff) * LDS_ROW + koff);
+      for (int fm = 0; fm < FM; ++fm) av[fm] = ld16(lds_h + (arow[fm] + toff) * LDS_ROW + koff);
 #pragma unroll
       for (int fn = 0; fn < FN; ++fn)
-        bv[fn].u = *reinterpret_cast<const uint4*>(
-            lds_w + (tap * BN + (wn * FN + fn) * 32 + (lane & 31)) * LDS_ROW + koff);
+        bv[fn] = ld16(lds_w + (tap * BN + (wn * FN + fn) * 32 + (lane & 31)) * LDS_ROW + koff);
 #pragma unroll
       for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
         for (int fn = 0; fn < FN; ++fn) {
           if constexpr (PREC == P_BF16) {
-            acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[fm].b, bv[fn].b, acc[fm][fn], 0, 0, 0);
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, av[fm]), __builtin_bit_cast(bf16x8, bv[fn]), acc[fm][fn], 0, 0, 0);
           } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[fm].f[e], bv[fn].f[e], acc[fm][fn], 0, 0, 0);
+            const v4f fa = __builtin_bit_cast(v4f, av[fm]);
+            const v4f fb = __builtin_bit_cast(v4f, bv[fn]);
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.x, fb.x, acc[fm][fn], 0, 0, 0);
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.y, fb.y, acc[fm][fn], 0, 0, 0);
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.z, fb.z, acc[fm][fn], 0, 0, 0);
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.w, fb.w, acc[fm][fn], 0, 0, 0);
           }
         }
     }
     __syncthreads();
   }
+#undef UFVC_GLOAD
+#undef UFVC_LSTORE
 
   // 32x32 accumulator block: register r of lane l holds row 8(r/4) + 4(l/32) + r%4, column l%32.
 #pragma unroll
