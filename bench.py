@@ -53,10 +53,10 @@ def conv_flops(T, C, h, w):
 
 
 def run_codec(torch, ufvc, weights, prec, chunks, H, W, steps, warmup, seg_log2, seg_log2_z,
-              profile):
+              profile, autotune=True):
     T = chunks[0].shape[0]
     c = ufvc.Codec(T, 128, weights, precision=prec, seg_log2=seg_log2, seg_log2_z=seg_log2_z,
-                   model_tag=0x0800_1080)
+                   model_tag=0x0800_1080, autotune=autotune)
     cap = c.max_bitstream_bytes(H, W)
     bufs = [torch.empty(cap, dtype=torch.uint8, device="cuda") for _ in chunks]
     out = torch.empty((T, 3, H, W), dtype=torch.float32, device="cuda")
@@ -101,9 +101,10 @@ def run_codec(torch, ufvc, weights, prec, chunks, H, W, steps, warmup, seg_log2,
     zs = c.buffer(ufvc.BUF_ZSYM, H, W).reshape(-1)
     f = freq.astype(np.float64)
     ideal = float(np.sum(16 - np.log2(f[idx, sym])) + np.sum(16 - np.log2(f[22, zs])))
+    tuning = c.tuning(H, W)
     c.close()
     return dict(seconds=t1 - t0, lat=lat, stages=stages, rec=rec, bytes=n0, ideal_bits=ideal,
-                n_sym=int(sym.size + zs.size))
+                n_sym=int(sym.size + zs.size), tuning=tuning)
 
 
 def psnr_t(torch, a, b):
@@ -142,6 +143,7 @@ def main():
     ap.add_argument("--seg-log2-z", type=int, default=11)
     ap.add_argument("--chunks", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build measures the single-GPU hot path "
@@ -162,10 +164,10 @@ def main():
 
     log("bench: bf16 timed region")
     r16 = run_codec(torch, ufvc, weights, "bf16", chunks, H, W, args.steps, args.warmup,
-                    args.seg_log2, args.seg_log2_z, profile=True)
+                    args.seg_log2, args.seg_log2_z, profile=True, autotune=not args.no_autotune)
     log("bench: fp32 timed region")
     r32 = run_codec(torch, ufvc, weights, "fp32", chunks, H, W, args.fp32_steps, 2,
-                    args.seg_log2, args.seg_log2_z, profile=True)
+                    args.seg_log2, args.seg_log2_z, profile=True, autotune=not args.no_autotune)
 
     fps16 = T * args.steps / r16["seconds"]
     fps32 = T * args.fp32_steps / r32["seconds"]
@@ -220,6 +222,7 @@ def main():
                        "frac_bf16_peak": round(conv_flop / (conv_ms * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"], 4)},
         "enc_ms": round(enc_ms, 4), "dec_ms": round(dec_ms, 4),
         "stage_ms": stage_ms,
+        "tile_configs": {k: (v[1:] if v else None) for k, v in r16["tuning"].items()},
         "fp32_stage_ms": {k: round(v[0] / args.fp32_steps, 4) for k, v in r32["stages"].items()},
         "bitstream": {"bytes": r16["bytes"], "bits_per_symbol": round(8 * r16["bytes"] / r16["n_sym"], 4),
                       "overhead_vs_ideal": round(8 * r16["bytes"] / r16["ideal_bits"] - 1, 5)},

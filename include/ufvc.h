@@ -61,6 +61,8 @@ typedef struct {
   int seg_log2;        /* y symbols per rANS segment = 2^seg_log2, 5..24 */
   int seg_log2_z;      /* z symbols per rANS segment = 2^seg_log2_z, 5..24 */
   uint32_t model_tag;  /* written to and checked against every bit-stream */
+  int autotune;        /* 1: the first call for an (H, W) bucket times every conv
+                          tile configuration per layer and keeps the fastest */
 } ufvc_config;
 
 typedef struct ufvc_ctx ufvc_ctx;
@@ -150,6 +152,15 @@ int ufvc_synthesize(ufvc_ctx* ctx, const float* y_hat, int T, int H, int W,
 enum { UFVC_BUF_Y = 0, UFVC_BUF_ZSYM = 1, UFVC_BUF_PARAMS = 2, UFVC_BUF_IDX = 3,
        UFVC_BUF_SYM = 4 };
 int ufvc_copy_buffer(ufvc_ctx* ctx, int which, void* host_dst, size_t bytes);
+
+/* ---- Conv tile configurations (autotuner) ----
+ * ufvc_get_tuning writes, for the 9 tunable conv layers of a T x H x W chunk
+ * (a1 a2 a3 d1 d2 d3 k1 k2 k3), the tile configuration chosen so far, or -1
+ * where the built-in default is used (n >= 9).  ufvc_tile_config describes a
+ * configuration: output tile rows x columns and output channels per
+ * workgroup.  Configurations never change results, only speed. */
+int ufvc_get_tuning(ufvc_ctx* ctx, int H, int W, int* cfg, int n);
+int ufvc_tile_config(int cfg, int* th, int* tw, int* bn);
 
 /* ---- Per-stage timing ----
  * With profiling enabled, every kernel launch of the coding calls is

@@ -33,7 +33,7 @@ class UfvcError(RuntimeError):
 class _Config(ctypes.Structure):
     _fields_ = [("T", ctypes.c_int), ("C", ctypes.c_int), ("precision", ctypes.c_int),
                 ("seg_log2", ctypes.c_int), ("seg_log2_z", ctypes.c_int),
-                ("model_tag", ctypes.c_uint32)]
+                ("model_tag", ctypes.c_uint32), ("autotune", ctypes.c_int)]
 
 
 def _load():
@@ -58,6 +58,8 @@ def _load():
         "ufvc_profile_stage_count": (I, []),
         "ufvc_profile_stage_name": (ctypes.c_char_p, [I]),
         "ufvc_profile_read": (I, [P, P, P, I]),
+        "ufvc_get_tuning": (I, [P, I, I, P, I]),
+        "ufvc_tile_config": (I, [I, P, P, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -74,7 +76,8 @@ EXPORTS = ("ufvc_weight_count", "ufvc_create", "ufvc_destroy", "ufvc_max_bitstre
            "ufvc_encode_chunk", "ufvc_decode_chunk", "ufvc_sync_status", "ufvc_get_tables",
            "ufvc_rans_encode", "ufvc_rans_decode", "ufvc_synthesize", "ufvc_copy_buffer",
            "ufvc_profile_enable", "ufvc_profile_stage_count", "ufvc_profile_stage_name",
-           "ufvc_profile_read")
+           "ufvc_profile_read", "ufvc_get_tuning", "ufvc_tile_config")
+TUNED_LAYERS = ("a1", "a2", "a3", "d1", "d2", "d3", "k1", "k2", "k3")
 
 
 def layer_order(T: int) -> list[str]:
@@ -109,12 +112,14 @@ class Codec:
     """One codec context (one model: fixed T and C) on the current device."""
 
     def __init__(self, T: int, C: int, weights: dict, precision: str = "bf16",
-                 seg_log2: int = 15, seg_log2_z: int = 11, model_tag: int = 0):
+                 seg_log2: int = 15, seg_log2_z: int = 11, model_tag: int = 0,
+                 autotune: bool = False):
         self.T, self.C = T, C
         self.precision = precision
         self.seg_log2, self.seg_log2_z, self.model_tag = seg_log2, seg_log2_z, model_tag
         flat = flatten_weights(weights, T)
-        cfg = _Config(T, C, PRECISIONS[precision], seg_log2, seg_log2_z, model_tag & 0xFFFFFFFF)
+        cfg = _Config(T, C, PRECISIONS[precision], seg_log2, seg_log2_z, model_tag & 0xFFFFFFFF,
+                      1 if autotune else 0)
         h = ctypes.c_void_p()
         _check(lib.ufvc_create(ctypes.byref(cfg), flat.ctypes.data, flat.size, ctypes.byref(h)),
                "ufvc_create")
@@ -207,6 +212,20 @@ class Codec:
         _check(lib.ufvc_rans_decode(self._h, _ptr(data), data.numel(), _ptr(idx), n, seg_log2,
                                     _ptr(sym), _stream(stream)), "ufvc_rans_decode")
         return sym
+
+    def tuning(self, H: int, W: int) -> dict:
+        """{layer: (config index, tile rows, tile cols, channels)} chosen so far."""
+        cfg = np.zeros(9, np.int32)
+        _check(lib.ufvc_get_tuning(self._h, H, W, cfg.ctypes.data, 9), "ufvc_get_tuning")
+        out = {}
+        for name, k in zip(TUNED_LAYERS, cfg):
+            if k < 0:
+                out[name] = None
+                continue
+            th, tw, bn = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            lib.ufvc_tile_config(int(k), ctypes.byref(th), ctypes.byref(tw), ctypes.byref(bn))
+            out[name] = (int(k), th.value, tw.value, bn.value)
+        return out
 
     # ------------------------------------------------------------ timing
     def profile(self, on: bool = True):

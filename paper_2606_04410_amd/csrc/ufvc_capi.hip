@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -70,6 +71,8 @@ struct ufvc_ctx {
   size_t ev_used = 0;
   struct Rec { int stage; hipEvent_t e0, e1; };
   std::vector<Rec> prof_rec;
+  // autotuned tile configuration per (conv stage, output height, width)
+  std::map<uint64_t, int> tune;
 };
 
 #define CK(x)                                   \
@@ -110,6 +113,56 @@ static hipError_t stage(ufvc_ctx* c, int id, hipStream_t s, F&& launch) {
     }
   }
   return r;
+}
+
+// Conv tile configurations are chosen per (layer, output size) bucket.  With
+// cfg.autotune set, the first call for a bucket times every configuration
+// whose channel tile divides the layer's outputs (HIP events, two runs each,
+// the second counted) and keeps the fastest.  All configurations accumulate
+// every output in the same order, so the choice never changes results.
+static int default_cfg(int cout, long npos) {
+  if (cout % 128 == 0) return npos >= 16384 ? 5 : 0;
+  if (cout % 192 == 0) return 2;
+  if (cout % 64 == 0) return 4;
+  return 1;
+}
+
+static uint64_t tune_key(int id, int h, int w) {
+  return ((uint64_t)id << 40) | ((uint64_t)h << 20) | (uint64_t)w;
+}
+
+static hipError_t tuned_conv(ufvc_ctx* c, int id, int prec, int ld, int st, const ConvArgs& a,
+                             int groups, hipStream_t s) {
+  const uint64_t key = tune_key(id, a.Hout, a.Wout);
+  auto it = c->tune.find(key);
+  if (it != c->tune.end()) return launch_conv(prec, ld, st, 1, it->second, a, groups, s);
+  if (!c->cfg.autotune)
+    return launch_conv(prec, ld, st, 1, default_cfg(a.cout, (long)a.Hout * a.Wout), a, groups, s);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hipErrorOutOfMemory;
+  int best = -1;
+  float best_ms = 1e30f;
+  hipError_t err = hipSuccess;
+  for (int cfg = 0; cfg < conv_num_cfgs(); ++cfg) {
+    const TileCfg t = conv_cfg(cfg);
+    if (a.cout % t.bn) continue;
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+      (void)hipEventRecord(e0, s);
+      err = launch_conv(prec, ld, st, 1, cfg, a, groups, s);
+      if (err != hipSuccess) break;
+      (void)hipEventRecord(e1, s);
+      if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (err != hipSuccess) break;
+    if (ms < best_ms) { best_ms = ms; best = cfg; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess || best < 0) return err != hipSuccess ? err : hipErrorInvalidValue;
+  c->tune[key] = best;
+  return launch_conv(prec, ld, st, 1, best, a, groups, s);
 }
 
 static int act_elem_size(int prec) { return prec == UFVC_FP32 ? 4 : 2; }
@@ -295,28 +348,28 @@ static hipError_t run_synthesis(ufvc_ctx* c, const Geom& g, const uint8_t* sym, 
   a.out = c->ws.act0;
   a.out_pitch = C;
   a.relu = 1;
-  e = stage(c, S_D1, s, [&] { return launch_conv(cp, ld, act_st, 1, cfg_for(a.cout), a, 1, s); });
+  e = stage(c, S_D1, s, [&] { return tuned_conv(c, S_D1, cp, ld, act_st, a, 1, s); });
   if (e != hipSuccess) return e;
   a = conv_args(g.h, g.w, g.h, g.w, c->d2);
   a.in = c->ws.act0; a.in_pitch = C; a.out = c->ws.act1; a.out_pitch = C; a.relu = 1;
-  if ((e = stage(c, S_D2, s, [&] { return launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s); })) != hipSuccess) return e;
+  if ((e = stage(c, S_D2, s, [&] { return tuned_conv(c, S_D2, cp, LD_NHWC, act_st, a, 1, s); })) != hipSuccess) return e;
   a = conv_args(g.h, g.w, g.h, g.w, c->d3);
   a.in = c->ws.act1; a.in_pitch = C; a.out = c->ws.act0; a.out_pitch = C; a.relu = 1;
-  if ((e = stage(c, S_D3, s, [&] { return launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s); })) != hipSuccess) return e;
+  if ((e = stage(c, S_D3, s, [&] { return tuned_conv(c, S_D3, cp, LD_NHWC, act_st, a, 1, s); })) != hipSuccess) return e;
   // k1 of all heads as one GEMM with T*C outputs
   a = conv_args(g.h, g.w, g.h, g.w, c->k1);
   a.in = c->ws.act0; a.in_pitch = C; a.out = c->ws.big0; a.out_pitch = (long)T * C; a.relu = 1;
-  if ((e = stage(c, S_K1, s, [&] { return launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s); })) != hipSuccess) return e;
+  if ((e = stage(c, S_K1, s, [&] { return tuned_conv(c, S_K1, cp, LD_NHWC, act_st, a, 1, s); })) != hipSuccess) return e;
   // k2 per head: group t reads channels [tC, tC + C) and writes the same range
   a = conv_args(g.h, g.w, g.h, g.w, c->k2);
   a.in = c->ws.big0; a.in_pitch = (long)T * C; a.in_goff = C;
   a.out = c->ws.big1; a.out_pitch = (long)T * C; a.out_goff = C; a.relu = 1;
-  if ((e = stage(c, S_K2, s, [&] { return launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, T, s); })) != hipSuccess) return e;
+  if ((e = stage(c, S_K2, s, [&] { return tuned_conv(c, S_K2, cp, LD_NHWC, act_st, a, T, s); })) != hipSuccess) return e;
   // k3 per head with the pixel-shuffle store into frame t
   a = conv_args(g.h, g.w, g.h, g.w, c->k3);
   a.in = c->ws.big1; a.in_pitch = (long)T * C; a.in_goff = C;
   a.out = frames; a.T = T; a.H = H; a.W = W;
-  return stage(c, S_K3, s, [&] { return launch_conv(cp, LD_NHWC, ST_SHUFFLE, 1, 2, a, T, s); });
+  return stage(c, S_K3, s, [&] { return tuned_conv(c, S_K3, cp, LD_NHWC, ST_SHUFFLE, a, T, s); });
 }
 
 extern "C" {
@@ -436,13 +489,13 @@ int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uin
   ConvArgs a = conv_args(g.h, g.w, g.h, g.w, c->a1);
   a.in = frames; a.T = T; a.H = H; a.W = W;
   a.out = ws.act0; a.out_pitch = C; a.relu = 1;
-  CK(stage(c, S_A1, s, [&] { return launch_conv(cp, LD_UNSHUFFLE, act_st, 1, cfg_for(a.cout), a, 1, s); }));
+  CK(stage(c, S_A1, s, [&] { return tuned_conv(c, S_A1, cp, LD_UNSHUFFLE, act_st, a, 1, s); }));
   a = conv_args(g.h, g.w, g.h, g.w, c->a2);
   a.in = ws.act0; a.in_pitch = C; a.out = ws.act1; a.out_pitch = C; a.relu = 1;
-  CK(stage(c, S_A2, s, [&] { return launch_conv(cp, LD_NHWC, act_st, 1, cfg_for(a.cout), a, 1, s); }));
+  CK(stage(c, S_A2, s, [&] { return tuned_conv(c, S_A2, cp, LD_NHWC, act_st, a, 1, s); }));
   a = conv_args(g.h, g.w, g.h, g.w, c->a3);
   a.in = ws.act1; a.in_pitch = C; a.out = ws.y; a.out_pitch = C; a.relu = 0;
-  CK(stage(c, S_A3, s, [&] { return launch_conv(cp, LD_NHWC, ST_F32, 1, cfg_for(a.cout), a, 1, s); }));
+  CK(stage(c, S_A3, s, [&] { return tuned_conv(c, S_A3, cp, LD_NHWC, ST_F32, a, 1, s); }));
   // hyper prior: stride-2 conv, z_hat = clamp(rint(z)) stored as symbols
   a = conv_args(g.h, g.w, g.hz, g.wz, c->h);
   a.in = ws.y; a.in_pitch = C; a.out = ws.zsym; a.out_pitch = ZC;
@@ -607,6 +660,26 @@ int ufvc_profile_read(ufvc_ctx* c, double* total_ms, int* count, int n) {
   }
   c->prof_rec.clear();
   c->ev_used = 0;
+  return UFVC_OK;
+}
+
+int ufvc_get_tuning(ufvc_ctx* c, int H, int W, int* cfg, int n) {
+  Geom g;
+  if (!c || !cfg || n < 9 || !geom(c, H, W, g)) return UFVC_E_INVAL;
+  const int ids[9] = {S_A1, S_A2, S_A3, S_D1, S_D2, S_D3, S_K1, S_K2, S_K3};
+  for (int i = 0; i < 9; ++i) {
+    auto it = c->tune.find(tune_key(ids[i], g.h, g.w));
+    cfg[i] = it == c->tune.end() ? -1 : it->second;
+  }
+  return UFVC_OK;
+}
+
+int ufvc_tile_config(int cfg, int* th, int* tw, int* bn) {
+  if (cfg < 0 || cfg >= conv_num_cfgs() || !th || !tw || !bn) return UFVC_E_INVAL;
+  const TileCfg t = conv_cfg(cfg);
+  *th = t.th;
+  *tw = t.tw;
+  *bn = t.bn;
   return UFVC_OK;
 }
 

@@ -7,8 +7,8 @@
 // Per workgroup and per K slice of 32 bytes of input channels (16 bf16 or 8
 // f32 channels) the kernel stages into LDS
 //   * the input halo of the tile, (TH+2) x (TW+2) positions (stride 1) or
-//     (2TH+1) x (2TW+1) (stride 2), 48-byte rows (32 data + 16 pad so that
-//     16 consecutive rows hit disjoint banks), and
+//     (2TH+1) x (2TW+1) (stride 2), 32-byte rows with an XOR swizzle of their
+//     halves so that 16 consecutive rows hit disjoint banks, and
 //   * the packed weights of that slice for all 9 taps and BN channels,
 // then every wave runs 9 taps of 32x32 MFMA blocks (bf16 32x32x16 or four
 // f32 32x32x2) reading A (positions x channels) from the halo shifted by the
@@ -163,7 +163,13 @@ __device__ __forceinline__ void store_out(const ConvArgs& a, int grp, int oy, in
   }
 }
 
-constexpr int LDS_ROW = 48;
+// LDS rows are the 32 bytes of one position (or weight row) per slice.  The
+// two 16-byte halves swap places every 8 rows, so 16 lanes reading the same
+// half of 16 consecutive rows hit 64 distinct banks (no padding needed).
+constexpr int LDS_ROW = 32;
+__device__ __forceinline__ int lds_off(int row, int half) {
+  return row * LDS_ROW + ((half ^ ((row >> 3) & 1)) << 4);
+}
 
 template <int STRIDE, int TH, int TW, int BN>
 constexpr int conv_lds_bytes() {
@@ -197,9 +203,15 @@ conv3x3_kernel(ConvArgs a) {
   const int wm = wave / WN;
   const int wn = wave - wm * WN;
   const int grp = blockIdx.z;
+  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous band of spatial tiles so neighbouring halos share its L2.
   const int tiles_x = (a.Wout + TW - 1) / TW;
-  const int oy0 = (blockIdx.x / tiles_x) * TH;
-  const int ox0 = (blockIdx.x % tiles_x) * TW;
+  const int ntiles = ((a.Hout + TH - 1) / TH) * tiles_x;
+  const int per_xcd = (ntiles + 7) >> 3;
+  const int tile = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (tile >= ntiles) return;
+  const int oy0 = (tile / tiles_x) * TH;
+  const int ox0 = (tile % tiles_x) * TW;
   const int n0 = blockIdx.y * BN;
   const int iy0 = STRIDE * oy0 - 1;
   const int ix0 = STRIDE * ox0 - 1;
@@ -240,12 +252,12 @@ conv3x3_kernel(ConvArgs a) {
       if (LD == LD_UNSHUFFLE) { ch = q / HP; pos = q - ch * HP; }                        \
       else { pos = q >> 1; ch = q & 1; }                                                 \
       if (HCH % NT == 0 || q < HCH)                                                      \
-        *reinterpret_cast<v4u*>(lds_h + pos * LDS_ROW + ch * 16) = hreg[i];              \
+        *reinterpret_cast<v4u*>(lds_h + lds_off(pos, ch)) = hreg[i];                     \
     }                                                                                    \
     _Pragma("unroll") for (int i = 0; i < WIT; ++i) {                                    \
       const int q = tid + i * NT;                                                        \
       if (WCH % NT == 0 || q < WCH)                                                      \
-        *reinterpret_cast<v4u*>(lds_w + (q >> 1) * LDS_ROW + (q & 1) * 16) = wreg[i];    \
+        *reinterpret_cast<v4u*>(lds_w + lds_off(q >> 1, q & 1)) = wreg[i];               \
     }                                                                                    \
   } while (0)
 
@@ -256,7 +268,7 @@ conv3x3_kernel(ConvArgs a) {
     const int r = M / TW, c = M - (M / TW) * TW;
     arow[fm] = STRIDE == 1 ? r * HW + c : 2 * r * HW + 2 * c;
   }
-  const int koff = (lane >> 5) * 16;
+  const int khalf = lane >> 5;
 
   f32x16 acc[FM][FN];
 #pragma unroll
@@ -271,25 +283,39 @@ conv3x3_kernel(ConvArgs a) {
     UFVC_LSTORE();
     __syncthreads();
     UFVC_GLOAD(min(s + 1, nslices - 1));
+    // Fragments of tap t + 1 are read from LDS into the second register set
+    // before the MFMAs of tap t are issued, so LDS latency overlaps the
+    // matrix cores.
+    v4u af[2][FM], bf[2][FN];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm) af[0][fm] = ld16(lds_h + lds_off(arow[fm], khalf));
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+      bf[0][fn] = ld16(lds_w + lds_off((wn * FN + fn) * 32 + (lane & 31), khalf));
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-      const int toff = (tap / 3) * HW + (tap % 3);
-      v4u av[FM], bv[FN];
+      const int cur = tap & 1, nxt = cur ^ 1;
+      if (tap + 1 < 9) {
+        const int toff = ((tap + 1) / 3) * HW + ((tap + 1) % 3);
 #pragma unroll
-      for (int fm = 0; fm < FM; ++fm) av[fm] = ld16(lds_h + (arow[fm] + toff) * LDS_ROW + koff);
+        for (int fm = 0; fm < FM; ++fm) af[nxt][fm] = ld16(lds_h + lds_off(arow[fm] + toff, khalf));
 #pragma unroll
-      for (int fn = 0; fn < FN; ++fn)
-        bv[fn] = ld16(lds_w + (tap * BN + (wn * FN + fn) * 32 + (lane & 31)) * LDS_ROW + koff);
+        for (int fn = 0; fn < FN; ++fn)
+          bf[nxt][fn] = ld16(lds_w + lds_off((tap + 1) * BN + (wn * FN + fn) * 32 + (lane & 31), khalf));
+      }
+      // keep the next tap's reads ahead of this tap's MFMAs
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
         for (int fn = 0; fn < FN; ++fn) {
           if constexpr (PREC == P_BF16) {
             acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, av[fm]), __builtin_bit_cast(bf16x8, bv[fn]), acc[fm][fn], 0, 0, 0);
+                __builtin_bit_cast(bf16x8, af[cur][fm]), __builtin_bit_cast(bf16x8, bf[cur][fn]),
+                acc[fm][fn], 0, 0, 0);
           } else {
-            const v4f fa = __builtin_bit_cast(v4f, av[fm]);
-            const v4f fb = __builtin_bit_cast(v4f, bv[fn]);
+            const v4f fa = __builtin_bit_cast(v4f, af[cur][fm]);
+            const v4f fb = __builtin_bit_cast(v4f, bf[cur][fn]);
             acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.x, fb.x, acc[fm][fn], 0, 0, 0);
             acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.y, fb.y, acc[fm][fn], 0, 0, 0);
             acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.z, fb.z, acc[fm][fn], 0, 0, 0);
@@ -322,7 +348,11 @@ conv3x3_kernel(ConvArgs a) {
 //      2 = 8x16 tile, 192 channels, 2x2 waves of 64x96
 //      3 = 4x16 tile, 128 channels, 2x2 waves of 32x64 (more workgroups)
 //      4 = 8x16 tile,  64 channels, 2x2 waves of 64x32
-static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32}, {8, 16, 192}, {4, 16, 128}, {8, 16, 64}};
+//      5 = 16x16 tile, 128 channels, 2x2 waves of 128x64
+//      6 = 16x16 tile, 192 channels, 2x2 waves of 128x96
+//      7 = 16x16 tile,  64 channels, 2x2 waves of 128x32
+static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 16, 128},
+                                {8, 16, 64},  {16, 16, 128}, {16, 16, 192}, {16, 16, 64}};
 int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 TileCfg conv_cfg(int c) { return kCfgs[c]; }
 
@@ -340,7 +370,7 @@ static hipError_t run_conv(const ConvArgs& a, int groups, hipStream_t s) {
   }
   if (a.cout % BN || a.cin % PT<PREC>::E) return hipErrorInvalidValue;
   const int tiles = ((a.Hout + TH - 1) / TH) * ((a.Wout + TW - 1) / TW);
-  dim3 grid(tiles, a.cout / BN, groups);
+  dim3 grid(((tiles + 7) / 8) * 8, a.cout / BN, groups);
   hipLaunchKernelGGL(kern, grid, dim3(WM * WN * 64), lds, s, a);
   return hipGetLastError();
 }
@@ -353,6 +383,9 @@ static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, hipStream_t s)
     case 2: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 3>(a, groups, s);
     case 3: return run_conv<PREC, LD, ST, STRIDE, 4, 16, 2, 2, 1, 2>(a, groups, s);
     case 4: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 1>(a, groups, s);
+    case 5: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 2>(a, groups, s);
+    case 6: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 3>(a, groups, s);
+    case 7: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 1>(a, groups, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -282,3 +282,25 @@ def test_bf16_psnr_within_005db_of_fp32_c1():
         ps[prec] = ocodec.psnr(fr, c.decode(bs, n, H, W).cpu().numpy())
     say(f"  PSNR fp32 {ps['fp32']:.4f} bf16 {ps['bf16']:.4f}")
     assert abs(ps["fp32"] - ps["bf16"]) <= 0.05
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_tile_configuration_never_changes_results(prec):
+    """Autotuned and default tile configurations give identical streams and frames."""
+    say(f"autotune invariance {prec}")
+    T, H, W, C = 4, 128, 192, 64
+    fr = torch.from_numpy(video_chunk(T, H, W, 3, seed=5)).cuda()
+    w = stand_in_weights(T, C)
+    outs = []
+    for tune in (False, True):
+        c = pkg().Codec(T, C, w, precision=prec, seg_log2=12, seg_log2_z=9, model_tag=7,
+                        autotune=tune)
+        bs, n = c.encode(fr)
+        rec = c.decode(bs, n, H, W)
+        outs.append((bs[:n].cpu().numpy().tobytes(), rec.cpu().numpy()))
+        if tune:
+            say(f"  tuned: {c.tuning(H, W)}")
+            assert all(v is not None for v in c.tuning(H, W).values())
+        c.close()
+    assert outs[0][0] == outs[1][0]
+    assert np.array_equal(outs[0][1], outs[1][1])
