@@ -153,6 +153,37 @@ enum { UFVC_BUF_Y = 0, UFVC_BUF_ZSYM = 1, UFVC_BUF_PARAMS = 2, UFVC_BUF_IDX = 3,
        UFVC_BUF_SYM = 4 };
 int ufvc_copy_buffer(ufvc_ctx* ctx, int which, void* host_dst, size_t bytes);
 
+/* ---- Batches: many chunks of uneven size per launch ----
+ * A batch object runs encode or decode of n chunks (each with its own model,
+ * i.e. its own T, and its own H x W) with one launch per pipeline stage and
+ * tile configuration, instead of one launch per chunk and stage.  All models
+ * must share C, precision and segment sizes.  Per batch composition (the
+ * list of (model, H, W)) the object keeps a device arena and fixed-address
+ * work lists; with use_graph the decode of a composition is captured once
+ * into a hipGraph and replayed.  Results are bitwise identical to the
+ * single-chunk calls.  Calls on one batch object must use one stream. */
+typedef struct ufvc_batch ufvc_batch;
+typedef struct {
+  int model;            /* index into the models given to ufvc_batch_create */
+  int H, W;             /* frame size; T is the model's */
+  const float* frames;  /* encode: input frames, device [T][3][H][W] */
+  float* frames_out;    /* decode: output frames, device [T][3][H][W] */
+  uint8_t* bitstream;   /* encode: output buffer; decode: input stream (device) */
+  size_t capacity;      /* encode: bytes available at bitstream */
+  size_t len;           /* decode: stream bytes; encode: set to the coded size */
+  int status;           /* set: UFVC_OK or this chunk's error */
+} ufvc_chunk;
+
+/* models: n_models contexts, which must outlive the batch object. */
+int ufvc_batch_create(ufvc_ctx* const* models, int n_models, ufvc_batch** out);
+void ufvc_batch_destroy(ufvc_batch* b);
+/* Encodes every chunk; synchronises `stream` and sets len and status. */
+int ufvc_encode_batch(ufvc_batch* b, ufvc_chunk* chunks, int n, void* stream);
+/* Decodes every chunk; asynchronous (status via ufvc_batch_sync_status). */
+int ufvc_decode_batch(ufvc_batch* b, ufvc_chunk* chunks, int n, int use_graph, void* stream);
+/* Synchronises `stream` and sets each chunk's decode status. */
+int ufvc_batch_sync_status(ufvc_batch* b, ufvc_chunk* chunks, int n, void* stream);
+
 /* ---- Conv tile configurations (autotuner) ----
  * ufvc_get_tuning writes, for the 9 tunable conv layers of a T x H x W chunk
  * (a1 a2 a3 d1 d2 d3 k1 k2 k3), the tile configuration chosen so far, or -1

@@ -36,6 +36,13 @@ class _Config(ctypes.Structure):
                 ("model_tag", ctypes.c_uint32), ("autotune", ctypes.c_int)]
 
 
+class _Chunk(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int), ("H", ctypes.c_int), ("W", ctypes.c_int),
+                ("frames", ctypes.c_void_p), ("frames_out", ctypes.c_void_p),
+                ("bitstream", ctypes.c_void_p), ("capacity", ctypes.c_size_t),
+                ("len", ctypes.c_size_t), ("status", ctypes.c_int)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing; build it with python paper_2606_04410_amd/build.py")
@@ -60,6 +67,11 @@ def _load():
         "ufvc_profile_read": (I, [P, P, P, I]),
         "ufvc_get_tuning": (I, [P, I, I, P, I]),
         "ufvc_tile_config": (I, [I, P, P, P]),
+        "ufvc_batch_create": (I, [P, I, ctypes.POINTER(P)]),
+        "ufvc_batch_destroy": (None, [P]),
+        "ufvc_encode_batch": (I, [P, P, I, P]),
+        "ufvc_decode_batch": (I, [P, P, I, I, P]),
+        "ufvc_batch_sync_status": (I, [P, P, I, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -76,7 +88,8 @@ EXPORTS = ("ufvc_weight_count", "ufvc_create", "ufvc_destroy", "ufvc_max_bitstre
            "ufvc_encode_chunk", "ufvc_decode_chunk", "ufvc_sync_status", "ufvc_get_tables",
            "ufvc_rans_encode", "ufvc_rans_decode", "ufvc_synthesize", "ufvc_copy_buffer",
            "ufvc_profile_enable", "ufvc_profile_stage_count", "ufvc_profile_stage_name",
-           "ufvc_profile_read", "ufvc_get_tuning", "ufvc_tile_config")
+           "ufvc_profile_read", "ufvc_get_tuning", "ufvc_tile_config", "ufvc_batch_create",
+           "ufvc_batch_destroy", "ufvc_encode_batch", "ufvc_decode_batch", "ufvc_batch_sync_status")
 TUNED_LAYERS = ("a1", "a2", "a3", "d1", "d2", "d3", "k1", "k2", "k3")
 
 
@@ -249,3 +262,56 @@ class Codec:
         a = np.zeros(shape, dt)
         _check(lib.ufvc_copy_buffer(self._h, which, a.ctypes.data, a.nbytes), "ufvc_copy_buffer")
         return a
+
+
+class Batch:
+    """Many chunks per launch over one or more models (contexts) sharing C,
+    precision and segment sizes.  Keep the codecs alive while the batch is."""
+
+    def __init__(self, codecs):
+        self.codecs = list(codecs)
+        arr = (ctypes.c_void_p * len(self.codecs))(*[c._h.value for c in self.codecs])
+        h = ctypes.c_void_p()
+        _check(lib.ufvc_batch_create(arr, len(self.codecs), ctypes.byref(h)), "ufvc_batch_create")
+        self._h = h
+        self._last = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.ufvc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def encode(self, items, stream=None):
+        """items: [(model index, frames cuda (T,3,H,W), out uint8 cuda buffer)].
+        Returns the coded lengths."""
+        n = len(items)
+        arr = (_Chunk * n)()
+        for i, (m, fr, out) in enumerate(items):
+            arr[i] = _Chunk(m, fr.shape[2], fr.shape[3], _ptr(fr), None, _ptr(out), out.numel(), 0, 0)
+        code = lib.ufvc_encode_batch(self._h, arr, n, _stream(stream))
+        _check(code, "ufvc_encode_batch")
+        return [int(arr[i].len) for i in range(n)]
+
+    def decode(self, items, graph=False, stream=None, check=True):
+        """items: [(model index, bitstream cuda, nbytes, H, W, frames_out cuda)]."""
+        n = len(items)
+        arr = (_Chunk * n)()
+        for i, (m, bs, nb, H, W, out) in enumerate(items):
+            arr[i] = _Chunk(m, H, W, None, _ptr(out), _ptr(bs), 0, nb, 0)
+        self._last = arr
+        _check(lib.ufvc_decode_batch(self._h, arr, n, 1 if graph else 0, _stream(stream)),
+               "ufvc_decode_batch")
+        if check:
+            return self.sync_status(stream)
+        return None
+
+    def sync_status(self, stream=None):
+        arr = self._last
+        code = lib.ufvc_batch_sync_status(self._h, arr, len(arr), _stream(stream))
+        return [int(arr[i].status) for i in range(len(arr))], code

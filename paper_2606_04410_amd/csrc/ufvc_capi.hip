@@ -9,86 +9,9 @@
 #include <vector>
 
 #include "ufvc_common.h"
+#include "ufvc_ctx.h"
 
 using namespace ufvc;
-
-namespace {
-
-constexpr int ZC = 32;   // hyper-latent channels
-constexpr int K_Z = 22;  // table row of every z symbol (sigma ~ 1)
-
-struct Layer {
-  void* w = nullptr;   // packed [group][slice][tap][cout][32 bytes]
-  long gstride = 0;    // bytes per group
-  int cin = 0, cout = 0, groups = 0, prec = 0;
-};
-
-struct Workspace {
-  int h = 0, w = 0;               // latent size the buffers are sized for
-  void* act0 = nullptr;           // [h][w][C], compute type
-  void* act1 = nullptr;
-  float* y = nullptr;             // [h][w][C]
-  uint8_t* zsym = nullptr;        // [hz][wz][32]
-  float* P = nullptr;             // [h][w][2C]
-  uint8_t* idx = nullptr;         // [h][w][C]
-  uint8_t* sym = nullptr;         // [h][w][C]
-  void* big0 = nullptr;           // [h][w][T C]
-  void* big1 = nullptr;
-};
-
-struct RansWs {
-  size_t scratch_bytes = 0;
-  uint8_t* scratch = nullptr;
-  int nseg_cap = 0;
-  SegInfo* info = nullptr;
-  uint32_t* seg_off = nullptr;
-  uint32_t* seg_len = nullptr;
-  // padded copies of caller-provided symbol / index arrays (the coders read
-  // 32-byte windows that may run past the end of an array)
-  size_t pad_cap = 0;
-  uint8_t* pad_a = nullptr;
-  uint8_t* pad_b = nullptr;
-};
-
-}  // namespace
-
-struct ufvc_ctx {
-  ufvc_config cfg{};
-  int device = 0;
-  Tables tab{};
-  Layer a1, a2, a3, h, p, d1, d2, d3, k1, k2, k3;
-  Workspace ws;
-  RansWs rw;
-  unsigned long long* result = nullptr;      // device
-  unsigned long long* result_host = nullptr; // pinned
-  uint32_t* status = nullptr;                // device
-  uint32_t* status_host = nullptr;           // pinned
-  hipStream_t last_stream = nullptr;
-  int last_h = 0, last_w = 0;
-  // per-stage timing (events recorded on the caller's stream around kernels)
-  bool prof_on = false;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  struct Rec { int stage; hipEvent_t e0, e1; };
-  std::vector<Rec> prof_rec;
-  // autotuned tile configuration per (conv stage, output height, width)
-  std::map<uint64_t, int> tune;
-};
-
-#define CK(x)                                   \
-  do {                                          \
-    if ((x) != hipSuccess) return UFVC_E_DEVICE; \
-  } while (0)
-
-enum Stage {
-  S_A1, S_A2, S_A3, S_HYPER, S_PARAMS_ENC, S_EPI_ENC, S_RANS_ENC, S_COMPACT, S_PARSE,
-  S_RANS_DEC_Z, S_PARAMS_DEC, S_EPI_DEC, S_RANS_DEC_Y, S_D1, S_D2, S_D3, S_K1, S_K2, S_K3,
-  S_COUNT
-};
-static const char* kStageNames[S_COUNT] = {
-    "a1_conv", "a2_conv", "a3_conv", "hyper_conv", "params_conv_enc", "params_epilogue_enc",
-    "rans_encode", "compact", "parse", "rans_decode_z", "params_conv_dec", "params_epilogue_dec",
-    "rans_decode_y", "d1_conv", "d2_conv", "d3_conv", "k1_conv", "k2_conv", "k3_conv"};
 
 static hipEvent_t prof_event(ufvc_ctx* c) {
   if (c->ev_used == c->ev_pool.size()) {
@@ -120,17 +43,6 @@ static hipError_t stage(ufvc_ctx* c, int id, hipStream_t s, F&& launch) {
 // whose channel tile divides the layer's outputs (HIP events, two runs each,
 // the second counted) and keeps the fastest.  All configurations accumulate
 // every output in the same order, so the choice never changes results.
-static int default_cfg(int cout, long npos) {
-  if (cout % 128 == 0) return npos >= 16384 ? 5 : 0;
-  if (cout % 192 == 0) return 2;
-  if (cout % 64 == 0) return 4;
-  return 1;
-}
-
-static uint64_t tune_key(int id, int h, int w) {
-  return ((uint64_t)id << 40) | ((uint64_t)h << 20) | (uint64_t)w;
-}
-
 static hipError_t tuned_conv(ufvc_ctx* c, int id, int prec, int ld, int st, const ConvArgs& a,
                              int groups, hipStream_t s) {
   const uint64_t key = tune_key(id, a.Hout, a.Wout);
@@ -164,9 +76,6 @@ static hipError_t tuned_conv(ufvc_ctx* c, int id, int prec, int ld, int st, cons
   c->tune[key] = best;
   return launch_conv(prec, ld, st, 1, best, a, groups, s);
 }
-
-static int act_elem_size(int prec) { return prec == UFVC_FP32 ? 4 : 2; }
-static int conv_prec(int prec) { return prec == UFVC_FP32 ? P_F32 : P_BF16; }
 
 static size_t weight_count_tc(int T, int C) {
   const size_t k9 = 9;
@@ -286,44 +195,6 @@ static int ensure_pad(ufvc_ctx* c, size_t n) {
   return UFVC_OK;
 }
 
-static int nseg_of(long n, int sl) { return n == 0 ? 0 : (int)((n + (1L << sl) - 1) >> sl); }
-static size_t slot_bytes(int sl) { return (size_t)SEG_STATE_BYTES + 2 * ((size_t)1 << sl); }
-
-struct Geom {
-  int Hp, Wp, h, w, hz, wz;
-  long ny, nz;
-  int nseg_y, nseg_z;
-};
-
-static bool geom(const ufvc_ctx* c, int H, int W, Geom& g) {
-  if (H < 16 || W < 16 || (H & 7) || (W & 7) || H > 65535 || W > 65535) return false;
-  g.Hp = (H + 15) / 16 * 16;
-  g.Wp = (W + 15) / 16 * 16;
-  g.h = g.Hp / 8;
-  g.w = g.Wp / 8;
-  g.hz = (g.h + 1) / 2;
-  g.wz = (g.w + 1) / 2;
-  g.ny = (long)g.h * g.w * c->cfg.C;
-  g.nz = (long)g.hz * g.wz * ZC;
-  g.nseg_y = nseg_of(g.ny, c->cfg.seg_log2);
-  g.nseg_z = nseg_of(g.nz, c->cfg.seg_log2_z);
-  return true;
-}
-
-static ConvArgs conv_args(int Hin, int Win, int Hout, int Wout, const Layer& L) {
-  ConvArgs a{};
-  a.Hin = Hin;
-  a.Win = Win;
-  a.Hout = Hout;
-  a.Wout = Wout;
-  a.cin = L.cin;
-  a.cout = L.cout;
-  a.wpk = L.w;
-  a.w_gstride = L.gstride;
-  return a;
-}
-
-// Tile configuration: the widest channel tile that divides the layer's outputs.
 static int cfg_for(int cout) { return cout % 128 == 0 ? 0 : (cout % 64 == 0 ? 4 : 1); }
 
 static hipError_t run_synthesis(ufvc_ctx* c, const Geom& g, const uint8_t* sym, const float* mu,

@@ -51,6 +51,11 @@ struct ConvArgs {
 hipError_t launch_conv(int prec, int loader, int store, int stride, int cfg,
                        const ConvArgs& a, int groups, hipStream_t s);
 
+// Batched form: one launch over nwork work items (problem index, tile,
+// first output channel, group) of the problems in descs (device memory).
+hipError_t launch_conv_batch(int prec, int loader, int store, int stride, int cfg,
+                             const ConvArgs* descs, const int4* work, int nwork, hipStream_t s);
+
 // Tile configurations: output rows x cols per workgroup and channel tile.
 struct TileCfg { int th, tw, bn; };
 int conv_num_cfgs();
@@ -130,6 +135,78 @@ struct DecStream {
 hipError_t launch_rans_decode(const Tables& t, const uint8_t* bs, const uint32_t* seg_off,
                               const uint32_t* seg_len, DecStream d, uint32_t* status,
                               hipStream_t s);
+
+// ---- Batched (descriptor-driven) forms: one launch for many chunks ----
+// Problem descriptors live in device memory; the same kernels run with
+// either inline arguments (one chunk) or these arrays (a batch).
+
+// Entropy-parameter epilogue of one chunk (see launch_params_epilogue).
+struct EpiDesc {
+  const float* P;
+  const float* y;    // null in the decoder
+  uint8_t* idx;
+  uint8_t* sym;
+  long npos;
+  int C;
+  int pad;
+};
+constexpr int EPI_BLOCK_ELEMS = 4096;  // elements per block of the batched epilogue
+
+// One rANS segment to encode.
+struct EncSeg {
+  const uint8_t* sym;   // first symbol of the segment (CODER_PAD readable past its stream)
+  const uint8_t* idx;   // first table row of the segment, null: fixed_row for all
+  uint8_t* slot;        // scratch: 128 state bytes + 2 * cap bytes of words
+  SegInfo* info;        // receives the segment's word range
+  uint32_t nsym;
+  uint32_t cap;         // word capacity of the slot (>= nsym)
+  uint32_t fixed_row;
+  uint32_t pad;
+};
+
+// One rANS segment to decode (offsets come from the parse of its chunk).
+struct DecSeg {
+  const uint8_t* bs;         // the chunk's stream
+  const uint32_t* seg_off;   // this segment's entry of the parse output
+  const uint32_t* seg_len;
+  const uint8_t* idx;        // first table row of the segment, null: fixed_row
+  uint8_t* out;              // first decoded symbol of the segment
+  uint32_t* status;
+  unsigned long long len;    // bytes of the chunk's stream
+  uint32_t nsym;
+  uint32_t fixed_row;
+};
+
+// Container assembly of one chunk.
+struct CompDesc {
+  const uint8_t* scratch_z;  // first z slot
+  const uint8_t* scratch_y;  // first y slot
+  unsigned long long slot_z, slot_y;
+  const SegInfo* info;       // z segments then y segments
+  int n_seg_z, n_seg_y, with_header, pad;
+  HeaderFields hf;
+  uint8_t* out;
+  unsigned long long capacity;
+  unsigned long long* result;
+};
+
+// Stream validation of one chunk.
+struct ParseDesc {
+  const uint8_t* bs;
+  unsigned long long len;
+  int with_header, n_seg_z, n_seg_y, pad;
+  HeaderFields ex;
+  uint32_t* seg_off;
+  uint32_t* seg_len;
+  uint32_t* status;
+};
+
+hipError_t launch_params_epilogue_batch(const EpiDesc* d, const int2* work, int nwork,
+                                        const float* thr, hipStream_t s);
+hipError_t launch_rans_encode_batch(const Tables& t, const EncSeg* segs, int nsegs, hipStream_t s);
+hipError_t launch_compact_batch(const CompDesc* d, const int2* map, int nblocks, hipStream_t s);
+hipError_t launch_parse_batch(const ParseDesc* d, int nchunks, hipStream_t s);
+hipError_t launch_rans_decode_batch(const Tables& t, const DecSeg* segs, int nsegs, hipStream_t s);
 
 // Device status bits.
 constexpr uint32_t ST_BAD_HEADER = 1u;

@@ -178,7 +178,8 @@ constexpr int conv_lds_bytes() {
 
 template <int PREC, int LD, int ST, int STRIDE, int TH, int TW, int WM, int WN, int FM, int FN>
 __global__ void __launch_bounds__(WM * WN * 64)
-conv3x3_kernel(ConvArgs a) {
+conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __restrict__ work,
+               int nwork) {
   constexpr int NT = WM * WN * 64;
   constexpr int BM = TH * TW;
   static_assert(BM == WM * FM * 32, "tile rows must match the wave grid");
@@ -202,17 +203,34 @@ conv3x3_kernel(ConvArgs a) {
   const int wave = tid >> 6;
   const int wm = wave / WN;
   const int wn = wave - wm * WN;
-  const int grp = blockIdx.z;
   // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-  // contiguous band of spatial tiles so neighbouring halos share its L2.
+  // contiguous band of tiles (or work items) so neighbouring halos and shared
+  // weights stay in its L2.  A batched launch reads its problem, tile, channel
+  // tile and group from a work list; a single launch derives them from the
+  // grid.
+  ConvArgs a;
+  int tile, n0, grp;
+  if (descs) {
+    const int per = (nwork + 7) >> 3;
+    const int wi = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (wi >= nwork) return;
+    const int4 w = work[wi];
+    a = descs[w.x];
+    tile = w.y;
+    n0 = w.z;
+    grp = w.w;
+  } else {
+    a = a0;
+    const int nt = ((a.Hout + TH - 1) / TH) * ((a.Wout + TW - 1) / TW);
+    const int per = (nt + 7) >> 3;
+    tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= nt) return;
+    n0 = blockIdx.y * BN;
+    grp = blockIdx.z;
+  }
   const int tiles_x = (a.Wout + TW - 1) / TW;
-  const int ntiles = ((a.Hout + TH - 1) / TH) * tiles_x;
-  const int per_xcd = (ntiles + 7) >> 3;
-  const int tile = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (tile >= ntiles) return;
   const int oy0 = (tile / tiles_x) * TH;
   const int ox0 = (tile % tiles_x) * TW;
-  const int n0 = blockIdx.y * BN;
   const int iy0 = STRIDE * oy0 - 1;
   const int ix0 = STRIDE * ox0 - 1;
   const int nslices = a.cin / E;
@@ -356,8 +374,11 @@ static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 1
 int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 TileCfg conv_cfg(int c) { return kCfgs[c]; }
 
+// descs == nullptr: one problem `a` over a (tiles, cout / BN, groups) grid.
+// Otherwise: nwork items of the work list over the problems in descs.
 template <int PREC, int LD, int ST, int STRIDE, int TH, int TW, int WM, int WN, int FM, int FN>
-static hipError_t run_conv(const ConvArgs& a, int groups, hipStream_t s) {
+static hipError_t run_conv(const ConvArgs& a, int groups, const ConvArgs* descs, const int4* work,
+                           int nwork, hipStream_t s) {
   constexpr int BN = WN * FN * 32;
   constexpr int lds = conv_lds_bytes<STRIDE, TH, TW, BN>();
   auto kern = conv3x3_kernel<PREC, LD, ST, STRIDE, TH, TW, WM, WN, FM, FN>;
@@ -368,33 +389,40 @@ static hipError_t run_conv(const ConvArgs& a, int groups, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  if (a.cout % BN || a.cin % PT<PREC>::E) return hipErrorInvalidValue;
-  const int tiles = ((a.Hout + TH - 1) / TH) * ((a.Wout + TW - 1) / TW);
-  dim3 grid(((tiles + 7) / 8) * 8, a.cout / BN, groups);
-  hipLaunchKernelGGL(kern, grid, dim3(WM * WN * 64), lds, s, a);
+  dim3 grid;
+  if (descs) {
+    if (nwork <= 0) return hipSuccess;
+    grid = dim3(((nwork + 7) / 8) * 8, 1, 1);
+  } else {
+    if (a.cout % BN || a.cin % PT<PREC>::E) return hipErrorInvalidValue;
+    const int tiles = ((a.Hout + TH - 1) / TH) * ((a.Wout + TW - 1) / TW);
+    grid = dim3(((tiles + 7) / 8) * 8, a.cout / BN, groups);
+  }
+  hipLaunchKernelGGL(kern, grid, dim3(WM * WN * 64), lds, s, a, descs, work, nwork);
   return hipGetLastError();
 }
 
 template <int PREC, int LD, int ST, int STRIDE>
-static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, hipStream_t s) {
+static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs* d,
+                          const int4* w, int nw, hipStream_t s) {
   switch (cfg) {
-    case 0: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 2>(a, groups, s);
-    case 1: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 4, 1, 1, 1>(a, groups, s);
-    case 2: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 3>(a, groups, s);
-    case 3: return run_conv<PREC, LD, ST, STRIDE, 4, 16, 2, 2, 1, 2>(a, groups, s);
-    case 4: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 1>(a, groups, s);
-    case 5: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 2>(a, groups, s);
-    case 6: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 3>(a, groups, s);
-    case 7: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 1>(a, groups, s);
+    case 0: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 2>(a, groups, d, w, nw, s);
+    case 1: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 4, 1, 1, 1>(a, groups, d, w, nw, s);
+    case 2: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 3>(a, groups, d, w, nw, s);
+    case 3: return run_conv<PREC, LD, ST, STRIDE, 4, 16, 2, 2, 1, 2>(a, groups, d, w, nw, s);
+    case 4: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 1>(a, groups, d, w, nw, s);
+    case 5: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 2>(a, groups, d, w, nw, s);
+    case 6: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 3>(a, groups, d, w, nw, s);
+    case 7: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 1>(a, groups, d, w, nw, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_conv(int prec, int loader, int store, int stride, int cfg,
-                       const ConvArgs& a, int groups, hipStream_t s) {
+static hipError_t dispatch(int prec, int loader, int store, int stride, int cfg, const ConvArgs& a,
+                           int groups, const ConvArgs* d, const int4* w, int nw, hipStream_t s) {
 #define UFVC_CONV(P, L, S, STR)                                         \
   if (prec == P && loader == L && store == S && stride == STR)          \
-    return run_cfg<P, L, S, STR>(cfg, a, groups, s);
+    return run_cfg<P, L, S, STR>(cfg, a, groups, d, w, nw, s);
   // bf16 analysis / synthesis
   UFVC_CONV(P_BF16, LD_UNSHUFFLE, ST_BF16, 1)
   UFVC_CONV(P_BF16, LD_NHWC, ST_BF16, 1)
@@ -411,6 +439,17 @@ hipError_t launch_conv(int prec, int loader, int store, int stride, int cfg,
   UFVC_CONV(P_F32, LD_NHWC, ST_ZSYM, 2)
 #undef UFVC_CONV
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_conv(int prec, int loader, int store, int stride, int cfg,
+                       const ConvArgs& a, int groups, hipStream_t s) {
+  return dispatch(prec, loader, store, stride, cfg, a, groups, nullptr, nullptr, 0, s);
+}
+
+hipError_t launch_conv_batch(int prec, int loader, int store, int stride, int cfg,
+                             const ConvArgs* descs, const int4* work, int nwork, hipStream_t s) {
+  ConvArgs none{};
+  return dispatch(prec, loader, store, stride, cfg, none, 1, descs, work, nwork, s);
 }
 
 }  // namespace ufvc

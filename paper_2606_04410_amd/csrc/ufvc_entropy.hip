@@ -93,6 +93,27 @@ hipError_t launch_build_tables(const Tables& t, hipStream_t s) {
 }
 
 // ------------------------------------------------------ params epilogue ----
+__device__ __forceinline__ void params_element(const float* __restrict__ P, const float* __restrict__ y,
+                                               const float* s_thr, uint8_t* __restrict__ idx,
+                                               uint8_t* __restrict__ sym, int C, long e) {
+  const long pos = e / C;
+  const int c = (int)(e - pos * C);
+  const float xs = P[pos * 2 * C + C + c];
+  const float sp = fmaxf(xs, 0.f) + log1pf(expf(-fabsf(xs)));
+  const float sigma = fminf(fmaxf(sp, 0.11f), 64.f);
+  // number of thresholds <= sigma (thr[63] = +inf)
+  int k = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1)
+    if (s_thr[k + step - 1] <= sigma) k += step;
+  idx[e] = (uint8_t)k;
+  if (y) {
+    const float mu = P[pos * 2 * C + c];
+    const float r = fminf(fmaxf(rintf(y[e] - mu), -32.f), 32.f);
+    sym[e] = (uint8_t)((int)r + 32);
+  }
+}
+
 __global__ void __launch_bounds__(256)
 params_epilogue_kernel(const float* __restrict__ P, const float* __restrict__ y,
                        const float* __restrict__ thr, uint8_t* __restrict__ idx,
@@ -102,24 +123,23 @@ params_epilogue_kernel(const float* __restrict__ P, const float* __restrict__ y,
   __syncthreads();
   const long total = npos * C;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (long)gridDim.x * blockDim.x) {
-    const long pos = e / C;
-    const int c = (int)(e - pos * C);
-    const float xs = P[pos * 2 * C + C + c];
-    const float sp = fmaxf(xs, 0.f) + log1pf(expf(-fabsf(xs)));
-    const float sigma = fminf(fmaxf(sp, 0.11f), 64.f);
-    // number of thresholds <= sigma (thr[63] = +inf)
-    int k = 0;
-#pragma unroll
-    for (int step = 32; step > 0; step >>= 1)
-      if (s_thr[k + step - 1] <= sigma) k += step;
-    idx[e] = (uint8_t)k;
-    if (y) {
-      const float mu = P[pos * 2 * C + c];
-      const float r = fminf(fmaxf(rintf(y[e] - mu), -32.f), 32.f);
-      sym[e] = (uint8_t)((int)r + 32);
-    }
-  }
+       e += (long)gridDim.x * blockDim.x)
+    params_element(P, y, s_thr, idx, sym, C, e);
+}
+
+__global__ void __launch_bounds__(256)
+params_epilogue_batch_kernel(const EpiDesc* __restrict__ descs, const int2* __restrict__ work,
+                             const float* __restrict__ thr) {
+  __shared__ float s_thr[64];
+  if (threadIdx.x < 64) s_thr[threadIdx.x] = thr[threadIdx.x];
+  __syncthreads();
+  const int2 w = work[blockIdx.x];
+  const EpiDesc d = descs[w.x];
+  const long total = d.npos * d.C;
+  const long e0 = (long)w.y * EPI_BLOCK_ELEMS;
+  const long e1 = min(e0 + EPI_BLOCK_ELEMS, total);
+  for (long e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+    params_element(d.P, d.y, s_thr, d.idx, d.sym, d.C, e);
 }
 
 hipError_t launch_params_epilogue(const float* P, const float* y, const float* thr,
@@ -131,6 +151,13 @@ hipError_t launch_params_epilogue(const float* P, const float* y, const float* t
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(params_epilogue_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
                      P, y, thr, idx, sym, npos, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_params_epilogue_batch(const EpiDesc* d, const int2* work, int nwork,
+                                        const float* thr, hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  hipLaunchKernelGGL(params_epilogue_batch_kernel, dim3(nwork), dim3(256), 0, s, d, work, thr);
   return hipGetLastError();
 }
 
@@ -162,9 +189,31 @@ __device__ __forceinline__ void load32(const uint8_t* __restrict__ p, long pos, 
   b = *reinterpret_cast<const uint4*>(p + pos + 16);
 }
 
+// Segment `seg` of the (z, y) stream pair of one chunk as a descriptor.
+__device__ __forceinline__ EncSeg enc_seg_of(const EncStream& z, const EncStream& y,
+                                             uint8_t* scratch, size_t slot_z, size_t slot_y,
+                                             SegInfo* info, int seg) {
+  const bool isz = seg < z.n_seg;
+  const int si = isz ? seg : seg - z.n_seg;
+  const EncStream& st = isz ? z : y;
+  const long base = (long)si << st.seg_log2;
+  EncSeg e;
+  e.sym = st.sym + base;
+  e.idx = st.idx ? st.idx + base : nullptr;
+  e.slot = isz ? scratch + (size_t)si * slot_z
+               : scratch + (size_t)z.n_seg * slot_z + (size_t)si * slot_y;
+  e.info = info + seg;
+  e.nsym = (uint32_t)min((long)1 << st.seg_log2, st.n - base);
+  e.cap = 1u << st.seg_log2;
+  e.fixed_row = (uint32_t)st.fixed_row;
+  e.pad = 0;
+  return e;
+}
+
 __global__ void __launch_bounds__(64)
 rans_encode_kernel(Tables t, EncStream z, EncStream y, uint8_t* __restrict__ scratch,
-                   size_t slot_z, size_t slot_y, SegInfo* __restrict__ info) {
+                   size_t slot_z, size_t slot_y, SegInfo* __restrict__ info,
+                   const EncSeg* __restrict__ segd, int nsegd) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   uint32_t* s_fc = reinterpret_cast<uint32_t*>(lds);
   uint32_t* s_mg = s_fc + NSCALES * NSYM;
@@ -179,34 +228,30 @@ rans_encode_kernel(Tables t, EncStream z, EncStream y, uint8_t* __restrict__ scr
   const int half = threadIdx.x >> 5;
   const int lane = threadIdx.x & 31;
   const int shsel = threadIdx.x & 32;
-  const int nseg = z.n_seg + y.n_seg;
+  const int nseg = segd ? nsegd : z.n_seg + y.n_seg;
   const int seg0 = blockIdx.x * 2;
   const int seg = seg0 + half;
   const bool active = seg < nseg;
-  auto seg_n = [&](int sg) -> int {
-    const bool iz = sg < z.n_seg;
-    const int si = iz ? sg : sg - z.n_seg;
-    const int sl = iz ? z.seg_log2 : y.seg_log2;
-    const long n = iz ? z.n : y.n;
-    return (int)min((long)1 << sl, n - ((long)si << sl));
-  };
+  // an inactive half mirrors the pair's first segment with no symbols, so its
+  // unconditional prefetches stay in bounds
+  EncSeg me = segd ? segd[active ? seg : seg0]
+                   : enc_seg_of(z, y, scratch, slot_z, slot_y, info, active ? seg : seg0);
+  const uint32_t n_other = segd ? segd[seg0 + 1 < nseg ? seg0 + 1 : seg0].nsym
+                                : enc_seg_of(z, y, scratch, slot_z, slot_y, info,
+                                             seg0 + 1 < nseg ? seg0 + 1 : seg0).nsym;
+  const uint32_t n_first = segd ? segd[seg0].nsym
+                                : enc_seg_of(z, y, scratch, slot_z, slot_y, info, seg0).nsym;
   // both halves run the larger epoch count of the pair, so barriers stay uniform
-  const int n0 = seg_n(seg0);
-  const int n1 = seg0 + 1 < nseg ? seg_n(seg0 + 1) : 0;
-  const int nep = (max(n0, n1) + EPB - 1) / EPB;
-  const bool isz = seg < z.n_seg;
-  const int sidx = isz ? seg : seg - z.n_seg;
-  const uint8_t* __restrict__ sym = isz ? z.sym : y.sym;
-  const uint8_t* __restrict__ idxp = isz ? z.idx : y.idx;
-  const int fixed = isz ? z.fixed_row : y.fixed_row;
-  const int sl = isz ? z.seg_log2 : y.seg_log2;
-  const long base = active ? (long)sidx << sl : 0;
-  const int nsym = active ? seg_n(seg) : 0;
-  uint8_t* slot = isz ? scratch + (size_t)sidx * slot_z
-                      : scratch + (size_t)z.n_seg * slot_z + (size_t)sidx * slot_y;
+  const int nep = (int)((max(n_first, n_other) + EPB - 1) / EPB);
+  const uint8_t* __restrict__ sym = me.sym;
+  const uint8_t* __restrict__ idxp = me.idx;
+  const int fixed = (int)me.fixed_row;
+  const long base = 0;
+  const int nsym = active ? (int)me.nsym : 0;
+  uint8_t* slot = me.slot;
   uint16_t* __restrict__ words = reinterpret_cast<uint16_t*>(slot + SEG_STATE_BYTES);
   EncSegLds& L = segs[half];
-  const uint32_t cap = 1u << sl;
+  const uint32_t cap = me.cap;
   uint32_t cursor = cap;
   uint32_t x = RANS_L;
 
@@ -283,7 +328,7 @@ rans_encode_kernel(Tables t, EncStream z, EncStream y, uint8_t* __restrict__ scr
       SegInfo si;
       si.start_word = cursor;
       si.nwords = cap - cursor;
-      info[seg] = si;
+      *me.info = si;
     }
   }
 }
@@ -301,7 +346,22 @@ hipError_t launch_rans_encode(const Tables& t, EncStream z, EncStream y, uint8_t
     attr = true;
   }
   hipLaunchKernelGGL(rans_encode_kernel, dim3((nseg + 1) / 2), dim3(64), ENC_LDS_BYTES, s, t, z, y,
-                     scratch, slot_bytes_z, slot_bytes_y, info);
+                     scratch, slot_bytes_z, slot_bytes_y, info, nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_rans_encode_batch(const Tables& t, const EncSeg* segs, int nsegs, hipStream_t s) {
+  if (nsegs <= 0) return hipSuccess;
+  EncStream none{nullptr, nullptr, 0, 0, 5, 0};
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rans_encode_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)ENC_LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(rans_encode_kernel, dim3((nsegs + 1) / 2), dim3(64), ENC_LDS_BYTES, s, t, none,
+                     none, nullptr, 0, 0, nullptr, segs, nsegs);
   return hipGetLastError();
 }
 
@@ -323,14 +383,21 @@ __device__ unsigned long long block_sum(unsigned long long v, unsigned long long
 }
 
 __global__ void __launch_bounds__(256)
-compact_kernel(const uint8_t* __restrict__ scratch, size_t slot_z, size_t slot_y,
-               const SegInfo* __restrict__ info, int n_seg_z, int n_seg_y, int with_header,
-               HeaderFields hf, uint8_t* __restrict__ out, size_t capacity,
-               unsigned long long* __restrict__ result) {
+compact_kernel(CompDesc d0, const CompDesc* __restrict__ descs, const int2* __restrict__ map) {
   __shared__ unsigned long long red[8];
-  const int nseg = n_seg_z + n_seg_y;
-  const int b = blockIdx.x;
-  const size_t h0 = (with_header ? 28u : 0u) + 4u * (size_t)nseg;
+  int b = blockIdx.x;
+  CompDesc d;
+  if (descs) {
+    const int2 m = map[blockIdx.x];
+    d = descs[m.x];
+    b = m.y;
+  } else {
+    d = d0;
+  }
+  const SegInfo* __restrict__ info = d.info;
+  const int n_seg_z = d.n_seg_z;
+  const int nseg = d.n_seg_z + d.n_seg_y;
+  const size_t h0 = (d.with_header ? 28u : 0u) + 4u * (size_t)nseg;
   unsigned long long before = 0, all = 0;
   for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
     const unsigned long long sb = seg_bytes_of(info[i]);
@@ -340,10 +407,12 @@ compact_kernel(const uint8_t* __restrict__ scratch, size_t slot_z, size_t slot_y
   before = block_sum(before, red);
   all = block_sum(all, red);
   const unsigned long long total = h0 + all;
-  if (b == 0 && threadIdx.x == 0) result[0] = total;
-  if (total > capacity) return;
+  if (b == 0 && threadIdx.x == 0) d.result[0] = total;
+  if (total > d.capacity) return;
+  uint8_t* __restrict__ out = d.out;
   if (b == 0) {
-    if (with_header && threadIdx.x == 0) {
+    if (d.with_header && threadIdx.x == 0) {
+      const HeaderFields hf = d.hf;
       uint32_t* h = reinterpret_cast<uint32_t*>(out);
       h[0] = 0x31564655u;  // "UFV1"
       h[1] = (uint32_t)hf.T | ((uint32_t)hf.C << 16);
@@ -351,15 +420,15 @@ compact_kernel(const uint8_t* __restrict__ scratch, size_t slot_z, size_t slot_y
       h[3] = (uint32_t)hf.seg_log2 | ((uint32_t)hf.seg_log2_z << 8) | ((uint32_t)hf.k_z << 16);
       h[4] = hf.model_tag;
       h[5] = (uint32_t)n_seg_z;
-      h[6] = (uint32_t)n_seg_y;
+      h[6] = (uint32_t)d.n_seg_y;
     }
-    uint32_t* tab = reinterpret_cast<uint32_t*>(out + (with_header ? 28 : 0));
+    uint32_t* tab = reinterpret_cast<uint32_t*>(out + (d.with_header ? 28 : 0));
     for (int i = threadIdx.x; i < nseg; i += blockDim.x) tab[i] = seg_bytes_of(info[i]);
   }
   if (b >= nseg) return;
   const SegInfo si = info[b];
-  const uint8_t* src = b < n_seg_z ? scratch + (size_t)b * slot_z
-                                   : scratch + (size_t)n_seg_z * slot_z + (size_t)(b - n_seg_z) * slot_y;
+  const uint8_t* src = b < n_seg_z ? d.scratch_z + (size_t)b * d.slot_z
+                                   : d.scratch_y + (size_t)(b - n_seg_z) * d.slot_y;
   uint8_t* dst = out + h0 + before;
   if (threadIdx.x < LANES)
     reinterpret_cast<uint32_t*>(dst)[threadIdx.x] = reinterpret_cast<const uint32_t*>(src)[threadIdx.x];
@@ -374,19 +443,45 @@ hipError_t launch_compact(const uint8_t* scratch, size_t slot_bytes_z, size_t sl
                           HeaderFields hf, uint8_t* out, size_t capacity,
                           unsigned long long* result, hipStream_t s) {
   const int nseg = n_seg_z + n_seg_y;
-  hipLaunchKernelGGL(compact_kernel, dim3(nseg > 0 ? nseg : 1), dim3(256), 0, s, scratch,
-                     slot_bytes_z, slot_bytes_y, info, n_seg_z, n_seg_y, with_header, hf, out,
-                     capacity, result);
+  CompDesc d{};
+  d.scratch_z = scratch;
+  d.scratch_y = scratch + (size_t)n_seg_z * slot_bytes_z;
+  d.slot_z = slot_bytes_z;
+  d.slot_y = slot_bytes_y;
+  d.info = info;
+  d.n_seg_z = n_seg_z;
+  d.n_seg_y = n_seg_y;
+  d.with_header = with_header;
+  d.hf = hf;
+  d.out = out;
+  d.capacity = capacity;
+  d.result = result;
+  hipLaunchKernelGGL(compact_kernel, dim3(nseg > 0 ? nseg : 1), dim3(256), 0, s, d,
+                     (const CompDesc*)nullptr, (const int2*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_batch(const CompDesc* d, const int2* map, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  CompDesc none{};
+  hipLaunchKernelGGL(compact_kernel, dim3(nblocks), dim3(256), 0, s, none, d, map);
   return hipGetLastError();
 }
 
 // --------------------------------------------------------------- parse ----
 __global__ void __launch_bounds__(256)
-parse_kernel(const uint8_t* __restrict__ bs, size_t len, int with_header, HeaderFields ex,
-             int n_seg_z, int n_seg_y, uint32_t* __restrict__ seg_off,
-             uint32_t* __restrict__ seg_len, uint32_t* __restrict__ status) {
+parse_kernel(ParseDesc d0, const ParseDesc* __restrict__ descs) {
   __shared__ unsigned long long red[8];
   __shared__ int s_bad;
+  const ParseDesc d = descs ? descs[blockIdx.x] : d0;
+  const uint8_t* __restrict__ bs = d.bs;
+  const size_t len = (size_t)d.len;
+  const int with_header = d.with_header;
+  const HeaderFields ex = d.ex;
+  const int n_seg_z = d.n_seg_z, n_seg_y = d.n_seg_y;
+  uint32_t* __restrict__ seg_off = d.seg_off;
+  uint32_t* __restrict__ seg_len = d.seg_len;
+  uint32_t* __restrict__ status = d.status;
   const int nseg = n_seg_z + n_seg_y;
   const size_t h0 = (with_header ? 28u : 0u) + 4u * (size_t)nseg;
   if (threadIdx.x == 0) {
@@ -449,8 +544,24 @@ parse_kernel(const uint8_t* __restrict__ bs, size_t len, int with_header, Header
 hipError_t launch_parse(const uint8_t* bs, size_t len, int with_header, HeaderFields expect,
                         int n_seg_z, int n_seg_y, uint32_t* seg_off, uint32_t* seg_len,
                         uint32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(parse_kernel, dim3(1), dim3(256), 0, s, bs, len, with_header, expect,
-                     n_seg_z, n_seg_y, seg_off, seg_len, status);
+  ParseDesc d{};
+  d.bs = bs;
+  d.len = len;
+  d.with_header = with_header;
+  d.n_seg_z = n_seg_z;
+  d.n_seg_y = n_seg_y;
+  d.ex = expect;
+  d.seg_off = seg_off;
+  d.seg_len = seg_len;
+  d.status = status;
+  hipLaunchKernelGGL(parse_kernel, dim3(1), dim3(256), 0, s, d, (const ParseDesc*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_parse_batch(const ParseDesc* d, int nchunks, hipStream_t s) {
+  if (nchunks <= 0) return hipSuccess;
+  ParseDesc none{};
+  hipLaunchKernelGGL(parse_kernel, dim3(nchunks), dim3(256), 0, s, none, d);
   return hipGetLastError();
 }
 
@@ -475,9 +586,28 @@ struct DecSegLds {
 constexpr size_t DEC_TAB_BYTES = NSCALES * NSYM * 4 + NSCALES * LUTB + NSCALES;
 constexpr size_t DEC_LDS_BYTES = DEC_TAB_BYTES + 2 * sizeof(DecSegLds);
 
+// Segment `si` of one decoded stream as a descriptor.
+__device__ __forceinline__ DecSeg dec_seg_of(const uint8_t* bs, const uint32_t* seg_off,
+                                             const uint32_t* seg_len, const DecStream& d,
+                                             uint32_t* status, int si) {
+  const long base = (long)si << d.seg_log2;
+  DecSeg e;
+  e.bs = bs;
+  e.seg_off = seg_off + d.seg_base + si;
+  e.seg_len = seg_len + d.seg_base + si;
+  e.idx = d.idx ? d.idx + base : nullptr;
+  e.out = d.sym_out + base;
+  e.status = status;
+  e.len = d.len;
+  e.nsym = (uint32_t)min((long)1 << d.seg_log2, d.n - base);
+  e.fixed_row = (uint32_t)d.fixed_row;
+  return e;
+}
+
 __global__ void __launch_bounds__(64)
-rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs, const uint32_t* __restrict__ seg_off,
-                   const uint32_t* __restrict__ seg_len, DecStream d, uint32_t* __restrict__ status) {
+rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __restrict__ seg_off0,
+                   const uint32_t* __restrict__ seg_len0, DecStream d, uint32_t* __restrict__ status0,
+                   const DecSeg* __restrict__ segd, int nsegd) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   uint32_t* s_fc = reinterpret_cast<uint32_t*>(lds);
   uint8_t* s_lut = lds + NSCALES * NSYM * 4;
@@ -491,26 +621,35 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs, const uint32_t* __r
   const int half = threadIdx.x >> 5;
   const int lane = threadIdx.x & 31;
   const int shsel = threadIdx.x & 32;
+  const int nseg = segd ? nsegd : d.n_seg;
   const int seg0 = blockIdx.x * 2;
   const int sidx = seg0 + half;
-  auto seg_n = [&](int si) -> int {
-    return (int)min((long)1 << d.seg_log2, d.n - ((long)si << d.seg_log2));
-  };
-  const int nep = (seg_n(seg0) + EPB - 1) / EPB;  // the first segment of a pair is the larger
-  const uint32_t off = sidx < d.n_seg ? seg_off[d.seg_base + sidx] : 0xFFFFFFFFu;
+  const bool active = sidx < nseg;
+  // an inactive half mirrors the pair's first segment with no symbols
+  const DecSeg me = segd ? segd[active ? sidx : seg0]
+                         : dec_seg_of(bs0, seg_off0, seg_len0, d, status0, active ? sidx : seg0);
+  const uint32_t n_first = segd ? segd[seg0].nsym
+                                : dec_seg_of(bs0, seg_off0, seg_len0, d, status0, seg0).nsym;
+  const int o1 = seg0 + 1 < nseg ? seg0 + 1 : seg0;
+  const uint32_t n_other = segd ? segd[o1].nsym
+                                : dec_seg_of(bs0, seg_off0, seg_len0, d, status0, o1).nsym;
+  // both halves run the larger epoch count of the pair, so barriers stay uniform
+  const int nep = (int)((max(n_first, n_other) + EPB - 1) / EPB);
+  const uint8_t* __restrict__ bs = me.bs;
+  uint32_t* __restrict__ status = me.status;
+  const uint32_t off = active ? *me.seg_off : 0xFFFFFFFFu;
   const bool usable = off != 0xFFFFFFFFu;
-  const bool active = sidx < d.n_seg;
-  const long base = active ? (long)sidx << d.seg_log2 : 0;
-  const int nsym = active ? seg_n(sidx) : 0;
-  const uint32_t slen = usable ? seg_len[d.seg_base + sidx] : (uint32_t)SEG_STATE_BYTES;
+  const int nsym = active ? (int)me.nsym : 0;
+  const uint32_t slen = usable ? *me.seg_len : (uint32_t)SEG_STATE_BYTES;
   const uint32_t nw = (slen - SEG_STATE_BYTES) >> 1;    // words including a pad word
   const uint32_t ndw = nw >> 1;                          // dwords of the word area
+  (void)ndw;
   const uint32_t* __restrict__ wdw =
       reinterpret_cast<const uint32_t*>(bs + (usable ? off : 0) + SEG_STATE_BYTES);
   // last readable dword of the stream, for clamped background fetches
-  const long last_dw = ((long)(d.len & ~(size_t)3) - 4) / 4;
+  const long last_dw = ((long)(me.len & ~3ull) - 4) / 4;
   const long wdw0 = ((usable ? (long)off : 0) + SEG_STATE_BYTES) / 4;
-  uint8_t* __restrict__ out = d.sym_out + base;
+  uint8_t* __restrict__ out = me.out;
   DecSegLds& L = segs[half];
 
   uint32_t x = usable ? reinterpret_cast<const uint32_t*>(bs + off)[lane] : RANS_L;
@@ -542,12 +681,12 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs, const uint32_t* __r
     }
   };
   uint4 pi0, pi1;
-  const uint32_t f4 = (uint32_t)d.fixed_row * 0x01010101u;
+  const uint32_t f4 = me.fixed_row * 0x01010101u;
   const int nep_own = (nsym + EPB - 1) / EPB;
   auto fetch_idx = [&](int ep) {
-    if (d.idx) {
+    if (me.idx) {
       // epochs past this segment's own count re-read epoch 0 (in bounds)
-      load32(d.idx + base, (long)(ep < nep_own ? ep : 0) * EPB + lane * 32, pi0, pi1);
+      load32(me.idx, (long)(ep < nep_own ? ep : 0) * EPB + lane * 32, pi0, pi1);
     } else {
       pi0 = make_uint4(f4, f4, f4, f4);
       pi1 = pi0;
@@ -648,7 +787,22 @@ hipError_t launch_rans_decode(const Tables& t, const uint8_t* bs, const uint32_t
     attr = true;
   }
   hipLaunchKernelGGL(rans_decode_kernel, dim3((d.n_seg + 1) / 2), dim3(64), DEC_LDS_BYTES, s, t, bs,
-                     seg_off, seg_len, d, status);
+                     seg_off, seg_len, d, status, nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_rans_decode_batch(const Tables& t, const DecSeg* segs, int nsegs, hipStream_t s) {
+  if (nsegs <= 0) return hipSuccess;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rans_decode_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)DEC_LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  DecStream none{nullptr, 0, 0, 5, 0, 0, nullptr, 0};
+  hipLaunchKernelGGL(rans_decode_kernel, dim3((nsegs + 1) / 2), dim3(64), DEC_LDS_BYTES, s, t,
+                     nullptr, nullptr, nullptr, none, nullptr, segs, nsegs);
   return hipGetLastError();
 }
 

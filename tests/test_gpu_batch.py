@@ -1,0 +1,71 @@
+"""Batched launches: each chunk's result is the same alone and in a batch of
+uneven chunks (two models, T = 4 and T = 8), and graph-captured decode
+replays equal eager decode."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from synthetic import stand_in_weights, video_chunk  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_batch_equals_single_and_graph_equals_eager(prec):
+    import paper_2606_04410_amd as u
+    C = 64
+    models = [u.Codec(4, C, stand_in_weights(4, C), precision=prec, seg_log2=11, seg_log2_z=9,
+                      model_tag=41, autotune=True),
+              u.Codec(8, C, stand_in_weights(8, C), precision=prec, seg_log2=11, seg_log2_z=9,
+                      model_tag=81, autotune=True)]
+    shapes = [(0, 64, 64), (1, 96, 128), (0, 136, 80), (1, 64, 64), (0, 48, 200)]
+    say(f"batch {prec}: {shapes}")
+    frames = [torch.from_numpy(video_chunk(models[m].T, H, W, 3, seed=7, chunk_id=i)).cuda()
+              for i, (m, H, W) in enumerate(shapes)]
+    # single-chunk reference
+    ref_bs, ref_fr = [], []
+    for (m, H, W), fr in zip(shapes, frames):
+        bs, n = models[m].encode(fr)
+        ref_bs.append(bs[:n].cpu().numpy().tobytes())
+        ref_fr.append(models[m].decode(bs, n, H, W).cpu().numpy())
+    batch = u.Batch(models)
+    outs = [torch.empty(models[m].max_bitstream_bytes(H, W), dtype=torch.uint8, device="cuda")
+            for (m, H, W) in shapes]
+    lens = batch.encode([(m, fr, o) for (m, _, _), fr, o in zip(shapes, frames, outs)])
+    for i in range(len(shapes)):
+        assert outs[i][:lens[i]].cpu().numpy().tobytes() == ref_bs[i], i
+    rec = [torch.empty((models[m].T, 3, H, W), dtype=torch.float32, device="cuda")
+           for (m, H, W) in shapes]
+    items = [(m, o, n, H, W, r) for (m, H, W), o, n, r in zip(shapes, outs, lens, rec)]
+    st, code = batch.decode(items, graph=False)
+    assert code == 0 and all(x == 0 for x in st)
+    for i in range(len(shapes)):
+        np.testing.assert_array_equal(rec[i].cpu().numpy(), ref_fr[i])
+    # graph replays, with eager work and synchronisation in between
+    for rep in range(3):
+        for r in rec:
+            r.fill_(-1.0)
+        st, code = batch.decode(items, graph=True)
+        assert code == 0 and all(x == 0 for x in st), (rep, st)
+        for i in range(len(shapes)):
+            np.testing.assert_array_equal(rec[i].cpu().numpy(), ref_fr[i])
+        models[0].encode(frames[0])
+        torch.cuda.synchronize()
+    # a corrupted stream is reported for its chunk only
+    bad = outs[2].clone()
+    bad[lens[2] // 2] ^= 0x55
+    items2 = list(items)
+    items2[2] = (shapes[2][0], bad, lens[2], shapes[2][1], shapes[2][2], rec[2])
+    st, code = batch.decode(items2, graph=True)
+    assert st[2] == -3 and all(st[i] == 0 for i in range(len(st)) if i != 2)
+    batch.close()
+    for m in models:
+        m.close()
