@@ -107,6 +107,70 @@ def run_codec(torch, ufvc, weights, prec, chunks, H, W, steps, warmup, seg_log2,
                 n_sym=int(sym.size + zs.size), tuning=tuning)
 
 
+C3_MIX = [(16, 832, 480), (16, 1280, 720), (12, 1920, 1088), (4, 3840, 2160)]
+
+
+def run_batch_c3(torch, ufvc, steps, seg_log2, seg_log2_z):
+    """48 uneven chunks (T drawn from {4, 8}) encoded and decoded as one batch:
+    one launch per stage and tile configuration, decode replayed from a graph."""
+    from synthetic import stand_in_weights, video_chunk
+    C = 128
+    rng = np.random.default_rng(2)
+    spec = []
+    for count, W, H in C3_MIX:
+        for _ in range(count):
+            spec.append((int(rng.choice([4, 8])), H, W))
+    models = {T: ufvc.Codec(T, C, stand_in_weights(T, C), precision="bf16", seg_log2=seg_log2,
+                            seg_log2_z=seg_log2_z, model_tag=0x0C30_0000 + T, autotune=True)
+              for T in (4, 8)}
+    midx = {4: 0, 8: 1}
+    batch = ufvc.Batch([models[4], models[8]])
+    cache = {}
+    frames = []
+    for i, (T, H, W) in enumerate(spec):
+        key = (T, H, W, i % 2)
+        if key not in cache:
+            cache[key] = torch.from_numpy(video_chunk(T, H, W, 16, seed=3, chunk_id=len(cache))).cuda()
+        frames.append(cache[key])
+    outs = [torch.empty(models[T].max_bitstream_bytes(H, W), dtype=torch.uint8, device="cuda")
+            for (T, H, W) in spec]
+    recs = [torch.empty((T, 3, H, W), dtype=torch.float32, device="cuda") for (T, H, W) in spec]
+    enc_items = [(midx[T], fr, o) for (T, H, W), fr, o in zip(spec, frames, outs)]
+    lens = batch.encode(enc_items)                      # plans, tunes buckets
+    dec_items = [(midx[T], o, n, H, W, r) for (T, H, W), o, n, r in zip(spec, outs, lens, recs)]
+    batch.decode(dec_items, graph=False)
+    st, code = batch.decode(dec_items, graph=True)      # captures the graph
+    if code != 0:
+        raise RuntimeError(f"batch decode status {st}")
+    torch.cuda.synchronize()
+    te = td = 0.0
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        lens = batch.encode(enc_items)
+        t1 = time.perf_counter()
+        batch.decode(dec_items, graph=True, check=False)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        te += t1 - t0
+        td += t2 - t1
+    st, code = batch.sync_status()
+    if code != 0:
+        raise RuntimeError(f"batch decode status {st}")
+    frames_total = sum(T for T, _, _ in spec)
+    tuning = {f"{W}x{H}": {f"T{T}": models[T].tuning(H, W)["k1"] for T in (4, 8)}
+              for _, W, H in C3_MIX}
+    res = {"chunks": len(spec), "frames_per_batch": frames_total,
+           "value": round(frames_total * steps / (te + td), 2), "unit": "frames/s",
+           "enc_ms_per_batch": round(1e3 * te / steps, 3),
+           "dec_ms_per_batch": round(1e3 * td / steps, 3), "steps": steps,
+           "decode": "hipGraph replay", "k1_tile_per_bucket": tuning,
+           "mix": "16x832x480, 16x1280x720, 12x1920x1088, 4x3840x2160; T from {4,8} (seed 2)"}
+    batch.close()
+    for m in models.values():
+        m.close()
+    return res
+
+
 def psnr_t(torch, a, b):
     mse = torch.mean((a.double() - b.double()) ** 2).item()
     return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
@@ -144,6 +208,8 @@ def main():
     ap.add_argument("--chunks", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build measures the single-GPU hot path "
@@ -227,6 +293,10 @@ def main():
         "bitstream": {"bytes": r16["bytes"], "bits_per_symbol": round(8 * r16["bytes"] / r16["n_sym"], 4),
                       "overhead_vs_ideal": round(8 * r16["bytes"] / r16["ideal_bits"] - 1, 5)},
     }
+    if not args.no_batch:
+        log("bench: 48-chunk batch")
+        result["batch_c3"] = run_batch_c3(torch, ufvc, args.batch_steps, args.seg_log2,
+                                          args.seg_log2_z)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(T, H, W, C)
