@@ -148,9 +148,20 @@ int ufvc_synthesize(ufvc_ctx* ctx, const float* y_hat, int T, int H, int W,
  *   UFVC_BUF_PARAMS float32 [h][w][2C]   mu (first C) and raw scale logits
  *   UFVC_BUF_IDX    uint8   [h][w][C]    table index from sigma
  *   UFVC_BUF_SYM    uint8   [h][w][C]    r_hat + 32
+ * and the synthesis activations of the last decode / synthesis, in the
+ * activation type (bfloat16 bits for UFVC_BF16 and UFVC_BF16_FP8, float32
+ * for UFVC_FP32), after ReLU:
+ *   UFVC_BUF_D2     act     [h][w][C]    output of chunk-decoder conv d2
+ *   UFVC_BUF_F      act     [h][w][C]    joint feature F (output of d3)
+ *   UFVC_BUF_K1     act     [h][w][T C]  first conv of every frame head
+ *   UFVC_BUF_K2     act     [h][w][T C]  second conv of every frame head
+ *   UFVC_BUF_AMAX   uint32  [8]          UFVC_BF16_FP8: float32 bits of the
+ *                                        amax of the outputs of d1, d2, d3,
+ *                                        k1 and k2 (slots 5-7 unused)
  * `bytes` must equal the buffer size for the last (H, W). */
 enum { UFVC_BUF_Y = 0, UFVC_BUF_ZSYM = 1, UFVC_BUF_PARAMS = 2, UFVC_BUF_IDX = 3,
-       UFVC_BUF_SYM = 4 };
+       UFVC_BUF_SYM = 4, UFVC_BUF_D2 = 5, UFVC_BUF_F = 6, UFVC_BUF_K1 = 7, UFVC_BUF_K2 = 8,
+       UFVC_BUF_AMAX = 9 };
 int ufvc_copy_buffer(ufvc_ctx* ctx, int which, void* host_dst, size_t bytes);
 
 /* ---- Batches: many chunks of uneven size per launch ----

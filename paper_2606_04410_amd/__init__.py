@@ -20,7 +20,7 @@ FP32, BF16, BF16_FP8 = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "bf16_fp8": BF16_FP8}
 STATUS = {0: "OK", -1: "INVAL", -2: "NOSPC", -3: "CORRUPT", -4: "DEVICE", -5: "NOMEM",
           -6: "UNSUPPORTED"}
-BUF_Y, BUF_ZSYM, BUF_PARAMS, BUF_IDX, BUF_SYM = range(5)
+BUF_Y, BUF_ZSYM, BUF_PARAMS, BUF_IDX, BUF_SYM, BUF_D2, BUF_F, BUF_K1, BUF_K2, BUF_AMAX = range(10)
 Z_CHANNELS = 32
 
 
@@ -256,11 +256,18 @@ class Codec:
     def buffer(self, which: int, H: int, W: int) -> np.ndarray:
         h, w, hz, wz = self.latent_size(H, W)
         C = self.C
+        act = np.float32 if self.precision == "fp32" else np.uint16
         shape, dt = {BUF_Y: ((h, w, C), np.float32), BUF_ZSYM: ((hz, wz, Z_CHANNELS), np.uint8),
                      BUF_PARAMS: ((h, w, 2 * C), np.float32), BUF_IDX: ((h, w, C), np.uint8),
-                     BUF_SYM: ((h, w, C), np.uint8)}[which]
+                     BUF_SYM: ((h, w, C), np.uint8), BUF_D2: ((h, w, C), act),
+                     BUF_F: ((h, w, C), act), BUF_K1: ((h, w, self.T * C), act),
+                     BUF_K2: ((h, w, self.T * C), act), BUF_AMAX: ((8,), np.uint32)}[which]
         a = np.zeros(shape, dt)
         _check(lib.ufvc_copy_buffer(self._h, which, a.ctypes.data, a.nbytes), "ufvc_copy_buffer")
+        if a.dtype == np.uint16:      # bfloat16 bits -> float32
+            a = (a.astype(np.uint32) << 16).view(np.float32)
+        elif which == BUF_AMAX:
+            a = a.view(np.float32)
         return a
 
 

@@ -22,11 +22,6 @@ namespace {
 constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
-__global__ void zero_u32_kernel(uint32_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
-}
-
 struct ChunkPlan {
   int model, T, H, W;
   Geom g;
@@ -62,7 +57,7 @@ struct ufvc_batch {
     std::vector<uint8_t> hblob;
     size_t off_conv = 0, off_work = 0, off_epi_e = 0, off_epi_d = 0, off_epi_work = 0,
            off_encseg = 0, off_comp = 0, off_compmap = 0, off_parse = 0, off_decz = 0, off_decy = 0,
-           off_status = 0, off_result = 0;
+           off_status = 0, off_result = 0, off_amax = 0;
     size_t dyn_bytes = 0;          // leading part of the blob rewritten per call
     bool uploaded = false;         // static part already on the device
     int n_conv = 0, n_work = 0, n_epi_work = 0, n_encseg = 0, n_compblk = 0, n_decz = 0, n_decy = 0;
@@ -171,11 +166,23 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
     cp.seg_len = take(4 * (size_t)nseg);
     P.chunks.push_back(cp);
   }
+  // fp8 amax slots of all chunks, cleared together before every decode
+  P.off_amax = take(4 * (size_t)N_AMAX * n);
   P.arena_bytes = off;
   if (hipMalloc(&P.arena, P.arena_bytes) != hipSuccess) return UFVC_E_NOMEM;
   uint8_t* A = P.arena;
   const int cp_prec = conv_prec(m0->cfg.precision);
+  const int sp = synth_prec(m0->cfg.precision);
+  const bool q8 = sp == P_FP8;
+  const int sld = q8 ? LD_Q8 : LD_NHWC;
   const int act_st = cp_prec == P_BF16 ? ST_BF16 : ST_F32;
+  // input slot k - 1, output slot k of chunk i's synthesis chain
+  auto chain = [&](ConvArgs& a, int i, int k) {
+    if (!q8) return;
+    uint32_t* slots = at<uint32_t>(A, P.off_amax) + (size_t)N_AMAX * i;
+    if (k > 0) a.amax_in = slots + k - 1;
+    if (k < 5) a.amax_out = slots + k;
+  };
 
   // ---- conv stages
   std::vector<ConvArgs> descs;
@@ -239,40 +246,46 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
     ConvArgs a = conv_of(q.g.h, q.g.w, q.g.h, q.g.w, b->models[q.model]->d1);
     a.in = A + q.sym; a.mu = reinterpret_cast<const float*>(A + q.P); a.mu_pitch = 2 * C;
     a.out = A + q.act0; a.out_pitch = C; a.relu = 1;
+    chain(a, i, 0);
     return a;
   });
-  stage(P.dec_stage[2], S_D2, cp_prec, LD_NHWC, act_st, 1, -1, [&](int i, int&) {
+  stage(P.dec_stage[2], S_D2, sp, sld, act_st, 1, -1, [&](int i, int&) {
     const ChunkPlan& q = P.chunks[i];
     ConvArgs a = conv_of(q.g.h, q.g.w, q.g.h, q.g.w, b->models[q.model]->d2);
     a.in = A + q.act0; a.in_pitch = C; a.out = A + q.act1; a.out_pitch = C; a.relu = 1;
+    chain(a, i, 1);
     return a;
   });
-  stage(P.dec_stage[3], S_D3, cp_prec, LD_NHWC, act_st, 1, -1, [&](int i, int&) {
+  stage(P.dec_stage[3], S_D3, sp, sld, act_st, 1, -1, [&](int i, int&) {
     const ChunkPlan& q = P.chunks[i];
     ConvArgs a = conv_of(q.g.h, q.g.w, q.g.h, q.g.w, b->models[q.model]->d3);
     a.in = A + q.act1; a.in_pitch = C; a.out = A + q.act0; a.out_pitch = C; a.relu = 1;
+    chain(a, i, 2);
     return a;
   });
-  stage(P.dec_stage[4], S_K1, cp_prec, LD_NHWC, act_st, 1, -1, [&](int i, int&) {
+  stage(P.dec_stage[4], S_K1, sp, sld, act_st, 1, -1, [&](int i, int&) {
     const ChunkPlan& q = P.chunks[i];
     ConvArgs a = conv_of(q.g.h, q.g.w, q.g.h, q.g.w, b->models[q.model]->k1);
     a.in = A + q.act0; a.in_pitch = C; a.out = A + q.big0; a.out_pitch = (long)q.T * C; a.relu = 1;
+    chain(a, i, 3);
     return a;
   });
-  stage(P.dec_stage[5], S_K2, cp_prec, LD_NHWC, act_st, 1, -1, [&](int i, int& g) {
+  stage(P.dec_stage[5], S_K2, sp, sld, act_st, 1, -1, [&](int i, int& g) {
     const ChunkPlan& q = P.chunks[i];
     ConvArgs a = conv_of(q.g.h, q.g.w, q.g.h, q.g.w, b->models[q.model]->k2);
     a.in = A + q.big0; a.in_pitch = (long)q.T * C; a.in_goff = C;
     a.out = A + q.big1; a.out_pitch = (long)q.T * C; a.out_goff = C; a.relu = 1;
+    chain(a, i, 4);
     g = q.T;
     return a;
   });
-  stage(P.dec_stage[6], S_K3, cp_prec, LD_NHWC, ST_SHUFFLE, 1, -1, [&](int i, int& g) {
+  stage(P.dec_stage[6], S_K3, sp, sld, ST_SHUFFLE, 1, -1, [&](int i, int& g) {
     const ChunkPlan& q = P.chunks[i];
     ConvArgs a = conv_of(q.g.h, q.g.w, q.g.h, q.g.w, b->models[q.model]->k3);
     a.in = A + q.big1; a.in_pitch = (long)q.T * C; a.in_goff = C;
     a.out = nullptr;  // the caller's frames, set per call
     a.T = q.T; a.H = q.H; a.W = q.W;
+    chain(a, i, 5);
     g = q.T;
     return a;
   });
@@ -466,9 +479,11 @@ hipError_t run_decode(ufvc_batch* b, ufvc_batch::Plan& P, hipStream_t s) {
   ufvc_ctx* m0 = b->models[0];
   uint8_t* D = P.dblob;
   const int n = (int)P.chunks.size();
-  hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, at<uint32_t>(D, P.off_status), n);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_zero_u32(at<uint32_t>(D, P.off_status), n, s);
   if (e != hipSuccess) return e;
+  if (synth_prec(m0->cfg.precision) == P_FP8 &&
+      (e = launch_zero_u32(at<uint32_t>(P.arena, P.off_amax), N_AMAX * n, s)) != hipSuccess)
+    return e;
   if ((e = launch_parse_batch(at<ParseDesc>(D, P.off_parse), n, s)) != hipSuccess) return e;
   if ((e = launch_rans_decode_batch(m0->tab, at<DecSeg>(D, P.off_decz), P.n_decz, s)) != hipSuccess) return e;
   if ((e = run_stage(P, P.dec_stage[0], s)) != hipSuccess) return e;

@@ -2,6 +2,7 @@
 // decode pipelines of one chunk (see include/ufvc.h for the contract).
 #include "../../include/ufvc.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -57,7 +58,7 @@ static hipError_t tuned_conv(ufvc_ctx* c, int id, int prec, int ld, int st, cons
   hipError_t err = hipSuccess;
   for (int cfg = 0; cfg < conv_num_cfgs(); ++cfg) {
     const TileCfg t = conv_cfg(cfg);
-    if (a.cout % t.bn) continue;
+    if (a.cout % t.bn || !conv_cfg_supported(prec, cfg)) continue;
     float ms = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       (void)hipEventRecord(e0, s);
@@ -85,37 +86,70 @@ static size_t weight_count_tc(int T, int C) {
   return n;
 }
 
+// OCP FP8 E4M3 (bias 7, no infinities, largest finite 448) of x, rounded to
+// nearest even and saturated at +-448.
+static uint8_t e4m3_rne_sat(double x) {
+  const uint8_t sign = std::signbit(x) ? 0x80 : 0;
+  double m = std::fabs(x);
+  if (!(m < 448.0)) return sign | 0x7E;  // saturate (NaN cannot occur for finite weights)
+  if (m < std::ldexp(1.0, -6)) {
+    // subnormals: steps of 2^-9; a result of 8 steps is the smallest normal
+    return sign | (uint8_t)std::nearbyint(m * 512.0);
+  }
+  int e = std::ilogb(m);
+  long q = std::lrint((m / std::ldexp(1.0, e) - 1.0) * 8.0);  // ties to even
+  if (q == 8) { q = 0; ++e; }
+  if (e > 8 || (e == 8 && q > 6)) return sign | 0x7E;
+  return sign | (uint8_t)(((e + 7) << 3) | q);
+}
+
 // Repacks OIHW float32 weights of `groups` groups into the conv kernels'
-// layout: [g][slice][tap][cout][32 bytes], a slice holding 16 bf16 or 8 f32
-// consecutive input channels.
+// layout: [g][slice][tap][cout][row], a slice holding 16 bf16, 8 f32 or 64
+// fp8 consecutive input channels (a row of 32, 32 or 64 bytes).  FP8 weights
+// carry a per-output-channel scale amax / 448 over that channel's taps.
 static int upload_layer(Layer& L, const std::vector<const float*>& src, int cout, int cin,
                         int prec_conv) {
-  const int E = prec_conv == P_BF16 ? 16 : 8;
-  const int esz = prec_conv == P_BF16 ? 2 : 4;
+  const int E = prec_conv == P_FP8 ? 64 : prec_conv == P_BF16 ? 16 : 8;
+  const int esz = prec_conv == P_FP8 ? 1 : prec_conv == P_BF16 ? 2 : 4;
+  const int rowb = E * esz;
   if (cin % E) return UFVC_E_UNSUPPORTED;
   const int groups = (int)src.size();
   const int nsl = cin / E;
-  const size_t gbytes = (size_t)nsl * 9 * cout * 32;
+  const size_t gbytes = (size_t)nsl * 9 * cout * rowb;
   std::vector<uint8_t> buf(gbytes * groups);
+  std::vector<float> scales;
   for (int g = 0; g < groups; ++g) {
     const float* W = src[g];
+    if (prec_conv == P_FP8) {
+      for (int n = 0; n < cout; ++n) {
+        float amax = 0.f;
+        for (size_t k = 0; k < (size_t)cin * 9; ++k) amax = std::max(amax, std::fabs(W[(size_t)n * cin * 9 + k]));
+        scales.push_back(amax > 0.f ? amax / 448.f : 1.f);
+      }
+    }
     for (int s = 0; s < nsl; ++s)
       for (int tap = 0; tap < 9; ++tap)
         for (int n = 0; n < cout; ++n)
           for (int e = 0; e < E; ++e) {
             const int ci = s * E + e;
             const float v = W[((size_t)n * cin + ci) * 9 + tap];
-            uint8_t* d = buf.data() + g * gbytes + ((((size_t)s * 9 + tap) * cout + n) * 32 + e * esz);
+            uint8_t* d = buf.data() + g * gbytes + ((((size_t)s * 9 + tap) * cout + n) * rowb + e * esz);
             if (esz == 4) {
               std::memcpy(d, &v, 4);
-            } else {
+            } else if (esz == 2) {
               const __bf16 b = (__bf16)v;
               std::memcpy(d, &b, 2);
+            } else {
+              *d = e4m3_rne_sat((double)v / (double)scales[(size_t)g * cout + n]);
             }
           }
   }
   if (hipMalloc(&L.w, buf.size()) != hipSuccess) return UFVC_E_NOMEM;
   CK(hipMemcpy(L.w, buf.data(), buf.size(), hipMemcpyHostToDevice));
+  if (!scales.empty()) {
+    if (hipMalloc(&L.wscale, 4 * scales.size()) != hipSuccess) return UFVC_E_NOMEM;
+    CK(hipMemcpy(L.wscale, scales.data(), 4 * scales.size(), hipMemcpyHostToDevice));
+  }
   L.gstride = (long)gbytes;
   L.cin = cin;
   L.cout = cout;
@@ -202,8 +236,18 @@ static hipError_t run_synthesis(ufvc_ctx* c, const Geom& g, const uint8_t* sym, 
                                 hipStream_t s) {
   const int C = c->cfg.C, T = c->cfg.T;
   const int cp = conv_prec(c->cfg.precision);
+  const int sp = synth_prec(c->cfg.precision);
   const int act_st = cp == P_BF16 ? ST_BF16 : ST_F32;
+  // fp8 layers quantise their bf16 input with the amax its producer recorded
+  const bool q8 = sp == P_FP8;
+  const int sld = q8 ? LD_Q8 : LD_NHWC;
   hipError_t e;
+  if (q8 && (e = launch_zero_u32(c->amax, N_AMAX, s)) != hipSuccess) return e;
+  auto chain = [&](ConvArgs& a, int k) {  // input slot k - 1, output slot k
+    if (!q8) return;
+    if (k > 0) a.amax_in = c->amax + k - 1;
+    if (k < 5) a.amax_out = c->amax + k;
+  };
   // d1: loads y_hat = r_hat + mu (or a caller-provided float32 y_hat)
   ConvArgs a = conv_args(g.h, g.w, g.h, g.w, c->d1);
   int ld = LD_DEQUANT;
@@ -219,28 +263,34 @@ static hipError_t run_synthesis(ufvc_ctx* c, const Geom& g, const uint8_t* sym, 
   a.out = c->ws.act0;
   a.out_pitch = C;
   a.relu = 1;
+  chain(a, 0);
   e = stage(c, S_D1, s, [&] { return tuned_conv(c, S_D1, cp, ld, act_st, a, 1, s); });
   if (e != hipSuccess) return e;
   a = conv_args(g.h, g.w, g.h, g.w, c->d2);
   a.in = c->ws.act0; a.in_pitch = C; a.out = c->ws.act1; a.out_pitch = C; a.relu = 1;
-  if ((e = stage(c, S_D2, s, [&] { return tuned_conv(c, S_D2, cp, LD_NHWC, act_st, a, 1, s); })) != hipSuccess) return e;
+  chain(a, 1);
+  if ((e = stage(c, S_D2, s, [&] { return tuned_conv(c, S_D2, sp, sld, act_st, a, 1, s); })) != hipSuccess) return e;
   a = conv_args(g.h, g.w, g.h, g.w, c->d3);
   a.in = c->ws.act1; a.in_pitch = C; a.out = c->ws.act0; a.out_pitch = C; a.relu = 1;
-  if ((e = stage(c, S_D3, s, [&] { return tuned_conv(c, S_D3, cp, LD_NHWC, act_st, a, 1, s); })) != hipSuccess) return e;
+  chain(a, 2);
+  if ((e = stage(c, S_D3, s, [&] { return tuned_conv(c, S_D3, sp, sld, act_st, a, 1, s); })) != hipSuccess) return e;
   // k1 of all heads as one GEMM with T*C outputs
   a = conv_args(g.h, g.w, g.h, g.w, c->k1);
   a.in = c->ws.act0; a.in_pitch = C; a.out = c->ws.big0; a.out_pitch = (long)T * C; a.relu = 1;
-  if ((e = stage(c, S_K1, s, [&] { return tuned_conv(c, S_K1, cp, LD_NHWC, act_st, a, 1, s); })) != hipSuccess) return e;
+  chain(a, 3);
+  if ((e = stage(c, S_K1, s, [&] { return tuned_conv(c, S_K1, sp, sld, act_st, a, 1, s); })) != hipSuccess) return e;
   // k2 per head: group t reads channels [tC, tC + C) and writes the same range
   a = conv_args(g.h, g.w, g.h, g.w, c->k2);
   a.in = c->ws.big0; a.in_pitch = (long)T * C; a.in_goff = C;
   a.out = c->ws.big1; a.out_pitch = (long)T * C; a.out_goff = C; a.relu = 1;
-  if ((e = stage(c, S_K2, s, [&] { return tuned_conv(c, S_K2, cp, LD_NHWC, act_st, a, T, s); })) != hipSuccess) return e;
+  chain(a, 4);
+  if ((e = stage(c, S_K2, s, [&] { return tuned_conv(c, S_K2, sp, sld, act_st, a, T, s); })) != hipSuccess) return e;
   // k3 per head with the pixel-shuffle store into frame t
   a = conv_args(g.h, g.w, g.h, g.w, c->k3);
   a.in = c->ws.big1; a.in_pitch = (long)T * C; a.in_goff = C;
   a.out = frames; a.T = T; a.H = H; a.W = W;
-  return stage(c, S_K3, s, [&] { return tuned_conv(c, S_K3, cp, LD_NHWC, ST_SHUFFLE, a, T, s); });
+  chain(a, 5);
+  return stage(c, S_K3, s, [&] { return tuned_conv(c, S_K3, sp, sld, ST_SHUFFLE, a, T, s); });
 }
 
 extern "C" {
@@ -256,7 +306,8 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
   if (cfg->T < 1 || cfg->T > 8 || (cfg->C != 64 && cfg->C != 128)) return UFVC_E_INVAL;
   if (cfg->seg_log2 < 5 || cfg->seg_log2 > 24 || cfg->seg_log2_z < 5 || cfg->seg_log2_z > 24)
     return UFVC_E_INVAL;
-  if (cfg->precision != UFVC_FP32 && cfg->precision != UFVC_BF16) return UFVC_E_UNSUPPORTED;
+  if (cfg->precision != UFVC_FP32 && cfg->precision != UFVC_BF16 && cfg->precision != UFVC_BF16_FP8)
+    return UFVC_E_UNSUPPORTED;
   if (n_weights != weight_count_tc(cfg->T, cfg->C)) return UFVC_E_INVAL;
   ufvc_ctx* c = new (std::nothrow) ufvc_ctx();
   if (!c) return UFVC_E_NOMEM;
@@ -264,6 +315,7 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
   (void)hipGetDevice(&c->device);
   const int T = cfg->T, C = cfg->C;
   const int cp = conv_prec(cfg->precision);
+  const int sp = synth_prec(cfg->precision);
   // blob offsets in the documented order
   const float* p = weights;
   const float* wa1 = p; p += (size_t)C * 192 * T * 9;
@@ -291,21 +343,22 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
   if (!rc) rc = upload_layer(c->h, {wh}, ZC, C, P_F32);
   if (!rc) rc = upload_layer(c->p, {wp}, 2 * C, ZC, P_F32);
   if (!rc) rc = upload_layer(c->d1, {wd1}, C, C, cp);
-  if (!rc) rc = upload_layer(c->d2, {wd2}, C, C, cp);
-  if (!rc) rc = upload_layer(c->d3, {wd3}, C, C, cp);
-  if (!rc) rc = upload_layer(c->k1, {k1cat.data()}, T * C, C, cp);
-  if (!rc) rc = upload_layer(c->k2, k2s, C, C, cp);
-  if (!rc) rc = upload_layer(c->k3, k3s, 192, C, cp);
+  if (!rc) rc = upload_layer(c->d2, {wd2}, C, C, sp);
+  if (!rc) rc = upload_layer(c->d3, {wd3}, C, C, sp);
+  if (!rc) rc = upload_layer(c->k1, {k1cat.data()}, T * C, C, sp);
+  if (!rc) rc = upload_layer(c->k2, k2s, C, C, sp);
+  if (!rc) rc = upload_layer(c->k3, k3s, 192, C, sp);
   if (!rc) {
     Tables& t = c->tab;
     if (hipMalloc(&t.fc, 4 * NSCALES * NSYM) || hipMalloc(&t.magic, 4 * NSCALES * NSYM) ||
         hipMalloc(&t.shift, NSCALES * NSYM) || hipMalloc(&t.lut, NSCALES * 1024) ||
         hipMalloc(&t.thresholds, 4 * 64) || hipMalloc(&t.tail, 64) || hipMalloc(&c->result, 16) ||
-        hipMalloc(&c->status, 16) || hipHostMalloc(&c->result_host, 16) ||
+        hipMalloc(&c->status, 16) || hipMalloc(&c->amax, 4 * N_AMAX) || hipHostMalloc(&c->result_host, 16) ||
         hipHostMalloc(&c->status_host, 16))
       rc = UFVC_E_NOMEM;
   }
-  if (!rc && hipMemset(c->status, 0, 16) != hipSuccess) rc = UFVC_E_DEVICE;
+  if (!rc && (hipMemset(c->status, 0, 16) != hipSuccess || hipMemset(c->amax, 0, 4 * N_AMAX) != hipSuccess))
+    rc = UFVC_E_DEVICE;
   if (!rc && launch_build_tables(c->tab, nullptr) != hipSuccess) rc = UFVC_E_DEVICE;
   if (!rc && hipDeviceSynchronize() != hipSuccess) rc = UFVC_E_DEVICE;
   if (rc) {
@@ -320,11 +373,13 @@ void ufvc_destroy(ufvc_ctx* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
   Layer* ls[] = {&c->a1, &c->a2, &c->a3, &c->h, &c->p, &c->d1, &c->d2, &c->d3, &c->k1, &c->k2, &c->k3};
-  for (Layer* l : ls)
+  for (Layer* l : ls) {
     if (l->w) (void)hipFree(l->w);
+    if (l->wscale) (void)hipFree(l->wscale);
+  }
   free_ws(c);
   void* dp[] = {c->tab.fc, c->tab.magic, c->tab.shift, c->tab.lut, c->tab.thresholds, c->tab.tail,
-                c->rw.pad_a, c->rw.pad_b, c->result,
+                c->rw.pad_a, c->rw.pad_b, c->result, c->amax,
                 c->status, c->rw.scratch, c->rw.info, c->rw.seg_off, c->rw.seg_len};
   for (void* q : dp)
     if (q) (void)hipFree(q);
@@ -503,6 +558,8 @@ int ufvc_synthesize(ufvc_ctx* c, const float* y_hat, int T, int H, int W, float*
   hipStream_t s = (hipStream_t)stream;
   CK(run_synthesis(c, g, nullptr, nullptr, 0, y_hat, H, W, frames, s));
   c->last_stream = s;
+  c->last_h = g.h;
+  c->last_w = g.w;
   return UFVC_OK;
 }
 
@@ -559,6 +616,7 @@ int ufvc_copy_buffer(ufvc_ctx* c, int which, void* dst, size_t bytes) {
   const size_t npos = (size_t)c->last_h * c->last_w;
   const size_t nz = (size_t)((c->last_h + 1) / 2) * ((c->last_w + 1) / 2) * ZC;
   const int C = c->cfg.C;
+  const size_t es = act_elem_size(c->cfg.precision);
   const void* src = nullptr;
   size_t need = 0;
   switch (which) {
@@ -567,6 +625,11 @@ int ufvc_copy_buffer(ufvc_ctx* c, int which, void* dst, size_t bytes) {
     case UFVC_BUF_PARAMS: src = c->ws.P; need = npos * 2 * C * 4; break;
     case UFVC_BUF_IDX: src = c->ws.idx; need = npos * C; break;
     case UFVC_BUF_SYM: src = c->ws.sym; need = npos * C; break;
+    case UFVC_BUF_D2: src = c->ws.act1; need = npos * C * es; break;
+    case UFVC_BUF_F: src = c->ws.act0; need = npos * C * es; break;
+    case UFVC_BUF_K1: src = c->ws.big0; need = npos * C * c->cfg.T * es; break;
+    case UFVC_BUF_K2: src = c->ws.big1; need = npos * C * c->cfg.T * es; break;
+    case UFVC_BUF_AMAX: src = c->amax; need = 4 * N_AMAX; break;
     default: return UFVC_E_INVAL;
   }
   if (bytes != need) return UFVC_E_INVAL;

@@ -10,13 +10,14 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------- conv ----
-enum Prec { P_F32 = 0, P_BF16 = 1 };
+enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
 enum Loader {
   LD_NHWC = 0,       // activation tensor, channels innermost, compute type
   LD_UNSHUFFLE = 1,  // float32 frames [T][3][H][W], pixel-unshuffle x8 + replicate pad
   LD_DEQUANT = 2,    // y_hat = (sym - 32) + mu from uint8 symbols and float32 mu
   LD_UP2 = 3,        // nearest x2 upsampling of uint8 z symbols (value sym - 32)
-  LD_F32 = 4         // float32 tensor, channels innermost, feeding a bf16 conv
+  LD_F32 = 4,        // float32 tensor, channels innermost, feeding a bf16 conv
+  LD_Q8 = 5          // bf16 tensor quantised to FP8 E4M3 with the producer's amax scale
 };
 enum Store {
   ST_BF16 = 0,     // bf16 [pos][pitch], optional ReLU
@@ -44,6 +45,11 @@ struct ConvArgs {
   long out_pitch;
   long out_goff;
   int relu;
+  // FP8: per-output-channel weight scales [group][cout]; the amax (float
+  // bits) of this layer's input and, for a producer, of its own output
+  const float* wscale;
+  const unsigned* amax_in;
+  unsigned* amax_out;
 };
 
 // Launches one conv layer.  `cfg` selects a tile configuration (see
@@ -60,6 +66,8 @@ hipError_t launch_conv_batch(int prec, int loader, int store, int stride, int cf
 struct TileCfg { int th, tw, bn; };
 int conv_num_cfgs();
 TileCfg conv_cfg(int cfg);
+// false for tile configurations a precision does not instantiate
+bool conv_cfg_supported(int prec, int cfg);
 
 // ------------------------------------------------------------- entropy ----
 constexpr int NSCALES = 64;
@@ -201,6 +209,7 @@ struct ParseDesc {
   uint32_t* status;
 };
 
+hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 hipError_t launch_params_epilogue_batch(const EpiDesc* d, const int2* work, int nwork,
                                         const float* thr, hipStream_t s);
 hipError_t launch_rans_encode_batch(const Tables& t, const EncSeg* segs, int nsegs, hipStream_t s);

@@ -29,8 +29,18 @@
 namespace ufvc {
 
 template <int PREC> struct PT;
-template <> struct PT<P_BF16> { static constexpr int ESZ = 2; static constexpr int E = 16; };
-template <> struct PT<P_F32> { static constexpr int ESZ = 4; static constexpr int E = 8; };
+// E channels per slice; a slice of one position (or weight row) is ROWB bytes
+// in LDS, CH chunks of 16 bytes.
+template <> struct PT<P_BF16> {
+  static constexpr int ESZ = 2, E = 16, ROWB = 32, CH = 2;
+};
+template <> struct PT<P_F32> {
+  static constexpr int ESZ = 4, E = 8, ROWB = 32, CH = 2;
+};
+template <> struct PT<P_FP8> {
+  static constexpr int ESZ = 1, E = 64, ROWB = 64, CH = 4;
+};
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 // 16 bytes as a native vector (HIP's uint4 is a struct whose copies lower to
 // memcpy and can pin staging arrays in scratch memory).
@@ -48,17 +58,40 @@ __device__ __forceinline__ v4u cvt8(const float* v) {
 
 __device__ __forceinline__ v4u ld16(const void* p) { return *reinterpret_cast<const v4u*>(p); }
 
+// E4M3 saturates at +-448
+__device__ __forceinline__ float sat448(float x) { return fminf(fmaxf(x, -448.f), 448.f); }
+
 // 16 bytes of compute-type input for channels [slice*E + ch*E/2, +E/2) at
-// input position (iy, ix); zero outside the input grid (conv zero padding).
+// input position (iy, ix) (fp8: 16 channels from slice*64 + ch*16); zero
+// outside the input grid (conv zero padding).
+
 template <int PREC, int LD>
 __device__ __forceinline__ v4u load_chunk(const ConvArgs& a, const unsigned char* inb,
-                                            int slice, int ch, int iy, int ix) {
+                                            int slice, int ch, int iy, int ix, float qinv) {
   constexpr int E = PT<PREC>::E;
   constexpr int ESZ = PT<PREC>::ESZ;
   if (iy < 0 || ix < 0 || iy >= a.Hin || ix >= a.Win) return zero16();
   const long pos = (long)iy * a.Win + ix;
   if constexpr (LD == LD_NHWC) {
     return ld16(inb + (pos * a.in_pitch + slice * E + ch * (E / 2)) * ESZ);
+  } else if constexpr (LD == LD_Q8) {
+    // 16 bf16 channels -> 16 FP8 E4M3 values of x * qinv (qinv = 448 / amax)
+    static_assert(PREC == P_FP8, "Q8 loader feeds FP8 convs");
+    const unsigned char* src = inb + (pos * a.in_pitch + slice * 64 + ch * 16) * 2;
+    const v4u u0 = ld16(src), u1 = ld16(src + 16);
+    const bf16x8 b0 = __builtin_bit_cast(bf16x8, u0), b1 = __builtin_bit_cast(bf16x8, u1);
+    v4u r;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bf16x8& bb = k < 2 ? b0 : b1;
+      const int o = (k & 1) * 4;
+      int w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448((float)bb[o] * qinv), sat448((float)bb[o + 1] * qinv),
+                                              0, false);
+      w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448((float)bb[o + 2] * qinv), sat448((float)bb[o + 3] * qinv),
+                                          w, true);
+      r[k] = (unsigned)w;
+    }
+    return r;
   } else if constexpr (LD == LD_F32) {
     // float32 tensor feeding a bf16 conv (8 channels -> 8 bf16)
     static_assert(PREC == P_BF16, "use LD_NHWC for float32 compute");
@@ -163,17 +196,20 @@ __device__ __forceinline__ void store_out(const ConvArgs& a, int grp, int oy, in
   }
 }
 
-// LDS rows are the 32 bytes of one position (or weight row) per slice.  The
-// two 16-byte halves swap places every 8 rows, so 16 lanes reading the same
-// half of 16 consecutive rows hit 64 distinct banks (no padding needed).
-constexpr int LDS_ROW = 32;
-__device__ __forceinline__ int lds_off(int row, int half) {
-  return row * LDS_ROW + ((half ^ ((row >> 3) & 1)) << 4);
+// LDS rows hold one position's (or weight row's) slice: 32 bytes (bf16 /
+// f32) or 64 bytes (fp8).  Their 16-byte chunks are XOR-swizzled with the
+// row index (the two halves swap every 8 rows; the four quarters rotate
+// every 4 rows), so 16 lanes reading the same chunk of 16 consecutive rows
+// hit 64 distinct banks (no padding needed).
+template <int ROWB>
+__device__ __forceinline__ int lds_off(int row, int chunk) {
+  if constexpr (ROWB == 32) return row * 32 + ((chunk ^ ((row >> 3) & 1)) << 4);
+  else return row * 64 + ((chunk ^ ((row >> 2) & 3)) << 4);
 }
 
-template <int STRIDE, int TH, int TW, int BN>
+template <int STRIDE, int TH, int TW, int BN, int ROWB>
 constexpr int conv_lds_bytes() {
-  return ((STRIDE == 1 ? (TH + 2) * (TW + 2) : (2 * TH + 1) * (2 * TW + 1)) + 9 * BN) * LDS_ROW;
+  return ((STRIDE == 1 ? (TH + 2) * (TW + 2) : (2 * TH + 1) * (2 * TW + 1)) + 9 * BN) * ROWB;
 }
 
 template <int PREC, int LD, int ST, int STRIDE, int TH, int TW, int WM, int WN, int FM, int FN>
@@ -187,8 +223,10 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
   constexpr int HH = STRIDE == 1 ? TH + 2 : 2 * TH + 1;
   constexpr int HW = STRIDE == 1 ? TW + 2 : 2 * TW + 1;
   constexpr int HP = HH * HW;
-  constexpr int HCH = HP * 2;
-  constexpr int WCH = 9 * BN * 2;
+  constexpr int ROWB = PT<PREC>::ROWB;
+  constexpr int CH = PT<PREC>::CH;
+  constexpr int HCH = HP * CH;
+  constexpr int WCH = 9 * BN * CH;
   constexpr int HIT = (HCH + NT - 1) / NT;
   constexpr int WIT = (WCH + NT - 1) / NT;
   constexpr int E = PT<PREC>::E;
@@ -196,7 +234,7 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
 
   extern __shared__ __attribute__((aligned(16))) unsigned char sh[];
   unsigned char* lds_h = sh;
-  unsigned char* lds_w = sh + HP * LDS_ROW;
+  unsigned char* lds_w = sh + HP * ROWB;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -237,7 +275,16 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
 
   const unsigned char* wbase = reinterpret_cast<const unsigned char*>(a.wpk) + grp * a.w_gstride;
   const unsigned char* inb = reinterpret_cast<const unsigned char*>(a.in) +
-                            grp * a.in_goff * (LD == LD_F32 ? 4 : ESZ);
+                            grp * a.in_goff * (LD == LD_F32 ? 4 : LD == LD_Q8 ? 2 : ESZ);
+  // FP8: input quantisation from the producer's amax
+  float qinv = 1.f, qscale = 1.f;
+  if constexpr (PREC == P_FP8) {
+    const float amax = __uint_as_float(*a.amax_in);
+    if (amax > 0.f) {
+      qinv = 448.f / amax;
+      qscale = amax / 448.f;
+    }
+  }
 
   // Staging registers for the next slice.  Written and read only through
   // fully unrolled loops with constant indices so they live in VGPRs.
@@ -249,17 +296,17 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
       const int q = tid + i * NT;                                                        \
       int pos, ch;                                                                       \
       if (LD == LD_UNSHUFFLE) { ch = q / HP; pos = q - ch * HP; }                        \
-      else { pos = q >> 1; ch = q & 1; }                                                 \
+      else { pos = q / CH; ch = q % CH; }                                                \
       const int hy = pos / HW, hx = pos - (pos / HW) * HW;                               \
       hreg[i] = (HCH % NT == 0 || q < HCH)                                               \
-                    ? load_chunk<PREC, LD>(a, inb, (S_), ch, iy0 + hy, ix0 + hx)         \
+                    ? load_chunk<PREC, LD>(a, inb, (S_), ch, iy0 + hy, ix0 + hx, qinv)   \
                     : zero16();                                                          \
     }                                                                                    \
     _Pragma("unroll") for (int i = 0; i < WIT; ++i) {                                    \
       const int q = min(tid + i * NT, WCH - 1);                                          \
-      const int row = q >> 1, ch = q & 1;                                                \
+      const int row = q / CH, ch = q % CH;                                               \
       const int tap = row / BN, n = row - (row / BN) * BN;                               \
-      wreg[i] = ld16(wbase + (((long)((S_) * 9 + tap) * a.cout + n0 + n) * 32 + ch * 16)); \
+      wreg[i] = ld16(wbase + (((long)((S_) * 9 + tap) * a.cout + n0 + n) * ROWB + ch * 16)); \
     }                                                                                    \
   } while (0)
 #define UFVC_LSTORE()                                                                    \
@@ -268,14 +315,14 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
       const int q = tid + i * NT;                                                        \
       int pos, ch;                                                                       \
       if (LD == LD_UNSHUFFLE) { ch = q / HP; pos = q - ch * HP; }                        \
-      else { pos = q >> 1; ch = q & 1; }                                                 \
+      else { pos = q / CH; ch = q % CH; }                                                \
       if (HCH % NT == 0 || q < HCH)                                                      \
-        *reinterpret_cast<v4u*>(lds_h + lds_off(pos, ch)) = hreg[i];                     \
+        *reinterpret_cast<v4u*>(lds_h + lds_off<ROWB>(pos, ch)) = hreg[i];               \
     }                                                                                    \
     _Pragma("unroll") for (int i = 0; i < WIT; ++i) {                                    \
       const int q = tid + i * NT;                                                        \
       if (WCH % NT == 0 || q < WCH)                                                      \
-        *reinterpret_cast<v4u*>(lds_w + lds_off(q >> 1, q & 1)) = wreg[i];               \
+        *reinterpret_cast<v4u*>(lds_w + lds_off<ROWB>(q / CH, q % CH)) = wreg[i];        \
     }                                                                                    \
   } while (0)
 
@@ -303,24 +350,29 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
     UFVC_GLOAD(min(s + 1, nslices - 1));
     // Fragments of tap t + 1 are read from LDS into the second register set
     // before the MFMAs of tap t are issued, so LDS latency overlaps the
-    // matrix cores.
-    v4u af[2][FM], bf[2][FN];
+    // matrix cores.  A lane's fragment is 16 bytes (bf16 / f32) or 32 bytes
+    // (fp8: chunks 2 khalf and 2 khalf + 1 of its row).
+    constexpr int FRAG = PREC == P_FP8 ? 2 : 1;
+    v4u af[2][FM][FRAG], bf[2][FN][FRAG];
+    auto read_frags = [&](int buf, int tap) {
+      const int toff = (tap / 3) * HW + (tap % 3);
 #pragma unroll
-    for (int fm = 0; fm < FM; ++fm) af[0][fm] = ld16(lds_h + lds_off(arow[fm], khalf));
+      for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
-    for (int fn = 0; fn < FN; ++fn)
-      bf[0][fn] = ld16(lds_w + lds_off((wn * FN + fn) * 32 + (lane & 31), khalf));
+        for (int k = 0; k < FRAG; ++k)
+          af[buf][fm][k] = ld16(lds_h + lds_off<ROWB>(arow[fm] + toff, khalf * FRAG + k));
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int k = 0; k < FRAG; ++k)
+          bf[buf][fn][k] = ld16(lds_w + lds_off<ROWB>(tap * BN + (wn * FN + fn) * 32 + (lane & 31),
+                                                      khalf * FRAG + k));
+    };
+    read_frags(0, 0);
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int cur = tap & 1, nxt = cur ^ 1;
-      if (tap + 1 < 9) {
-        const int toff = ((tap + 1) / 3) * HW + ((tap + 1) % 3);
-#pragma unroll
-        for (int fm = 0; fm < FM; ++fm) af[nxt][fm] = ld16(lds_h + lds_off(arow[fm] + toff, khalf));
-#pragma unroll
-        for (int fn = 0; fn < FN; ++fn)
-          bf[nxt][fn] = ld16(lds_w + lds_off((tap + 1) * BN + (wn * FN + fn) * 32 + (lane & 31), khalf));
-      }
+      if (tap + 1 < 9) read_frags(nxt, tap + 1);
       // keep the next tap's reads ahead of this tap's MFMAs
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -329,11 +381,22 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
         for (int fn = 0; fn < FN; ++fn) {
           if constexpr (PREC == P_BF16) {
             acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, af[cur][fm]), __builtin_bit_cast(bf16x8, bf[cur][fn]),
+                __builtin_bit_cast(bf16x8, af[cur][fm][0]), __builtin_bit_cast(bf16x8, bf[cur][fn][0]),
                 acc[fm][fn], 0, 0, 0);
+          } else if constexpr (PREC == P_FP8) {
+            const i32x8 fa = {(int)af[cur][fm][0].x, (int)af[cur][fm][0].y, (int)af[cur][fm][0].z,
+                              (int)af[cur][fm][0].w, (int)af[cur][fm][1].x, (int)af[cur][fm][1].y,
+                              (int)af[cur][fm][1].z, (int)af[cur][fm][1].w};
+            const i32x8 fb = {(int)bf[cur][fn][0].x, (int)bf[cur][fn][0].y, (int)bf[cur][fn][0].z,
+                              (int)bf[cur][fn][0].w, (int)bf[cur][fn][1].x, (int)bf[cur][fn][1].y,
+                              (int)bf[cur][fn][1].z, (int)bf[cur][fn][1].w};
+            // E4M3 x E4M3, block scales 2^0 (the per-tensor / per-channel
+            // scales are applied in the epilogue)
+            acc[fm][fn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa, fb, acc[fm][fn], 0, 0, 0,
+                                                                         127, 0, 127);
           } else {
-            const v4f fa = __builtin_bit_cast(v4f, af[cur][fm]);
-            const v4f fb = __builtin_bit_cast(v4f, bf[cur][fn]);
+            const v4f fa = __builtin_bit_cast(v4f, af[cur][fm][0]);
+            const v4f fb = __builtin_bit_cast(v4f, bf[cur][fn][0]);
             acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.x, fb.x, acc[fm][fn], 0, 0, 0);
             acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.y, fb.y, acc[fm][fn], 0, 0, 0);
             acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.z, fb.z, acc[fm][fn], 0, 0, 0);
@@ -347,17 +410,35 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
 #undef UFVC_LSTORE
 
   // 32x32 accumulator block: register r of lane l holds row 8(r/4) + 4(l/32) + r%4, column l%32.
+  float vmax = 0.f;
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
-    for (int fn = 0; fn < FN; ++fn)
+    for (int fn = 0; fn < FN; ++fn) {
+      const int n = n0 + (wn * FN + fn) * 32 + (lane & 31);
+      float sc = 1.f;
+      if constexpr (PREC == P_FP8) sc = qscale * a.wscale[grp * a.cout + n];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int M = (wm * FM + fm) * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
         const int oy = oy0 + M / TW, ox = ox0 + M % TW;
-        const int n = n0 + (wn * FN + fn) * 32 + (lane & 31);
-        if (oy < a.Hout && ox < a.Wout) store_out<ST>(a, grp, oy, ox, n, acc[fm][fn][r]);
+        float v = acc[fm][fn][r];
+        if constexpr (PREC == P_FP8) v *= sc;
+        if (oy < a.Hout && ox < a.Wout) {
+          store_out<ST>(a, grp, oy, ox, n, v);
+          if constexpr (ST == ST_BF16) vmax = fmaxf(vmax, fabsf(a.relu ? fmaxf(v, 0.f) : v));
+        }
       }
+    }
+  if constexpr (ST == ST_BF16) {
+    // amax of the stored output for the next FP8 layer (non-negative float
+    // bits order like unsigned integers, so the maximum is order independent)
+    if (a.amax_out) {
+      vmax = fmaxf(vmax, 0.f);
+      for (int o = 32; o > 0; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
+      if (lane == 0) atomicMax(a.amax_out, __float_as_uint((float)(__bf16)vmax));
+    }
+  }
 }
 
 // ------------------------------------------------------------ dispatch ----
@@ -372,6 +453,20 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
 static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 16, 128},
                                 {8, 16, 64},  {16, 16, 128}, {16, 16, 192}, {16, 16, 64}};
 int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
+bool conv_cfg_supported(int prec, int cfg) {
+  return cfg >= 0 && cfg < conv_num_cfgs() && !(prec == P_FP8 && cfg == 6);
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
 TileCfg conv_cfg(int c) { return kCfgs[c]; }
 
 // descs == nullptr: one problem `a` over a (tiles, cout / BN, groups) grid.
@@ -380,7 +475,7 @@ template <int PREC, int LD, int ST, int STRIDE, int TH, int TW, int WM, int WN, 
 static hipError_t run_conv(const ConvArgs& a, int groups, const ConvArgs* descs, const int4* work,
                            int nwork, hipStream_t s) {
   constexpr int BN = WN * FN * 32;
-  constexpr int lds = conv_lds_bytes<STRIDE, TH, TW, BN>();
+  constexpr int lds = conv_lds_bytes<STRIDE, TH, TW, BN, PT<PREC>::ROWB>();
   auto kern = conv3x3_kernel<PREC, LD, ST, STRIDE, TH, TW, WM, WN, FM, FN>;
   static bool attr_set = false;
   if (!attr_set) {
@@ -412,7 +507,10 @@ static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs
     case 3: return run_conv<PREC, LD, ST, STRIDE, 4, 16, 2, 2, 1, 2>(a, groups, d, w, nw, s);
     case 4: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 1>(a, groups, d, w, nw, s);
     case 5: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 2>(a, groups, d, w, nw, s);
-    case 6: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 3>(a, groups, d, w, nw, s);
+    case 6:
+      // 128x96 per wave with 32-byte fp8 fragments does not fit the registers
+      if constexpr (PREC == P_FP8) return hipErrorNotSupported;
+      else return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 3>(a, groups, d, w, nw, s);
     case 7: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 1>(a, groups, d, w, nw, s);
     default: return hipErrorInvalidValue;
   }
@@ -430,6 +528,9 @@ static hipError_t dispatch(int prec, int loader, int store, int stride, int cfg,
   UFVC_CONV(P_BF16, LD_DEQUANT, ST_BF16, 1)
   UFVC_CONV(P_BF16, LD_NHWC, ST_SHUFFLE, 1)
   UFVC_CONV(P_BF16, LD_F32, ST_BF16, 1)
+  // fp8 synthesis
+  UFVC_CONV(P_FP8, LD_Q8, ST_BF16, 1)
+  UFVC_CONV(P_FP8, LD_Q8, ST_SHUFFLE, 1)
   // float32 everything, plus hyper prior and entropy parameters
   UFVC_CONV(P_F32, LD_UNSHUFFLE, ST_F32, 1)
   UFVC_CONV(P_F32, LD_NHWC, ST_F32, 1)

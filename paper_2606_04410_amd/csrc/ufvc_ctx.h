@@ -12,7 +12,8 @@ constexpr int ZC = 32;   // hyper-latent channels
 constexpr int K_Z = 22;  // table row of every z symbol (sigma ~ 1)
 
 struct Layer {
-  void* w = nullptr;   // packed [group][slice][tap][cout][32 bytes]
+  void* w = nullptr;   // packed [group][slice][tap][cout][32 bytes (64 for fp8)]
+  float* wscale = nullptr;  // fp8: per-output-channel dequantisation scale [group][cout]
   long gstride = 0;    // bytes per group
   int cin = 0, cout = 0, groups = 0, prec = 0;
 };
@@ -59,6 +60,7 @@ struct ufvc_ctx {
   unsigned long long* result_host = nullptr; // pinned
   uint32_t* status = nullptr;                // device
   uint32_t* status_host = nullptr;           // pinned
+  uint32_t* amax = nullptr;                  // device, N_AMAX float bit patterns (fp8 synthesis)
   hipStream_t last_stream = nullptr;
   int last_h = 0, last_w = 0;
   // per-stage timing (events recorded on the caller's stream around kernels)
@@ -101,6 +103,10 @@ inline uint64_t tune_key(int id, int h, int w) {
 
 inline int act_elem_size(int prec) { return prec == UFVC_FP32 ? 4 : 2; }
 inline int conv_prec(int prec) { return prec == UFVC_FP32 ? P_F32 : P_BF16; }
+// d2, d3 and the frame heads; d1 (which dequantises the latent) stays at conv_prec
+inline int synth_prec(int prec) { return prec == UFVC_BF16_FP8 ? P_FP8 : conv_prec(prec); }
+// amax slots of the fp8 synthesis chain: outputs of d1, d2, d3, k1, k2
+constexpr int N_AMAX = 8;
 
 inline int nseg_of(long n, int sl) { return n == 0 ? 0 : (int)((n + (1L << sl) - 1) >> sl); }
 inline size_t slot_bytes(int sl) { return (size_t)SEG_STATE_BYTES + 2 * ((size_t)1 << sl); }
@@ -136,6 +142,7 @@ inline ConvArgs conv_args(int Hin, int Win, int Hout, int Wout, const Layer& L) 
   a.cout = L.cout;
   a.wpk = L.w;
   a.w_gstride = L.gstride;
+  a.wscale = L.wscale;
   return a;
 }
 

@@ -18,7 +18,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16", "fp32", "bf16_fp8"])
 def test_batch_equals_single_and_graph_equals_eager(prec):
     import paper_2606_04410_amd as u
     C = 64
