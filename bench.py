@@ -171,6 +171,85 @@ def run_batch_c3(torch, ufvc, steps, seg_log2, seg_log2_z):
     return res
 
 
+def run_fp8_c4(torch, ufvc, steps, seg_log2, seg_log2_z, n_chunks=16):
+    """16 chunks of 1920x1088, T = 8: analysis convs BF16, synthesis convs FP8
+    E4M3 (per-output-channel weight scales), entropy params FP32, tables FP64
+    on the GPU; encoded and decoded as one batch.  Reports throughput, the
+    bit-stream size against the FP32 path and PSNR against the source next to
+    the FP32 and BF16 paths (errors against the FP64 oracle are measured by
+    the full-size tests)."""
+    from synthetic import stand_in_weights, video_chunk
+    T, H, W, C = 8, 1088, 1920, 128
+    w = stand_in_weights(T, C)
+    frames = [torch.from_numpy(video_chunk(T, H, W, 16, seed=4, chunk_id=k)).cuda()
+              for k in range(n_chunks)]
+    codecs = {p: ufvc.Codec(T, C, w, precision=p, seg_log2=seg_log2, seg_log2_z=seg_log2_z,
+                            model_tag=0x0C40_1080, autotune=True)
+              for p in ("bf16_fp8", "bf16", "fp32")}
+    per = {p: [] for p in codecs}
+    sizes = {p: [] for p in codecs}
+    for p, c in codecs.items():
+        for fr in frames:
+            bs, n = c.encode(fr)
+            sizes[p].append(n)
+            per[p].append(psnr_t(torch, fr, c.decode(bs, n, H, W)))
+    batch = ufvc.Batch([codecs["bf16_fp8"]])
+    outs = [torch.empty(codecs["bf16_fp8"].max_bitstream_bytes(H, W), dtype=torch.uint8,
+                        device="cuda") for _ in frames]
+    recs = [torch.empty((T, 3, H, W), dtype=torch.float32, device="cuda") for _ in frames]
+    enc_items = [(0, fr, o) for fr, o in zip(frames, outs)]
+    lens = batch.encode(enc_items)
+    dec_items = [(0, o, n, H, W, r) for o, n, r in zip(outs, lens, recs)]
+    st, code = batch.decode(dec_items, graph=True)
+    if code != 0:
+        raise RuntimeError(f"fp8 batch decode status {st}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lens = batch.encode(enc_items)
+        batch.decode(dec_items, graph=True, check=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st, code = batch.sync_status()
+    if code != 0:
+        raise RuntimeError(f"fp8 batch decode status {st}")
+    same = all(int(lens[i]) == sizes["bf16_fp8"][i] for i in range(len(frames)))
+    d8 = np.array(per["bf16_fp8"]) - np.array(per["fp32"])
+    d16 = np.array(per["bf16"]) - np.array(per["fp32"])
+    dsize = np.array(sizes["bf16_fp8"], np.float64) / np.array(sizes["fp32"]) - 1
+    res = {"chunks": len(frames), "value": round(T * len(frames) * steps / dt, 2),
+           "unit": "frames/s", "steps": steps, "ms_per_batch": round(1e3 * dt / steps, 3),
+           "batch_lengths_equal_single": same,
+           "psnr_delta_fp8_vs_fp32_db": {"min": round(float(d8.min()), 4),
+                                         "max": round(float(d8.max()), 4),
+                                         "mean": round(float(d8.mean()), 4)},
+           "psnr_delta_bf16_vs_fp32_db_mean": round(float(d16.mean()), 4),
+           "bitstream_size_delta_vs_fp32": {"min": round(float(dsize.min()), 6),
+                                            "max": round(float(dsize.max()), 6)},
+           "per_chunk_psnr_db": {p: [round(x, 3) for x in v] for p, v in per.items()},
+           "precision": "analysis bf16, synthesis fp8 e4m3 (d1 bf16), params fp32, tables fp64"}
+    batch.close()
+    for c in codecs.values():
+        c.close()
+    return res
+
+
+def bitstream_report(r, h, w, C, sl, slz):
+    """Stream size against the ideal code length: the literal reading (whole
+    stream within 0.5%) and the per-segment reading (payload within 0.5% plus
+    the 32 flushed 32-bit lane states of every segment)."""
+    ny, nz = h * w * C, ((h + 1) // 2) * ((w + 1) // 2) * 32
+    n_seg = -(-ny // (1 << sl)) + -(-nz // (1 << slz))
+    payload_bits = 8 * (r["bytes"] - 28 - 4 * n_seg)
+    ideal = r["ideal_bits"]
+    return {"bytes": r["bytes"], "segments": n_seg,
+            "bits_per_symbol": round(8 * r["bytes"] / r["n_sym"], 4),
+            "overhead_vs_ideal": round(8 * r["bytes"] / ideal - 1, 5),
+            "overhead_excluding_lane_flush": round((payload_bits - 1024 * n_seg) / ideal - 1, 5),
+            "within_0p5pct_literal": bool(8 * r["bytes"] - ideal <= 0.005 * ideal),
+            "within_0p5pct_plus_flush": bool(0 <= payload_bits - ideal <= 0.005 * ideal + 1024 * n_seg)}
+
+
 def psnr_t(torch, a, b):
     mse = torch.mean((a.double() - b.double()) ** 2).item()
     return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
@@ -203,12 +282,13 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--fp32-steps", type=int, default=10)
-    ap.add_argument("--seg-log2", type=int, default=15)
-    ap.add_argument("--seg-log2-z", type=int, default=11)
+    ap.add_argument("--seg-log2", type=int, default=None, help="default: the package's")
+    ap.add_argument("--seg-log2-z", type=int, default=None, help="default: the package's")
     ap.add_argument("--chunks", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-fp8", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -219,6 +299,10 @@ def main():
     import torch
     import paper_2606_04410_amd as ufvc
     from synthetic import stand_in_weights, video_chunk
+    if args.seg_log2 is None:
+        args.seg_log2 = ufvc.DEFAULT_SEG_LOG2
+    if args.seg_log2_z is None:
+        args.seg_log2_z = ufvc.DEFAULT_SEG_LOG2_Z
 
     T, H, W, C = 8, 1080, 1920, 128
     log(f"bench: generating {args.chunks} chunks T={T} {W}x{H}")
@@ -290,13 +374,16 @@ def main():
         "stage_ms": stage_ms,
         "tile_configs": {k: (v[1:] if v else None) for k, v in r16["tuning"].items()},
         "fp32_stage_ms": {k: round(v[0] / args.fp32_steps, 4) for k, v in r32["stages"].items()},
-        "bitstream": {"bytes": r16["bytes"], "bits_per_symbol": round(8 * r16["bytes"] / r16["n_sym"], 4),
-                      "overhead_vs_ideal": round(8 * r16["bytes"] / r16["ideal_bits"] - 1, 5)},
+        "bitstream": bitstream_report(r16, h, w, C, args.seg_log2, args.seg_log2_z),
     }
     if not args.no_batch:
         log("bench: 48-chunk batch")
         result["batch_c3"] = run_batch_c3(torch, ufvc, args.batch_steps, args.seg_log2,
                                           args.seg_log2_z)
+    if not args.no_fp8:
+        log("bench: fp8 synthesis, 16 chunks")
+        result["fp8_c4"] = run_fp8_c4(torch, ufvc, args.batch_steps, args.seg_log2,
+                                      args.seg_log2_z)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(T, H, W, C)

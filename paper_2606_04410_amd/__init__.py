@@ -22,6 +22,12 @@ STATUS = {0: "OK", -1: "INVAL", -2: "NOSPC", -3: "CORRUPT", -4: "DEVICE", -5: "N
           -6: "UNSUPPORTED"}
 BUF_Y, BUF_ZSYM, BUF_PARAMS, BUF_IDX, BUF_SYM, BUF_D2, BUF_F, BUF_K1, BUF_K2, BUF_AMAX = range(10)
 Z_CHANNELS = 32
+# Segment sizes (log2 symbols per rANS segment) used unless a codec names its
+# own: the 1080p benchmark configuration.  Each segment carries 32 final lane
+# states (128 bytes), so smaller segments buy decoder parallelism (512 y
+# segments at 1080p) for about 2.5% of stream size against 0.9% at 2^15.
+DEFAULT_SEG_LOG2 = 13
+DEFAULT_SEG_LOG2_Z = 10
 
 
 class UfvcError(RuntimeError):
@@ -125,10 +131,12 @@ class Codec:
     """One codec context (one model: fixed T and C) on the current device."""
 
     def __init__(self, T: int, C: int, weights: dict, precision: str = "bf16",
-                 seg_log2: int = 15, seg_log2_z: int = 11, model_tag: int = 0,
+                 seg_log2: int = None, seg_log2_z: int = None, model_tag: int = 0,
                  autotune: bool = False):
         self.T, self.C = T, C
         self.precision = precision
+        seg_log2 = DEFAULT_SEG_LOG2 if seg_log2 is None else seg_log2
+        seg_log2_z = DEFAULT_SEG_LOG2_Z if seg_log2_z is None else seg_log2_z
         self.seg_log2, self.seg_log2_z, self.model_tag = seg_log2, seg_log2_z, model_tag
         flat = flatten_weights(weights, T)
         cfg = _Config(T, C, PRECISIONS[precision], seg_log2, seg_log2_z, model_tag & 0xFFFFFFFF,

@@ -485,12 +485,12 @@ hipError_t run_decode(ufvc_batch* b, ufvc_batch::Plan& P, hipStream_t s) {
       (e = launch_zero_u32(at<uint32_t>(P.arena, P.off_amax), N_AMAX * n, s)) != hipSuccess)
     return e;
   if ((e = launch_parse_batch(at<ParseDesc>(D, P.off_parse), n, s)) != hipSuccess) return e;
-  if ((e = launch_rans_decode_batch(m0->tab, at<DecSeg>(D, P.off_decz), P.n_decz, s)) != hipSuccess) return e;
+  if ((e = launch_rans_decode_batch(m0->tab, at<DecSeg>(D, P.off_decz), P.n_decz, true, s)) != hipSuccess) return e;
   if ((e = run_stage(P, P.dec_stage[0], s)) != hipSuccess) return e;
   if ((e = launch_params_epilogue_batch(at<EpiDesc>(D, P.off_epi_d), at<int2>(D, P.off_epi_work),
                                         P.n_epi_work, m0->tab.thresholds, s)) != hipSuccess)
     return e;
-  if ((e = launch_rans_decode_batch(m0->tab, at<DecSeg>(D, P.off_decy), P.n_decy, s)) != hipSuccess) return e;
+  if ((e = launch_rans_decode_batch(m0->tab, at<DecSeg>(D, P.off_decy), P.n_decy, false, s)) != hipSuccess) return e;
   for (int k = 1; k < 7; ++k)
     if ((e = run_stage(P, P.dec_stage[k], s)) != hipSuccess) return e;
   return hipSuccess;

@@ -351,7 +351,7 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
   if (!rc) {
     Tables& t = c->tab;
     if (hipMalloc(&t.fc, 4 * NSCALES * NSYM) || hipMalloc(&t.magic, 4 * NSCALES * NSYM) ||
-        hipMalloc(&t.shift, NSCALES * NSYM) || hipMalloc(&t.lut, NSCALES * 1024) ||
+        hipMalloc(&t.shift, NSCALES * NSYM) || hipMalloc(&t.lut, NSCALES * LUT_BUCKETS * 2) ||
         hipMalloc(&t.thresholds, 4 * 64) || hipMalloc(&t.tail, 64) || hipMalloc(&c->result, 16) ||
         hipMalloc(&c->status, 16) || hipMalloc(&c->amax, 4 * N_AMAX) || hipHostMalloc(&c->result_host, 16) ||
         hipHostMalloc(&c->status_host, 16))

@@ -6,6 +6,17 @@
 
 namespace ufvc {
 
+// Device-memory accesses through global (address space 1) pointers: the
+// loads and stores become global_* instructions, which count only against
+// vmcnt.  Generic pointers (e.g. read from a descriptor) would give flat_*
+// instructions, which also count against lgkmcnt, so every wait on an LDS
+// read would wait for the outstanding global prefetches too.
+#define UFVC_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ T ldg(const T* p) { return *(const UFVC_GLOBAL T*)(p); }
+template <class T>
+__device__ __forceinline__ void stg(T* p, T v) { *(UFVC_GLOBAL T*)(p) = v; }
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -73,6 +84,8 @@ bool conv_cfg_supported(int prec, int cfg);
 constexpr int NSCALES = 64;
 constexpr int NSYM = 65;
 constexpr int LANES = 32;
+constexpr int LUT_BUCKETS = 512;   // decoder lookup buckets per table row
+constexpr int LUT_SLOTS = 65536 / LUT_BUCKETS;
 constexpr int SEG_STATE_BYTES = 4 * LANES;
 
 // Device tables built once per context.
@@ -80,7 +93,7 @@ struct Tables {
   uint32_t* fc;      // [64][65] freq | cum << 16
   uint32_t* magic;   // [64][65] division multiplier for freq
   uint8_t* shift;    // [64][65] ceil(log2(freq))
-  uint8_t* lut;      // [64][1024] symbol at slot 64 b, bit 7: bucket inside it
+  uint16_t* lut;     // [64][512] decoder lookup per 128-slot bucket
   float* thresholds; // [64] (63 used, [63] = +inf)
   uint8_t* tail;     // [64] length of the leading run of frequency-1 symbols
 };
@@ -215,7 +228,8 @@ hipError_t launch_params_epilogue_batch(const EpiDesc* d, const int2* work, int 
 hipError_t launch_rans_encode_batch(const Tables& t, const EncSeg* segs, int nsegs, hipStream_t s);
 hipError_t launch_compact_batch(const CompDesc* d, const int2* map, int nblocks, hipStream_t s);
 hipError_t launch_parse_batch(const ParseDesc* d, int nchunks, hipStream_t s);
-hipError_t launch_rans_decode_batch(const Tables& t, const DecSeg* segs, int nsegs, hipStream_t s);
+hipError_t launch_rans_decode_batch(const Tables& t, const DecSeg* segs, int nsegs, bool fixed,
+                                    hipStream_t s);
 
 // Device status bits.
 constexpr uint32_t ST_BAD_HEADER = 1u;

@@ -46,6 +46,7 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 // memcpy and can pin staging arrays in scratch memory).
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ v4u zero16() { return v4u{0u, 0u, 0u, 0u}; }
 
@@ -56,7 +57,10 @@ __device__ __forceinline__ v4u cvt8(const float* v) {
   return __builtin_bit_cast(v4u, r);
 }
 
-__device__ __forceinline__ v4u ld16(const void* p) { return *reinterpret_cast<const v4u*>(p); }
+// 16 bytes of device memory (global load)
+__device__ __forceinline__ v4u ld16(const void* p) { return ldg(reinterpret_cast<const v4u*>(p)); }
+// 16 bytes of LDS
+__device__ __forceinline__ v4u lds16(const unsigned char* p) { return *reinterpret_cast<const v4u*>(p); }
 
 // E4M3 saturates at +-448
 __device__ __forceinline__ float sat448(float x) { return fminf(fmaxf(x, -448.f), 448.f); }
@@ -96,8 +100,8 @@ __device__ __forceinline__ v4u load_chunk(const ConvArgs& a, const unsigned char
     // float32 tensor feeding a bf16 conv (8 channels -> 8 bf16)
     static_assert(PREC == P_BF16, "use LD_NHWC for float32 compute");
     const float* fp = reinterpret_cast<const float*>(inb) + pos * a.in_pitch + slice * E + ch * (E / 2);
-    const v4f u0 = *reinterpret_cast<const v4f*>(fp);
-    const v4f u1 = *reinterpret_cast<const v4f*>(fp + 4);
+    const v4f u0 = ldg(reinterpret_cast<const v4f*>(fp));
+    const v4f u1 = ldg(reinterpret_cast<const v4f*>(fp + 4));
     const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
     return cvt8(v);
   } else if constexpr (LD == LD_UNSHUFFLE) {
@@ -112,22 +116,22 @@ __device__ __forceinline__ v4u load_chunk(const ConvArgs& a, const unsigned char
     if constexpr (PREC == P_BF16) {
       float v[8];
       if (px + 8 <= a.W) {
-        const v4f u0 = *reinterpret_cast<const v4f*>(row + px);
-        const v4f u1 = *reinterpret_cast<const v4f*>(row + px + 4);
+        const v4f u0 = ldg(reinterpret_cast<const v4f*>(row + px));
+        const v4f u1 = ldg(reinterpret_cast<const v4f*>(row + px + 4));
         v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
         v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w;
       } else {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = row[min(px + k, a.W - 1)];
+        for (int k = 0; k < 8; ++k) v[k] = ldg(row + min(px + k, a.W - 1));
       }
       return cvt8(v);
     } else {
       v4f r;
       if (px + 4 <= a.W) {
-        r = *reinterpret_cast<const v4f*>(row + px);
+        r = ldg(reinterpret_cast<const v4f*>(row + px));
       } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) r[k] = row[min(px + k, a.W - 1)];
+        for (int k = 0; k < 4; ++k) r[k] = ldg(row + min(px + k, a.W - 1));
       }
       return __builtin_bit_cast(v4u, r);
     }
@@ -136,9 +140,9 @@ __device__ __forceinline__ v4u load_chunk(const ConvArgs& a, const unsigned char
     const unsigned char* sp = reinterpret_cast<const unsigned char*>(a.in) + pos * a.cin + c0;
     const float* mp = a.mu + pos * a.mu_pitch + c0;
     if constexpr (PREC == P_BF16) {
-      const uint2 sb = *reinterpret_cast<const uint2*>(sp);
-      const v4f m0 = *reinterpret_cast<const v4f*>(mp);
-      const v4f m1 = *reinterpret_cast<const v4f*>(mp + 4);
+      const v2u sb = ldg(reinterpret_cast<const v2u*>(sp));
+      const v4f m0 = ldg(reinterpret_cast<const v4f*>(mp));
+      const v4f m1 = ldg(reinterpret_cast<const v4f*>(mp + 4));
       float v[8];
       v[0] = (float)((int)(sb.x & 255) - 32) + m0.x;
       v[1] = (float)((int)((sb.x >> 8) & 255) - 32) + m0.y;
@@ -150,8 +154,8 @@ __device__ __forceinline__ v4u load_chunk(const ConvArgs& a, const unsigned char
       v[7] = (float)((int)(sb.y >> 24) - 32) + m1.w;
       return cvt8(v);
     } else {
-      const uint32_t sb = *reinterpret_cast<const uint32_t*>(sp);
-      const v4f m = *reinterpret_cast<const v4f*>(mp);
+      const uint32_t sb = ldg(reinterpret_cast<const uint32_t*>(sp));
+      const v4f m = ldg(reinterpret_cast<const v4f*>(mp));
       v4f r;
       r[0] = (float)((int)(sb & 255) - 32) + m.x;
       r[1] = (float)((int)((sb >> 8) & 255) - 32) + m.y;
@@ -165,7 +169,7 @@ __device__ __forceinline__ v4u load_chunk(const ConvArgs& a, const unsigned char
     const int wz = (a.Win + 1) >> 1;
     const unsigned char* sp = reinterpret_cast<const unsigned char*>(a.in) +
                               ((long)(iy >> 1) * wz + (ix >> 1)) * a.cin + c0;
-    const uint32_t sb = *reinterpret_cast<const uint32_t*>(sp);
+    const uint32_t sb = ldg(reinterpret_cast<const uint32_t*>(sp));
     v4f r;
     r[0] = (float)((int)(sb & 255) - 32);
     r[1] = (float)((int)((sb >> 8) & 255) - 32);
@@ -180,19 +184,19 @@ __device__ __forceinline__ void store_out(const ConvArgs& a, int grp, int oy, in
   const long pos = (long)oy * a.Wout + ox;
   if constexpr (ST == ST_BF16) {
     if (a.relu) v = fmaxf(v, 0.f);
-    reinterpret_cast<__bf16*>(a.out)[pos * a.out_pitch + grp * a.out_goff + n] = (__bf16)v;
+    stg(reinterpret_cast<__bf16*>(a.out) + pos * a.out_pitch + grp * a.out_goff + n, (__bf16)v);
   } else if constexpr (ST == ST_F32) {
     if (a.relu) v = fmaxf(v, 0.f);
-    reinterpret_cast<float*>(a.out)[pos * a.out_pitch + grp * a.out_goff + n] = v;
+    stg(reinterpret_cast<float*>(a.out) + pos * a.out_pitch + grp * a.out_goff + n, v);
   } else if constexpr (ST == ST_ZSYM) {
     float z = fminf(fmaxf(rintf(v), -32.f), 32.f);
-    reinterpret_cast<unsigned char*>(a.out)[pos * a.out_pitch + n] = (unsigned char)((int)z + 32);
+    stg(reinterpret_cast<unsigned char*>(a.out) + pos * a.out_pitch + n, (unsigned char)((int)z + 32));
   } else {  // ST_SHUFFLE: channel n = c*64 + i*8 + j -> pixel (8 oy + i, 8 ox + j)
     const int c = n >> 6, i = (n >> 3) & 7, j = n & 7;
     const int py = 8 * oy + i, px = 8 * ox + j;
     if (py < a.H && px < a.W)
-      reinterpret_cast<float*>(a.out)[(((long)grp * 3 + c) * a.H + py) * a.W + px] =
-          fminf(fmaxf(v, 0.f), 1.f);
+      stg(reinterpret_cast<float*>(a.out) + (((long)grp * 3 + c) * a.H + py) * a.W + px,
+          fminf(fmaxf(v, 0.f), 1.f));
   }
 }
 
@@ -279,7 +283,7 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
   // FP8: input quantisation from the producer's amax
   float qinv = 1.f, qscale = 1.f;
   if constexpr (PREC == P_FP8) {
-    const float amax = __uint_as_float(*a.amax_in);
+    const float amax = __uint_as_float(ldg(a.amax_in));
     if (amax > 0.f) {
       qinv = 448.f / amax;
       qscale = amax / 448.f;
@@ -360,12 +364,12 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
       for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
         for (int k = 0; k < FRAG; ++k)
-          af[buf][fm][k] = ld16(lds_h + lds_off<ROWB>(arow[fm] + toff, khalf * FRAG + k));
+          af[buf][fm][k] = lds16(lds_h + lds_off<ROWB>(arow[fm] + toff, khalf * FRAG + k));
 #pragma unroll
       for (int fn = 0; fn < FN; ++fn)
 #pragma unroll
         for (int k = 0; k < FRAG; ++k)
-          bf[buf][fn][k] = ld16(lds_w + lds_off<ROWB>(tap * BN + (wn * FN + fn) * 32 + (lane & 31),
+          bf[buf][fn][k] = lds16(lds_w + lds_off<ROWB>(tap * BN + (wn * FN + fn) * 32 + (lane & 31),
                                                       khalf * FRAG + k));
     };
     read_frags(0, 0);
@@ -417,7 +421,7 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
     for (int fn = 0; fn < FN; ++fn) {
       const int n = n0 + (wn * FN + fn) * 32 + (lane & 31);
       float sc = 1.f;
-      if constexpr (PREC == P_FP8) sc = qscale * a.wscale[grp * a.cout + n];
+      if constexpr (PREC == P_FP8) sc = qscale * ldg(a.wscale + grp * a.cout + n);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int M = (wm * FM + fm) * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);

@@ -5,7 +5,7 @@
 //   scale-index thresholds, the multiplier/shift pairs that turn the
 //   encoder's division by a frequency into a multiply-high (Granlund and
 //   Montgomery 1994, "Division by invariant integers using multiplication"),
-//   and a 1024-bucket slot -> symbol lookup for the decoder.
+//   and a 512-bucket slot -> symbol lookup for the decoder.
 // * params_epilogue: sigma = clamp(softplus(.), 0.11, 64) in float32 and its
 //   table index for every latent element; in the encoder also the residual
 //   symbol r_hat = round(y - mu).  The mean is never needed for coding.
@@ -19,6 +19,8 @@
 #include "ufvc_common.h"
 
 namespace ufvc {
+
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 constexpr uint32_t RANS_L = 1u << 16;
 
@@ -64,26 +66,36 @@ __global__ void build_tables_kernel(Tables t) {
     t.shift[k * NSYM + i] = (uint8_t)l;
     cum += fi;
   }
-  // Tails: the leading run of frequency-1 symbols (and its mirror) maps slot
-  // -> symbol in closed form, so the lookup only covers the middle slots
-  // [tail, 65536 - tail).  lut[b]: bits 0..6 the symbol containing the first
-  // middle slot of bucket [64 b, 64 b + 63]; bit 7 set when the bucket's middle
-  // part lies inside that one symbol.
+  // Decoder lookup, 512 buckets of 128 slots per row.  lut[b] (16 bits):
+  // bits 0..6 the symbol s0 holding the bucket's first middle slot, bits
+  // 7..14 the offset in the bucket where s0 + 1 starts (128: s0 fills the rest
+  // of the bucket), bit 15 a slow bucket: it holds three or more symbols, or
+  // frequency-1 tail slots.  The tails (leading run of frequency-1 symbols and
+  // its mirror, fewer than 33 slots) sit in the first and last bucket and map
+  // slot -> symbol in closed form.
   uint32_t tail = 0;
   while (tail < 32 && f[tail] == 1u) ++tail;
   t.tail[k] = (uint8_t)tail;
   const uint32_t mid_end = 65536u - tail;
   int sidx = 0;
   uint32_t c = 0;
-  for (int b = 0; b < 1024; ++b) {
-    const uint32_t first = max((uint32_t)b << 6, tail);
-    uint32_t entry = 0;
-    if (first < mid_end) {
+  for (int b = 0; b < LUT_BUCKETS; ++b) {
+    const uint32_t b0 = (uint32_t)b * LUT_SLOTS;
+    const uint32_t first = max(b0, tail);
+    const uint32_t last = min(b0 + LUT_SLOTS, mid_end);
+    uint32_t entry = 0x8000u;
+    if (first < last) {
       while (sidx + 1 < NSYM && c + f[sidx] <= first) { c += f[sidx]; ++sidx; }
-      const uint32_t last = min(((uint32_t)b << 6) + 64u, mid_end);
-      entry = (uint32_t)sidx | ((c + f[sidx] >= last) ? 128u : 0u);
+      const uint32_t end0 = c + f[sidx];
+      uint32_t boff = LUT_SLOTS;
+      bool slow = tail > 0 && (first > b0 || last < b0 + LUT_SLOTS);
+      if (end0 < last) {
+        boff = end0 - b0;
+        if (sidx + 1 >= NSYM || end0 + f[sidx + 1] < last) slow = true;
+      }
+      entry = (uint32_t)sidx | (boff << 7) | (slow ? 0x8000u : 0u);
     }
-    t.lut[k * 1024 + b] = (uint8_t)entry;
+    t.lut[k * LUT_BUCKETS + b] = (uint16_t)entry;
   }
 }
 
@@ -163,31 +175,25 @@ hipError_t launch_params_epilogue_batch(const EpiDesc* d, const int2* work, int 
 
 // --------------------------------------------------------- rANS encode ----
 // One wave per block, one segment per half-wave.  A segment is processed in
-// epochs of EP steps, last epoch first.  The symbols and table rows of the
-// next epoch are fetched into registers while the current one is coded and
-// committed to LDS at the epoch boundary; the words a step pushes are placed
-// with a ballot + popcount prefix into an LDS staging buffer and written to
-// the segment slot with coalesced stores once per epoch.  The serial loop
-// itself only touches LDS and registers.
+// epochs of EP steps, last epoch first.  Each lane fetches its own symbols and
+// table rows of the next epoch (one coalesced byte load per step across the
+// half-wave) into registers while the current epoch is coded, so a step's
+// table reads depend only on registers and run ahead of the state chain; the
+// words a step pushes are placed with a ballot + popcount prefix into an LDS
+// staging buffer and written to the segment slot with coalesced stores once
+// per epoch.
 constexpr int EP = 32;                 // steps per epoch
 constexpr int EPB = EP * LANES;        // symbols per epoch and segment
 
 struct EncSegLds {
-  uint8_t sym[2][EPB];
-  uint8_t idx[2][EPB];
   uint16_t words[EPB];                 // at most one word per symbol
 };
 constexpr size_t ENC_TAB_BYTES = NSCALES * NSYM * 9;  // fc + magic (u32) + shift (u8)
 constexpr size_t ENC_LDS_BYTES = ((ENC_TAB_BYTES + 15) & ~(size_t)15) + 2 * sizeof(EncSegLds);
 
-// 32 bytes at p + pos.  Symbol and index arrays handed to the coders carry
-// CODER_PAD readable bytes past their end (more than one epoch), so this
-// never branches: the loads stay in flight until the values are committed to
-// LDS.  Positions past the segment's end are masked by the callers.
-__device__ __forceinline__ void load32(const uint8_t* __restrict__ p, long pos, uint4& a, uint4& b) {
-  a = *reinterpret_cast<const uint4*>(p + pos);
-  b = *reinterpret_cast<const uint4*>(p + pos + 16);
-}
+// Symbol and index arrays handed to the coders carry CODER_PAD readable bytes
+// past their end (more than one epoch), so the per-epoch prefetches never
+// branch; positions past a segment's end are masked by the callers.
 
 // Segment `seg` of the (z, y) stream pair of one chunk as a descriptor.
 __device__ __forceinline__ EncSeg enc_seg_of(const EncStream& z, const EncStream& y,
@@ -245,8 +251,7 @@ rans_encode_kernel(Tables t, EncStream z, EncStream y, uint8_t* __restrict__ scr
   const int nep = (int)((max(n_first, n_other) + EPB - 1) / EPB);
   const uint8_t* __restrict__ sym = me.sym;
   const uint8_t* __restrict__ idxp = me.idx;
-  const int fixed = (int)me.fixed_row;
-  const long base = 0;
+  const uint32_t fixed = min(me.fixed_row, 63u);
   const int nsym = active ? (int)me.nsym : 0;
   uint8_t* slot = me.slot;
   uint16_t* __restrict__ words = reinterpret_cast<uint16_t*>(slot + SEG_STATE_BYTES);
@@ -255,44 +260,35 @@ rans_encode_kernel(Tables t, EncStream z, EncStream y, uint8_t* __restrict__ scr
   uint32_t cursor = cap;
   uint32_t x = RANS_L;
 
-  uint4 ps0, ps1, pi0, pi1;
-  const uint32_t f4 = (uint32_t)fixed * 0x01010101u;
+  // raw symbols and rows of each step of the next epoch (used only in the
+  // epoch after the one that issued the loads, so they have a whole epoch to
+  // arrive)
+  uint32_t sn[EP], kn[EP];
   const int nep_own = (nsym + EPB - 1) / EPB;
   auto prefetch = [&](int ep) {
     // epochs outside this segment's own [0, nep_own) and inactive halves
     // re-read epoch 0, which is in bounds
-    const long pos = (ep >= 0 && ep < nep_own ? (long)ep * EPB : 0) + lane * 32;
-    load32(sym + base, pos, ps0, ps1);
-    if (idxp) {
-      load32(idxp + base, pos, pi0, pi1);
-    } else {
-      pi0 = make_uint4(f4, f4, f4, f4);
-      pi1 = pi0;
-    }
-  };
-  auto commit = [&](int buf) {
-    if (active) {
-      *reinterpret_cast<uint4*>(&L.sym[buf][lane * 32]) = ps0;
-      *reinterpret_cast<uint4*>(&L.sym[buf][lane * 32 + 16]) = ps1;
-      *reinterpret_cast<uint4*>(&L.idx[buf][lane * 32]) = pi0;
-      *reinterpret_cast<uint4*>(&L.idx[buf][lane * 32 + 16]) = pi1;
+    const long pos = (ep >= 0 && ep < nep_own ? (long)ep * EPB : 0) + lane;
+#pragma unroll
+    for (int u = 0; u < EP; ++u) {
+      sn[u] = ldg(sym + pos + u * LANES);
+      kn[u] = ldg((idxp ? idxp : sym) + pos + u * LANES);
     }
   };
 
   prefetch(nep - 1);
   for (int ep = nep - 1; ep >= 0; --ep) {
-    const int buf = ep & 1;
-    commit(buf);
-    __syncthreads();
+    // table entry (row * NSYM + symbol) of each step of this epoch
+    uint32_t ec[EP];
+#pragma unroll
+    for (int u = 0; u < EP; ++u) ec[u] = (idxp ? min(kn[u], 63u) : fixed) * NSYM + min(sn[u], 64u);
     prefetch(ep - 1);
     const uint32_t cstart = cursor;
-#pragma unroll 4
+#pragma unroll
     for (int u = EP - 1; u >= 0; --u) {
       const int j = ep * EPB + u * LANES + lane;
       const bool valid = active && j < nsym;
-      const uint32_t sv = min((uint32_t)L.sym[buf][u * LANES + lane], 64u);
-      const uint32_t kv = min((uint32_t)L.idx[buf][u * LANES + lane], 63u);
-      const int e = (int)kv * NSYM + (int)sv;
+      const uint32_t e = ec[u];
       const uint32_t fc = s_fc[e];
       const uint32_t mg = s_mg[e];
       const uint32_t l = s_sh[e];
@@ -319,11 +315,12 @@ rans_encode_kernel(Tables t, EncStream z, EncStream y, uint8_t* __restrict__ scr
     if (active) {
       const uint32_t nep_words = cstart - cursor;
       for (uint32_t i = lane; i < nep_words; i += LANES)
-        words[cursor + i] = L.words[cstart - 1u - (cursor + i)];
+        stg(words + cursor + i, L.words[cstart - 1u - (cursor + i)]);
     }
+    __syncthreads();
   }
   if (active) {
-    reinterpret_cast<uint32_t*>(slot)[lane] = x;
+    stg(reinterpret_cast<uint32_t*>(slot) + lane, x);
     if (lane == 0) {
       SegInfo si;
       si.start_word = cursor;
@@ -567,23 +564,23 @@ hipError_t launch_parse_batch(const ParseDesc* d, int nchunks, hipStream_t s) {
 
 // --------------------------------------------------------- rANS decode ----
 // One wave per block, one segment per half-wave, epochs of EP steps.  Per
-// segment the LDS holds a ring of RING words of the stream, the table rows
-// of two epochs and the decoded symbols of one epoch.  Refill rule: at each
-// epoch start the ring must hold the worst case of the epoch (EPB words past
-// the cursor); 1024 more words are fetched in the background whenever fewer
-// than two epochs' worth are buffered.  With at most EPB words consumed per
-// epoch this keeps the invariant and never overwrites unread words
-// (buffered - consumed < 3 EPB <= RING).  The serial loop itself only
-// touches LDS and registers.
+// segment the LDS holds a ring of RING words of the stream and the decoded
+// symbols of one epoch; each lane holds the table rows of its steps of the
+// current and the next epoch in registers.  Refill rule: at each epoch start
+// the ring must hold the worst case of the epoch (EPB words past the cursor);
+// 1024 more words are fetched in the background whenever fewer than two
+// epochs' worth are buffered.  With at most EPB words consumed per epoch this
+// keeps the invariant and never overwrites unread words (buffered - consumed
+// < 3 EPB <= RING).  A step's dependent chain is three LDS reads: the bucket
+// lookup, the symbol's frequency / cumulative pair and, on renormalisation,
+// the next stream word.
 constexpr int RING = 4096;   // words
-constexpr int LUTB = 1024;   // decoder lookup buckets per table row (slot >> 6)
 
 struct DecSegLds {
   uint16_t ring[RING];
-  uint8_t idx[2][EPB];
   uint8_t out[EPB];
 };
-constexpr size_t DEC_TAB_BYTES = NSCALES * NSYM * 4 + NSCALES * LUTB + NSCALES;
+constexpr size_t DEC_TAB_BYTES = NSCALES * NSYM * 4 + NSCALES * LUT_BUCKETS * 2 + NSCALES;
 constexpr size_t DEC_LDS_BYTES = DEC_TAB_BYTES + 2 * sizeof(DecSegLds);
 
 // Segment `si` of one decoded stream as a descriptor.
@@ -604,17 +601,19 @@ __device__ __forceinline__ DecSeg dec_seg_of(const uint8_t* bs, const uint32_t* 
   return e;
 }
 
+// FIXED: every symbol of the stream uses the row fixed_row (no index array).
+template <bool FIXED>
 __global__ void __launch_bounds__(64)
 rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __restrict__ seg_off0,
                    const uint32_t* __restrict__ seg_len0, DecStream d, uint32_t* __restrict__ status0,
                    const DecSeg* __restrict__ segd, int nsegd) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   uint32_t* s_fc = reinterpret_cast<uint32_t*>(lds);
-  uint8_t* s_lut = lds + NSCALES * NSYM * 4;
-  uint8_t* s_tail = s_lut + NSCALES * LUTB;
+  uint16_t* s_lut = reinterpret_cast<uint16_t*>(lds + NSCALES * NSYM * 4);
+  uint8_t* s_tail = reinterpret_cast<uint8_t*>(s_lut + NSCALES * LUT_BUCKETS);
   DecSegLds* segs = reinterpret_cast<DecSegLds*>(lds + DEC_TAB_BYTES);
   for (int i = threadIdx.x; i < NSCALES * NSYM; i += blockDim.x) s_fc[i] = t.fc[i];
-  for (int i = threadIdx.x; i < NSCALES * LUTB / 16; i += blockDim.x)
+  for (int i = threadIdx.x; i < NSCALES * LUT_BUCKETS * 2 / 16; i += blockDim.x)
     reinterpret_cast<uint4*>(s_lut)[i] = reinterpret_cast<const uint4*>(t.lut)[i];
   s_tail[threadIdx.x] = t.tail[threadIdx.x];
 
@@ -637,13 +636,11 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
   const int nep = (int)((max(n_first, n_other) + EPB - 1) / EPB);
   const uint8_t* __restrict__ bs = me.bs;
   uint32_t* __restrict__ status = me.status;
-  const uint32_t off = active ? *me.seg_off : 0xFFFFFFFFu;
+  const uint32_t off = active ? ldg(me.seg_off) : 0xFFFFFFFFu;
   const bool usable = off != 0xFFFFFFFFu;
   const int nsym = active ? (int)me.nsym : 0;
-  const uint32_t slen = usable ? *me.seg_len : (uint32_t)SEG_STATE_BYTES;
+  const uint32_t slen = usable ? ldg(me.seg_len) : (uint32_t)SEG_STATE_BYTES;
   const uint32_t nw = (slen - SEG_STATE_BYTES) >> 1;    // words including a pad word
-  const uint32_t ndw = nw >> 1;                          // dwords of the word area
-  (void)ndw;
   const uint32_t* __restrict__ wdw =
       reinterpret_cast<const uint32_t*>(bs + (usable ? off : 0) + SEG_STATE_BYTES);
   // last readable dword of the stream, for clamped background fetches
@@ -652,7 +649,7 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
   uint8_t* __restrict__ out = me.out;
   DecSegLds& L = segs[half];
 
-  uint32_t x = usable ? reinterpret_cast<const uint32_t*>(bs + off)[lane] : RANS_L;
+  uint32_t x = usable ? ldg(reinterpret_cast<const uint32_t*>(bs + off) + lane) : RANS_L;
   uint32_t cursor = 0, loaded = 0;
 
   // background word fetch: 512 dwords (1024 words) starting at `loaded`
@@ -665,7 +662,7 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const long dw = wdw0 + (long)((loaded >> 1) + lane + 32u * i);
-      wreg[i] = bsdw[min(dw, last_dw)];
+      wreg[i] = ldg(bsdw + min(dw, last_dw));
     }
     wpend = true;
   };
@@ -680,56 +677,54 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
       wpend = false;
     }
   };
-  uint4 pi0, pi1;
-  const uint32_t f4 = me.fixed_row * 0x01010101u;
+  // table row offset (row * NSYM) of each step of the next epoch; epochs past
+  // this segment's own count re-read epoch 0 (in bounds)
+  const uint32_t frow = min(me.fixed_row, 63u);
+  uint32_t rn[EP];
   const int nep_own = (nsym + EPB - 1) / EPB;
-  auto fetch_idx = [&](int ep) {
-    if (me.idx) {
-      // epochs past this segment's own count re-read epoch 0 (in bounds)
-      load32(me.idx, (long)(ep < nep_own ? ep : 0) * EPB + lane * 32, pi0, pi1);
-    } else {
-      pi0 = make_uint4(f4, f4, f4, f4);
-      pi1 = pi0;
+  auto fetch_rows = [&](int ep) {
+    // raw bytes; clamped only when the next epoch copies them, so the loads
+    // have a whole epoch to arrive
+    if constexpr (!FIXED) {
+      const long pos = (long)(ep < nep_own ? ep : 0) * EPB + lane;
+#pragma unroll
+      for (int u = 0; u < EP; ++u) rn[u] = ldg(me.idx + pos + u * LANES);
     }
   };
 
   fetch_words();
   commit_words();
-  fetch_idx(0);
+  fetch_rows(0);
   for (int ep = 0; ep < nep; ++ep) {
-    const int buf = ep & 1;
-    *reinterpret_cast<uint4*>(&L.idx[buf][lane * 32]) = pi0;
-    *reinterpret_cast<uint4*>(&L.idx[buf][lane * 32 + 16]) = pi1;
+    uint32_t rc[EP];
+#pragma unroll
+    for (int u = 0; u < EP; ++u) rc[u] = FIXED ? frow : min(rn[u], 63u);
     commit_words();
     __syncthreads();
-    fetch_idx(ep + 1);
+    fetch_rows(ep + 1);
     if (loaded - cursor < 2u * EPB) fetch_words();
-#pragma unroll 4
+#pragma unroll
     for (int u = 0; u < EP; ++u) {
       const int j = ep * EPB + u * LANES + lane;
       const bool valid = active && j < nsym;
-      const int row = (int)min((uint32_t)L.idx[buf][u * LANES + lane], 63u);
-      const int rowb = row * NSYM;
-      const uint32_t tl = s_tail[row];
+      const uint32_t row = rc[u];
       const uint32_t slot = x & 0xFFFFu;
-      const bool ltail = slot < tl;
-      const bool rtail = slot >= 65536u - tl;
-      const uint32_t le = s_lut[row * LUTB + (slot >> 6)];
-      uint32_t sy = le & 127u;
-      uint32_t fc = s_fc[rowb + sy];
-      if (!(le & 128u) && !ltail && !rtail) {
-        while (sy < NSYM - 1) {
-          const uint32_t nfc = s_fc[rowb + sy + 1];
-          if ((nfc >> 16) > slot) break;
-          ++sy;
-          fc = nfc;
+      const uint32_t e = s_lut[row * LUT_BUCKETS + (slot >> 7)];
+      uint32_t sy = (e & 127u) + ((slot & 127u) >= ((e >> 7) & 255u) ? 1u : 0u);
+      if (e & 0x8000u) {
+        // slow bucket: frequency-1 tails in closed form (slot s is symbol s
+        // on the left, 64 - (65535 - s) on the right), else a scan from s0
+        const uint32_t tl = s_tail[row];
+        if (slot < tl) {
+          sy = slot;
+        } else if (slot >= 65536u - tl) {
+          sy = slot - (65536u - NSYM);
+        } else {
+          sy = e & 127u;
+          while (sy < NSYM - 1 && (s_fc[row * NSYM + sy + 1] >> 16) <= slot) ++sy;
         }
       }
-      // frequency-1 tails: symbol = slot (left) or 64 - (65535 - slot) (right)
-      if (ltail | rtail) {
-        sy = ltail ? slot : slot - (65536u - NSYM);
-        fc = 1u | (slot << 16);
-      }
+      const uint32_t fc = s_fc[row * NSYM + sy];
       const uint32_t f = fc & 0xFFFFu, c = fc >> 16;
       uint32_t xn = f * (x >> 16) + slot - c;
       const bool need = valid && xn < RANS_L;
@@ -747,12 +742,11 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
     const long pos = (long)ep * EPB + lane * 32;
     if (active) {
       if (pos + 32 <= nsym) {
-        *reinterpret_cast<uint4*>(out + pos) = *reinterpret_cast<const uint4*>(&L.out[lane * 32]);
-        *reinterpret_cast<uint4*>(out + pos + 16) =
-            *reinterpret_cast<const uint4*>(&L.out[lane * 32 + 16]);
+        stg(reinterpret_cast<v4u*>(out + pos), *reinterpret_cast<const v4u*>(&L.out[lane * 32]));
+        stg(reinterpret_cast<v4u*>(out + pos + 16), *reinterpret_cast<const v4u*>(&L.out[lane * 32 + 16]));
       } else {
         for (int i = 0; i < 32; ++i)
-          if (pos + i < nsym) out[pos + i] = usable ? L.out[lane * 32 + i] : 32;
+          if (pos + i < nsym) stg(out + pos + i, (uint8_t)(usable ? L.out[lane * 32 + i] : 32));
       }
     }
   }
@@ -775,34 +769,51 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
   if (((uint32_t)(anybad >> shsel)) != 0u && lane == 0) atomicOr(status, ST_CORRUPT);
 }
 
+template <bool FIXED>
+static hipError_t set_dec_lds() {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rans_decode_kernel<FIXED>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)DEC_LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_rans_decode(const Tables& t, const uint8_t* bs, const uint32_t* seg_off,
                               const uint32_t* seg_len, DecStream d, uint32_t* status,
                               hipStream_t s) {
   if (d.n_seg == 0) return hipSuccess;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rans_decode_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)DEC_LDS_BYTES);
-    if (e != hipSuccess) return e;
-    attr = true;
+  const dim3 grid((d.n_seg + 1) / 2);
+  hipError_t e;
+  if (d.idx) {
+    if ((e = set_dec_lds<false>()) != hipSuccess) return e;
+    hipLaunchKernelGGL(rans_decode_kernel<false>, grid, dim3(64), DEC_LDS_BYTES, s, t, bs, seg_off,
+                       seg_len, d, status, nullptr, 0);
+  } else {
+    if ((e = set_dec_lds<true>()) != hipSuccess) return e;
+    hipLaunchKernelGGL(rans_decode_kernel<true>, grid, dim3(64), DEC_LDS_BYTES, s, t, bs, seg_off,
+                       seg_len, d, status, nullptr, 0);
   }
-  hipLaunchKernelGGL(rans_decode_kernel, dim3((d.n_seg + 1) / 2), dim3(64), DEC_LDS_BYTES, s, t, bs,
-                     seg_off, seg_len, d, status, nullptr, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_rans_decode_batch(const Tables& t, const DecSeg* segs, int nsegs, hipStream_t s) {
+hipError_t launch_rans_decode_batch(const Tables& t, const DecSeg* segs, int nsegs, bool fixed,
+                                    hipStream_t s) {
   if (nsegs <= 0) return hipSuccess;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rans_decode_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)DEC_LDS_BYTES);
-    if (e != hipSuccess) return e;
-    attr = true;
+  const dim3 grid((nsegs + 1) / 2);
+  DecStream none{};
+  hipError_t e;
+  if (!fixed) {
+    if ((e = set_dec_lds<false>()) != hipSuccess) return e;
+    hipLaunchKernelGGL(rans_decode_kernel<false>, grid, dim3(64), DEC_LDS_BYTES, s, t, nullptr,
+                       nullptr, nullptr, none, nullptr, segs, nsegs);
+  } else {
+    if ((e = set_dec_lds<true>()) != hipSuccess) return e;
+    hipLaunchKernelGGL(rans_decode_kernel<true>, grid, dim3(64), DEC_LDS_BYTES, s, t, nullptr,
+                       nullptr, nullptr, none, nullptr, segs, nsegs);
   }
-  DecStream none{nullptr, 0, 0, 5, 0, 0, nullptr, 0};
-  hipLaunchKernelGGL(rans_decode_kernel, dim3((nsegs + 1) / 2), dim3(64), DEC_LDS_BYTES, s, t,
-                     nullptr, nullptr, nullptr, none, nullptr, segs, nsegs);
   return hipGetLastError();
 }
 

@@ -1,0 +1,167 @@
+"""Full-size parity: one 1080p chunk (T = 8, 1920x1080 padded to 1088,
+C = 128) in the benchmark's launch configuration (default segment sizes,
+autotuned tiles), checked against the oracle on sampled outputs.
+
+* Encoder stages at sampled latent windows (corners, the padded bottom rows,
+  interior), each stage isolated on the GPU's own input: y against the
+  analysis (float32: 1e-3; bfloat16: the error is stated, bounded by 2% of
+  max |y|), z and symbols identical except at provable near-half ties, mu
+  within 1e-4, scale indices identical except at near-threshold sigmas.
+* Sampled rANS segments (first and last z, first, middle and last y) are
+  byte-identical to the oracle coding the GPU's symbols; every segment's
+  size matches the container's table and the stream parses exactly.
+* Decoder: indices and symbols equal the encoder's over the whole latent;
+  frames at sampled windows against the oracle synthesis of the GPU's y_hat
+  (float32: 1e-3; bfloat16: PSNR >= 35 dB; FP8: PSNR >= 20 dB).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from oracle import codec as ocodec  # noqa: E402
+from oracle import container, entropy, nets, rans  # noqa: E402
+from synthetic import stand_in_weights, video_chunk  # noqa: E402
+from tests import windows as wn  # noqa: E402
+
+FREQ, CUM = entropy.cdf_tables()
+THR = entropy.thresholds().astype(np.float64)
+T, H, W, C = 8, 1080, 1920, 128
+# latent windows (rows, cols) of 4x4 positions: corners incl. the padded bottom
+# rows (latent row 135 covers pixel rows 1080-1087 of the 1088 padded), interior
+WINDOWS = [(0, 4, 0, 4), (132, 136, 236, 240), (61, 65, 117, 121), (37, 41, 201, 205),
+           (133, 136, 0, 4)]
+ZWINDOWS = [(0, 3, 0, 3), (65, 68, 117, 120), (30, 33, 60, 64)]
+
+_CACHE = {}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def pkg():
+    import paper_2606_04410_amd as p
+    return p
+
+
+def chunk():
+    if "fr" not in _CACHE:
+        _CACHE["fr"] = video_chunk(T, H, W, 16, seed=1, chunk_id=0)
+        _CACHE["w"] = stand_in_weights(T, C)
+    return _CACHE["fr"], _CACHE["w"]
+
+
+def chw(a):
+    return np.ascontiguousarray(np.transpose(a, (2, 0, 1)))
+
+
+def near_half(v, tol=1e-3):
+    return np.abs(v - np.floor(v) - 0.5) < tol
+
+
+def near_threshold(sigma, tol=1e-4):
+    return ((np.abs(sigma[..., None] - THR) / THR) < tol).any(axis=-1)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_fullsize_chunk_sampled_parity(prec):
+    u = pkg()
+    fr, w = chunk()
+    say(f"full-size {prec}: T={T} {W}x{H} C={C} seg {u.DEFAULT_SEG_LOG2}/{u.DEFAULT_SEG_LOG2_Z}")
+    c = u.Codec(T, C, w, precision=prec, model_tag=0x0800_1080, autotune=True)
+    bs, n = c.encode(torch.from_numpy(fr).cuda())
+    stream = bs[:n].cpu().numpy().tobytes()
+    h, ww, hz, wz = ocodec.latent_size(H, W)
+    g_y = chw(c.buffer(u.BUF_Y, H, W)).astype(np.float64)
+    g_zh = chw(c.buffer(u.BUF_ZSYM, H, W)).astype(np.float64) - 32
+    g_P = chw(c.buffer(u.BUF_PARAMS, H, W))
+    g_idx = c.buffer(u.BUF_IDX, H, W)
+    g_sym = c.buffer(u.BUF_SYM, H, W)
+    ymax = float(np.abs(g_y).max())
+    worst = 0.0
+    for r0, r1, c0, c1 in WINDOWS:
+        o_y = wn.analysis_window(fr, w, h, ww, r0, r1, c0, c1)
+        worst = max(worst, float(np.abs(g_y[:, r0:r1, c0:c1] - o_y).max()))
+        mu, sigma = wn.params_window(g_zh, w, h, ww, r0, r1, c0, c1)
+        assert float(np.abs(g_P[:C, r0:r1, c0:c1] - mu).max()) < 1e-4
+        o_idx = entropy.scale_index(sigma)
+        gi = chw(g_idx)[:, r0:r1, c0:c1]
+        assert not ((gi != o_idx) & ~near_threshold(sigma)).any()
+        r = g_y[:, r0:r1, c0:c1] - g_P[:C, r0:r1, c0:c1].astype(np.float64)
+        o_sym = np.clip(np.rint(r), -32, 32) + 32
+        assert not ((chw(g_sym)[:, r0:r1, c0:c1] != o_sym) & ~near_half(r)).any()
+    say(f"  y max abs {worst:.3e} at sampled windows (max |y| {ymax:.2f})")
+    assert worst <= (1e-3 if prec == "fp32" else 0.02 * ymax)
+    for a0, a1, b0, b1 in ZWINDOWS:
+        zu = wn.hyper_window(g_y, w, a0, a1, b0, b1)
+        mis = g_zh[:, a0:a1, b0:b1] != nets.rint_clamp(zu)
+        assert not (mis & ~near_half(zu)).any()
+    # container and sampled segments, bit-exact
+    hdr = container.parse(stream)
+    assert (hdr["T"], hdr["C"], hdr["H"], hdr["W"]) == (T, C, H, W)
+    sl, slz = hdr["seg_log2"], hdr["seg_log2_z"]
+    zsym = c.buffer(u.BUF_ZSYM, H, W).reshape(-1)
+    ysym, yidx = g_sym.reshape(-1), g_idx.reshape(-1)
+    nz, ny = len(hdr["z_segs"]), len(hdr["y_segs"])
+    assert nz == -(-zsym.size // (1 << slz)) and ny == -(-ysym.size // (1 << sl))
+    for kind, k in [("z", 0), ("z", nz - 1), ("y", 0), ("y", ny // 2), ("y", ny - 1)]:
+        S = 1 << (slz if kind == "z" else sl)
+        sym = (zsym if kind == "z" else ysym)[k * S:(k + 1) * S]
+        idx = np.full(sym.size, entropy.K_Z) if kind == "z" else yidx[k * S:(k + 1) * S]
+        want = rans.encode(sym, idx, FREQ, CUM, S)
+        assert len(want) == 1
+        assert hdr[f"{kind}_segs"][k] == want[0], (kind, k)
+    # decode: indices and symbols over the whole latent, frames at windows
+    out = c.decode(bs, n, H, W).cpu().numpy()
+    np.testing.assert_array_equal(c.buffer(u.BUF_IDX, H, W), g_idx)
+    np.testing.assert_array_equal(c.buffer(u.BUF_SYM, H, W), g_sym)
+    assert np.isfinite(out).all() and out.min() >= 0 and out.max() <= 1
+    y_hat = chw(g_sym.astype(np.float32) - 32 + chw_inv(g_P[:C])).astype(np.float64)
+    worst, sq, cnt = 0.0, 0.0, 0
+    for r0, r1, c0, c1 in WINDOWS:
+        o = wn.synthesis_window(y_hat, w, T, H, W, r0, r1, c0, c1)
+        g = out[:, :, 8 * r0:8 * r0 + o.shape[2], 8 * c0:8 * c0 + o.shape[3]]
+        worst = max(worst, float(np.abs(g - o).max()))
+        sq += float(((g - o) ** 2).sum())
+        cnt += o.size
+    psnr = 10 * np.log10(cnt / sq) if sq else float("inf")
+    say(f"  frames at sampled windows: max abs {worst:.3e}, PSNR vs oracle {psnr:.2f} dB; "
+        f"{n} bytes")
+    if prec == "fp32":
+        assert worst <= 1e-3
+    else:
+        assert psnr >= 35
+    c.close()
+
+
+def chw_inv(a_chw):
+    return np.ascontiguousarray(np.transpose(a_chw, (1, 2, 0)))
+
+
+def test_fullsize_fp8_synthesis_sampled():
+    u = pkg()
+    fr, w = chunk()
+    say(f"full-size bf16_fp8: T={T} {W}x{H} C={C}")
+    c = u.Codec(T, C, w, precision="bf16_fp8", model_tag=0x0800_1080, autotune=True)
+    bs, n = c.encode(torch.from_numpy(fr).cuda())
+    out = c.decode(bs, n, H, W).cpu().numpy()
+    sym = c.buffer(u.BUF_SYM, H, W).astype(np.float32) - 32
+    mu = c.buffer(u.BUF_PARAMS, H, W)[..., :C]
+    y_hat = chw(sym + mu).astype(np.float64)
+    worst, sq, cnt = 0.0, 0.0, 0
+    for r0, r1, c0, c1 in WINDOWS:
+        o = wn.synthesis_window(y_hat, w, T, H, W, r0, r1, c0, c1)
+        g = out[:, :, 8 * r0:8 * r0 + o.shape[2], 8 * c0:8 * c0 + o.shape[3]]
+        worst = max(worst, float(np.abs(g - o).max()))
+        sq += float(((g - o) ** 2).sum())
+        cnt += o.size
+    psnr = 10 * np.log10(cnt / sq) if sq else float("inf")
+    say(f"  fp8 frames at sampled windows: max abs {worst:.3e}, PSNR vs oracle {psnr:.2f} dB")
+    assert np.isfinite(out).all() and psnr >= 20
+    c.close()
