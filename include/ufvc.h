@@ -195,6 +195,71 @@ int ufvc_decode_batch(ufvc_batch* b, ufvc_chunk* chunks, int n, int use_graph, v
 /* Synchronises `stream` and sets each chunk's decode status. */
 int ufvc_batch_sync_status(ufvc_batch* b, ufvc_chunk* chunks, int n, void* stream);
 
+/* ---- Request server: continuous batching over the batch executor ----
+ * Requests (encode or decode of one chunk) arrive from any thread at any
+ * time with ufvc_server_submit.  `lanes` executor threads each own a HIP
+ * stream (default priority) and a batch object; whenever a lane is free it
+ * forms the next batch from the queue in arrival order: the head request's
+ * kind, then further queued requests of that kind, up to `max_batch`, while
+ * (a) the chunks' working arena fits the lane's share of the HBM budget
+ * (hbm_budget / lanes) and (b) the HBM footprint of all admitted, unfinished
+ * requests stays within hbm_budget.  A request's footprint is its working
+ * arena plus its own device buffers (input and output).  Batches of
+ * different lanes run concurrently on the device, so requests that arrive
+ * while others are on the GPU join the next batch as lanes and memory free
+ * up.  Model weights, CDF tables, and the callers' frames and bit-streams
+ * stay resident; nothing is copied to the host except lengths and status.
+ * Results are bitwise those of ufvc_encode_chunk / ufvc_decode_chunk.
+ *
+ * Ownership: the caller keeps every request's buffers alive and untouched
+ * until its completion is polled.  Times are microseconds on a steady clock
+ * since the server was created: t_submit when ufvc_server_submit ran,
+ * t_admit when the request joined a batch, t_done when that batch's stream
+ * had finished. */
+typedef struct ufvc_server ufvc_server;
+typedef struct {
+  size_t hbm_budget;    /* bytes; 0 selects 64 GiB */
+  int lanes;            /* 1..8 concurrent batches */
+  int max_batch;        /* 1..64 chunks per batch */
+  int use_graph;        /* decode batches replay a captured hipGraph */
+} ufvc_server_config;
+enum { UFVC_REQ_ENCODE = 0, UFVC_REQ_DECODE = 1 };
+typedef struct {
+  int kind;             /* UFVC_REQ_ENCODE or UFVC_REQ_DECODE */
+  int model;            /* index into the server's models */
+  int H, W;
+  const float* frames;  /* encode: input frames, device [T][3][H][W] */
+  float* frames_out;    /* decode: output frames, device [T][3][H][W] */
+  uint8_t* bitstream;   /* encode: output buffer; decode: input stream (device) */
+  size_t capacity;      /* encode: bytes available at bitstream */
+  size_t len;           /* decode: stream bytes */
+  uint64_t tag;         /* caller's cookie, returned with the completion */
+} ufvc_request;
+typedef struct {
+  uint64_t ticket, tag;
+  int status;           /* UFVC_OK, UFVC_E_NOSPC (encode), UFVC_E_CORRUPT / INVAL (decode) */
+  int batch_size;       /* chunks in the batch that carried the request */
+  size_t len;           /* encode: coded bytes */
+  double t_submit_us, t_admit_us, t_done_us;
+} ufvc_completion;
+/* models: contexts that share C, precision and segment sizes, and outlive
+ * the server. */
+int ufvc_server_create(ufvc_ctx* const* models, int n_models, const ufvc_server_config* cfg,
+                       ufvc_server** out);
+/* Queues one request; never blocks on the GPU.  UFVC_E_INVAL for a bad
+ * model or size or missing buffer, UFVC_E_NOSPC when its footprint alone
+ * exceeds a lane's share of the budget. */
+int ufvc_server_submit(ufvc_server* s, const ufvc_request* req, uint64_t* ticket);
+/* Moves up to `max` completions to `out`, waiting up to timeout_ms for the
+ * first; returns their number (or a negative status). */
+int ufvc_server_poll(ufvc_server* s, ufvc_completion* out, int max, int timeout_ms);
+/* stats[0] requests queued, [1] in flight, [2] completed, [3] batches run,
+ * [4] peak admitted footprint (bytes), [5] HBM budget (bytes). */
+int ufvc_server_stats(ufvc_server* s, uint64_t* stats, int n);
+/* Finishes every queued and in-flight request, then frees the server
+ * (unpolled completions are dropped). */
+void ufvc_server_destroy(ufvc_server* s);
+
 /* ---- Conv tile configurations (autotuner) ----
  * ufvc_get_tuning writes, for the 9 tunable conv layers of a T x H x W chunk
  * (a1 a2 a3 d1 d2 d3 k1 k2 k3), the tile configuration chosen so far, or -1

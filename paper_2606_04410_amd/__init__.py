@@ -49,6 +49,25 @@ class _Chunk(ctypes.Structure):
                 ("len", ctypes.c_size_t), ("status", ctypes.c_int)]
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("lanes", ctypes.c_int),
+                ("max_batch", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("model", ctypes.c_int), ("H", ctypes.c_int),
+                ("W", ctypes.c_int), ("frames", ctypes.c_void_p), ("frames_out", ctypes.c_void_p),
+                ("bitstream", ctypes.c_void_p), ("capacity", ctypes.c_size_t),
+                ("len", ctypes.c_size_t), ("tag", ctypes.c_uint64)]
+
+
+class _Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int),
+                ("batch_size", ctypes.c_int), ("len", ctypes.c_size_t),
+                ("t_submit_us", ctypes.c_double), ("t_admit_us", ctypes.c_double),
+                ("t_done_us", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing; build it with python paper_2606_04410_amd/build.py")
@@ -78,6 +97,11 @@ def _load():
         "ufvc_encode_batch": (I, [P, P, I, P]),
         "ufvc_decode_batch": (I, [P, P, I, I, P]),
         "ufvc_batch_sync_status": (I, [P, P, I, P]),
+        "ufvc_server_create": (I, [P, I, ctypes.POINTER(_ServerConfig), ctypes.POINTER(P)]),
+        "ufvc_server_submit": (I, [P, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]),
+        "ufvc_server_poll": (I, [P, P, I, I]),
+        "ufvc_server_stats": (I, [P, P, I]),
+        "ufvc_server_destroy": (None, [P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -95,7 +119,10 @@ EXPORTS = ("ufvc_weight_count", "ufvc_create", "ufvc_destroy", "ufvc_max_bitstre
            "ufvc_rans_encode", "ufvc_rans_decode", "ufvc_synthesize", "ufvc_copy_buffer",
            "ufvc_profile_enable", "ufvc_profile_stage_count", "ufvc_profile_stage_name",
            "ufvc_profile_read", "ufvc_get_tuning", "ufvc_tile_config", "ufvc_batch_create",
-           "ufvc_batch_destroy", "ufvc_encode_batch", "ufvc_decode_batch", "ufvc_batch_sync_status")
+           "ufvc_batch_destroy", "ufvc_encode_batch", "ufvc_decode_batch", "ufvc_batch_sync_status",
+           "ufvc_server_create", "ufvc_server_submit", "ufvc_server_poll", "ufvc_server_stats",
+           "ufvc_server_destroy")
+REQ_ENCODE, REQ_DECODE = 0, 1
 TUNED_LAYERS = ("a1", "a2", "a3", "d1", "d2", "d3", "k1", "k2", "k3")
 
 
@@ -330,3 +357,69 @@ class Batch:
         arr = self._last
         code = lib.ufvc_batch_sync_status(self._h, arr, len(arr), _stream(stream))
         return [int(arr[i].status) for i in range(len(arr))], code
+
+
+class Server:
+    """Continuous-batching request server over one or more codecs (sharing C,
+    precision and segment sizes).  Requests carry device tensors that the
+    caller keeps alive until their completion is polled."""
+
+    def __init__(self, codecs, hbm_budget: int = 0, lanes: int = 2, max_batch: int = 8,
+                 graph: bool = True):
+        self.codecs = list(codecs)
+        arr = (ctypes.c_void_p * len(self.codecs))(*[c._h.value for c in self.codecs])
+        cfg = _ServerConfig(hbm_budget, lanes, max_batch, 1 if graph else 0)
+        h = ctypes.c_void_p()
+        _check(lib.ufvc_server_create(arr, len(self.codecs), ctypes.byref(cfg), ctypes.byref(h)),
+               "ufvc_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit_encode(self, model: int, frames, out, tag: int = 0) -> int:
+        r = _Request(REQ_ENCODE, model, frames.shape[2], frames.shape[3], _ptr(frames), None,
+                     _ptr(out), out.numel(), 0, tag)
+        return self._submit(r, (frames, out))
+
+    def submit_decode(self, model: int, bitstream, nbytes: int, H: int, W: int, out,
+                      tag: int = 0) -> int:
+        r = _Request(REQ_DECODE, model, H, W, None, _ptr(out), _ptr(bitstream), 0, nbytes, tag)
+        return self._submit(r, (bitstream, out))
+
+    def _submit(self, r, keep) -> int:
+        t = ctypes.c_uint64()
+        _check(lib.ufvc_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)), "ufvc_server_submit")
+        self._keep[t.value] = keep
+        return t.value
+
+    def poll(self, max_n: int = 64, timeout_ms: int = 100):
+        """Completions as dicts (ticket, tag, status, batch_size, len, times in us)."""
+        arr = (_Completion * max_n)()
+        k = lib.ufvc_server_poll(self._h, arr, max_n, timeout_ms)
+        if k < 0:
+            _check(k, "ufvc_server_poll")
+        out = []
+        for i in range(k):
+            c = arr[i]
+            self._keep.pop(c.ticket, None)
+            out.append(dict(ticket=c.ticket, tag=c.tag, status=c.status, batch_size=c.batch_size,
+                            len=c.len, t_submit_us=c.t_submit_us, t_admit_us=c.t_admit_us,
+                            t_done_us=c.t_done_us))
+        return out
+
+    def stats(self):
+        v = (ctypes.c_uint64 * 6)()
+        _check(lib.ufvc_server_stats(self._h, v, 6), "ufvc_server_stats")
+        return dict(queued=v[0], in_flight=v[1], completed=v[2], batches=v[3],
+                    peak_footprint=v[4], budget=v[5])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.ufvc_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

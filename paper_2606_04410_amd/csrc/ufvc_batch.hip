@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -52,6 +53,7 @@ struct ufvc_batch {
     std::vector<ChunkPlan> chunks;
     uint8_t* arena = nullptr;
     size_t arena_bytes = 0;
+    bool owns_arena = true;        // false: the batch object's shared arena
     // descriptor blob (device) and its host mirror
     uint8_t* dblob = nullptr;
     std::vector<uint8_t> hblob;
@@ -79,6 +81,12 @@ struct ufvc_batch {
   unsigned long long* results_host = nullptr;
   uint32_t* status_host = nullptr;
   int host_cap = 0;
+  // shared-arena mode (arena_cap > 0): every plan lays its chunks out from the
+  // start of one arena, grown on demand up to arena_cap; calls on a batch
+  // object are stream-ordered, so plans never use it at the same time
+  size_t arena_cap = 0;
+  uint8_t* shared = nullptr;
+  size_t shared_bytes = 0;
 };
 
 namespace {
@@ -90,7 +98,7 @@ void free_plan(ufvc_batch::Plan* p) {
   if (!p) return;
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
-  if (p->arena) (void)hipFree(p->arena);
+  if (p->arena && p->owns_arena) (void)hipFree(p->arena);
   if (p->dblob) (void)hipFree(p->dblob);
 }
 
@@ -131,45 +139,79 @@ void add_stage(ufvc_batch::Plan& P, ConvStage& st, std::vector<ConvArgs>& descs,
   (void)P;
 }
 
+// Places one chunk's buffers in an arena at `off` (advanced past them).
+int layout_chunk(ufvc_ctx* c, int model, int H, int W, ChunkPlan& cp, size_t& off) {
+  const int C = c->cfg.C;
+  const int es = act_elem_size(c->cfg.precision);
+  auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
+  cp = ChunkPlan{};
+  cp.model = model;
+  cp.T = c->cfg.T;
+  cp.H = H;
+  cp.W = W;
+  if (!geom(c, cp.H, cp.W, cp.g)) return UFVC_E_INVAL;
+  const size_t npos = (size_t)cp.g.h * cp.g.w;
+  cp.slot_z = slot_bytes(c->cfg.seg_log2_z);
+  cp.slot_y = slot_bytes(c->cfg.seg_log2);
+  cp.act0 = take(npos * C * es);
+  cp.act1 = take(npos * C * es);
+  cp.y = take(npos * C * 4);
+  cp.zsym = take((size_t)cp.g.nz + CODER_PAD);
+  cp.P = take(npos * 2 * C * 4);
+  cp.idx = take(npos * C + CODER_PAD);
+  cp.sym = take(npos * C + CODER_PAD);
+  cp.big0 = take(npos * C * cp.T * es);
+  cp.big1 = take(npos * C * cp.T * es);
+  cp.scratch = take(cp.slot_z * cp.g.nseg_z + cp.slot_y * cp.g.nseg_y);
+  const int nseg = cp.g.nseg_z + cp.g.nseg_y;
+  cp.info = take(sizeof(SegInfo) * nseg);
+  cp.seg_off = take(4 * (size_t)nseg);
+  cp.seg_len = take(4 * (size_t)nseg);
+  return UFVC_OK;
+}
+
+// Arena for the plan: its own allocation, or the shared arena (grown, which
+// drops the plans laid out in the old one).
+int plan_arena(ufvc_batch* b, ufvc_batch::Plan& P) {
+  if (!b->arena_cap) {
+    if (hipMalloc(&P.arena, P.arena_bytes) != hipSuccess) return UFVC_E_NOMEM;
+    return UFVC_OK;
+  }
+  if (P.arena_bytes > b->arena_cap) return UFVC_E_NOSPC;
+  if (P.arena_bytes > b->shared_bytes) {
+    (void)hipDeviceSynchronize();
+    for (auto& kv : b->plans) free_plan(kv.second.get());
+    b->plans.clear();
+    if (b->shared) (void)hipFree(b->shared);
+    b->shared = nullptr;
+    b->shared_bytes = 0;
+    const size_t want = std::min(b->arena_cap, align_up(P.arena_bytes + P.arena_bytes / 4));
+    if (hipMalloc(&b->shared, want) != hipSuccess) return UFVC_E_NOMEM;
+    b->shared_bytes = want;
+  }
+  P.arena = b->shared;
+  P.owns_arena = false;
+  return UFVC_OK;
+}
+
 int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan& P) {
   ufvc_ctx* m0 = b->models[0];
   const int C = m0->cfg.C;
-  const int es = act_elem_size(m0->cfg.precision);
   const int sl = m0->cfg.seg_log2, slz = m0->cfg.seg_log2_z;
   // arena layout
   size_t off = 0;
-  auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
   for (int i = 0; i < n; ++i) {
-    ChunkPlan cp{};
-    cp.model = chunks[i].model;
-    ufvc_ctx* c = b->models[cp.model];
-    cp.T = c->cfg.T;
-    cp.H = chunks[i].H;
-    cp.W = chunks[i].W;
-    if (!geom(c, cp.H, cp.W, cp.g)) return UFVC_E_INVAL;
-    const size_t npos = (size_t)cp.g.h * cp.g.w;
-    cp.slot_z = slot_bytes(slz);
-    cp.slot_y = slot_bytes(sl);
-    cp.act0 = take(npos * C * es);
-    cp.act1 = take(npos * C * es);
-    cp.y = take(npos * C * 4);
-    cp.zsym = take((size_t)cp.g.nz + CODER_PAD);
-    cp.P = take(npos * 2 * C * 4);
-    cp.idx = take(npos * C + CODER_PAD);
-    cp.sym = take(npos * C + CODER_PAD);
-    cp.big0 = take(npos * C * cp.T * es);
-    cp.big1 = take(npos * C * cp.T * es);
-    cp.scratch = take(cp.slot_z * cp.g.nseg_z + cp.slot_y * cp.g.nseg_y);
-    const int nseg = cp.g.nseg_z + cp.g.nseg_y;
-    cp.info = take(sizeof(SegInfo) * nseg);
-    cp.seg_off = take(4 * (size_t)nseg);
-    cp.seg_len = take(4 * (size_t)nseg);
+    ChunkPlan cp;
+    const int rc = layout_chunk(b->models[chunks[i].model], chunks[i].model, chunks[i].H,
+                                chunks[i].W, cp, off);
+    if (rc) return rc;
     P.chunks.push_back(cp);
   }
   // fp8 amax slots of all chunks, cleared together before every decode
-  P.off_amax = take(4 * (size_t)N_AMAX * n);
+  P.off_amax = off;
+  off = align_up(off + 4 * (size_t)N_AMAX * n);
   P.arena_bytes = off;
-  if (hipMalloc(&P.arena, P.arena_bytes) != hipSuccess) return UFVC_E_NOMEM;
+  if (const int rc = plan_arena(b, P)) return rc;
   uint8_t* A = P.arena;
   const int cp_prec = conv_prec(m0->cfg.precision);
   const int sp = synth_prec(m0->cfg.precision);
@@ -541,6 +583,10 @@ int get_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, hipStream_t s, ufvc
     *out = it->second.get();
     return UFVC_OK;
   }
+  // tuning runs single-chunk calls on the shared model contexts, and plans
+  // read their tuning maps: one plan build at a time across batch objects
+  static std::mutex build_mu;
+  std::lock_guard<std::mutex> lock(build_mu);
   int rc = tune_buckets(b, chunks, n, s);
   if (rc) return rc;
   std::unique_ptr<ufvc_batch::Plan> P(new (std::nothrow) ufvc_batch::Plan());
@@ -567,6 +613,19 @@ int get_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, hipStream_t s, ufvc
 }
 
 }  // namespace
+
+int batch_set_arena_cap(ufvc_batch* b, size_t cap) {
+  if (!b || !b->plans.empty() || b->arena_cap) return UFVC_E_INVAL;
+  b->arena_cap = cap;
+  return UFVC_OK;
+}
+
+size_t batch_chunk_footprint(ufvc_ctx* c, int H, int W) {
+  ChunkPlan cp;
+  size_t off = 0;
+  if (layout_chunk(c, 0, H, W, cp, off)) return 0;
+  return off + ALIGN;  // + a share of the per-batch amax block
+}
 
 extern "C" {
 
@@ -598,6 +657,7 @@ void ufvc_batch_destroy(ufvc_batch* b) {
   if (!b) return;
   (void)hipDeviceSynchronize();
   for (auto& kv : b->plans) free_plan(kv.second.get());
+  if (b->shared) (void)hipFree(b->shared);
   if (b->staging) (void)hipHostFree(b->staging);
   if (b->results_host) (void)hipHostFree(b->results_host);
   if (b->status_host) (void)hipHostFree(b->status_host);

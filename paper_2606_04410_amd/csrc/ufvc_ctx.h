@@ -149,3 +149,10 @@ inline ConvArgs conv_args(int Hin, int Win, int Hout, int Wout, const Layer& L) 
 // Tile configuration: the widest channel tile that divides the layer's outputs.
 
 }  // namespace ufvc
+
+// Batch executor hooks used by the request server (defined in ufvc_batch.hip).
+// Shared-arena mode: every plan of `b` lays its chunks out in one arena of at
+// most `cap` bytes, grown on demand (call before the first batch).
+int batch_set_arena_cap(ufvc_batch* b, size_t cap);
+// Arena bytes one chunk of model `c` at H x W takes in a batch (0: invalid size).
+size_t batch_chunk_footprint(ufvc_ctx* c, int H, int W);
