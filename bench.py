@@ -234,6 +234,89 @@ def run_fp8_c4(torch, ufvc, steps, seg_log2, seg_log2_z, n_chunks=16):
     return res
 
 
+C5_MIX = [(21, 832, 480), (21, 1280, 720), (16, 1920, 1088), (6, 3840, 2160)]
+
+
+def run_serving(torch, ufvc, prec, mix, seconds, rate, seg_log2, seg_log2_z, seed=5,
+                lanes=2, max_batch=8):
+    """Open-loop serving: 64 streams (resolution mix), Poisson arrivals of
+    `rate` chunk requests/s for `seconds`, 70% decode / 30% encode, T = 8,
+    C = 128.  Inputs and bit-streams are resident in HBM before the clock
+    starts; the server admits requests within a 64 GiB footprint."""
+    import threading
+    from synthetic import stand_in_weights, video_chunk
+    T, C = 8, 128
+    codec = ufvc.Codec(T, C, stand_in_weights(T, C), precision=prec, seg_log2=seg_log2,
+                       seg_log2_z=seg_log2_z, model_tag=0x0C50_0000, autotune=True)
+    streams = [(W, H) for count, W, H in mix for _ in range(count)]
+    res = sorted(set(streams))
+    src, bits = {}, {}
+    for k, (W, H) in enumerate(res):
+        fr = torch.from_numpy(video_chunk(T, H, W, 16, seed=seed, chunk_id=k)).cuda()
+        bs, n = codec.encode(fr)              # also tunes this size's tiles
+        codec.decode(bs, n, H, W)
+        src[(W, H)], bits[(W, H)] = fr, (bs[:n].clone(), n)
+    enc_out = [torch.empty(codec.max_bitstream_bytes(H, W), dtype=torch.uint8, device="cuda")
+               for (W, H) in streams]
+    dec_out = [torch.empty((T, 3, H, W), dtype=torch.float32, device="cuda") for (W, H) in streams]
+    srv = ufvc.Server([codec], hbm_budget=64 << 30, lanes=lanes, max_batch=max_batch, graph=True)
+
+    def submit(i, kind):
+        W, H = streams[i]
+        if kind == "enc":
+            return srv.submit_encode(0, src[(W, H)], enc_out[i], tag=i)
+        bs, n = bits[(W, H)]
+        return srv.submit_decode(0, bs, n, H, W, dec_out[i], tag=i)
+
+    # warm-up burst: plans and arenas for the common compositions
+    warm = [submit(i % len(streams), "dec" if i % 3 else "enc") for i in range(4 * max_batch)]
+    got = 0
+    while got < len(warm):
+        got += len(srv.poll(64, 200))
+    rng = np.random.default_rng(seed)
+    n_req = int(rng.poisson(rate * seconds))
+    t_arr = np.sort(rng.uniform(0.0, seconds, n_req))
+    who = rng.integers(0, len(streams), n_req)
+    kinds = np.where(rng.uniform(size=n_req) < 0.7, "dec", "enc")
+    comps = []
+
+    def poller():
+        while len(comps) < n_req:
+            comps.extend(srv.poll(256, 200))
+
+    th = threading.Thread(target=poller)
+    th.start()
+    t0 = time.perf_counter()
+    for k in range(n_req):
+        dt = t0 + t_arr[k] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        submit(int(who[k]), kinds[k])
+    th.join()
+    st = srv.stats()
+    srv.close()
+    codec.close()
+    bad = sum(1 for c in comps if c["status"] != 0)
+    if bad:
+        raise RuntimeError(f"{bad} serving requests failed")
+    lat = np.array([(c["t_done_us"] - c["t_submit_us"]) / 1e3 for c in comps])
+    first = min(c["t_submit_us"] for c in comps)
+    last = max(c["t_done_us"] for c in comps)
+    pix = {i: streams[i][0] * streams[i][1] for i in range(len(streams))}
+    frames = T * n_req
+    return {"precision": prec, "requests": n_req, "seconds": seconds, "rate_req_s": rate,
+            "value": round(frames / ((last - first) / 1e6), 2), "unit": "frames/s",
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                           "p99": round(float(np.percentile(lat, 99)), 3),
+                           "max": round(float(lat.max()), 3)},
+            "decode_share": round(float(np.mean(kinds == "dec")), 3),
+            "mean_batch": round(float(np.mean([c["batch_size"] for c in comps])), 2),
+            "batches": int(st["batches"]), "lanes": lanes, "max_batch": max_batch,
+            "peak_footprint_gib": round(st["peak_footprint"] / 2 ** 30, 3),
+            "budget_gib": round(st["budget"] / 2 ** 30, 1),
+            "mpix_per_s": round(sum(pix[int(i)] for i in who) * T / ((last - first) / 1e6) / 1e6, 1)}
+
+
 def bitstream_report(r, h, w, C, sl, slz):
     """Stream size against the ideal code length: the literal reading (whole
     stream within 0.5%) and the per-segment reading (payload within 0.5% plus
@@ -255,8 +338,9 @@ def psnr_t(torch, a, b):
     return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
 
 
-def cpu_baseline(T, H, W, C):
-    """The oracle, untouched, on one full chunk of the same workload."""
+def cpu_baseline(T, H, W, C, n_chunks=3):
+    """The oracle, untouched, on `n_chunks` full chunks of the same workload
+    (about 10-30 s of host work)."""
     from oracle import codec as ocodec
     from synthetic import stand_in_weights, video_chunk
     try:
@@ -264,16 +348,17 @@ def cpu_baseline(T, H, W, C):
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
         threads = 1
-    fr = video_chunk(T, H, W, 16, seed=1, chunk_id=0)
     w = stand_in_weights(T, C)
+    frames = [video_chunk(T, H, W, 16, seed=1, chunk_id=k) for k in range(n_chunks)]
     t0 = time.perf_counter()
-    bs, _ = ocodec.encode_chunk(fr, w, seg_log2=15, seg_log2_z=11, model_tag=0x0800_1080)
-    x_hat, _ = ocodec.decode_chunk(bs, w)
+    for fr in frames:
+        bs, _ = ocodec.encode_chunk(fr, w, seg_log2=15, seg_log2_z=11, model_tag=0x0800_1080)
+        ocodec.decode_chunk(bs, w)
     dt = time.perf_counter() - t0
-    return {"value": T / dt, "unit": "frames/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one {W}x{H} T={T} chunk (generator chunk 0): float64 oracle encode + "
-                      f"decode, {dt:.1f} s; BLAS threads {threads}, rANS loop single-threaded, "
-                      f"host cpus {len(os.sched_getaffinity(0))}"}
+    return {"value": T * n_chunks / dt, "unit": "frames/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_chunks} {W}x{H} T={T} chunks (generator chunks 0-{n_chunks - 1}): "
+                      f"float64 oracle encode + decode, {dt:.1f} s; BLAS threads {threads}, "
+                      f"rANS loop single-threaded, host cpus {len(os.sched_getaffinity(0))}"}
 
 
 def main():
@@ -289,6 +374,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-fp8", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -384,6 +471,14 @@ def main():
         log("bench: fp8 synthesis, 16 chunks")
         result["fp8_c4"] = run_fp8_c4(torch, ufvc, args.batch_steps, args.seg_log2,
                                       args.seg_log2_z)
+    if not args.no_serve:
+        serving = {}
+        for name, mix in (("mix", C5_MIX), ("all_1080p", [(64, 1920, 1088)])):
+            for prec in ("bf16", "fp32"):
+                log(f"bench: serving {name} {prec}")
+                serving[f"{name}_{prec}"] = run_serving(torch, ufvc, prec, mix, args.serve_seconds,
+                                                        240.0, args.seg_log2, args.seg_log2_z)
+        result["serving"] = serving
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(T, H, W, C)
