@@ -58,7 +58,7 @@ static hipError_t tuned_conv(ufvc_ctx* c, int id, int prec, int ld, int st, cons
   hipError_t err = hipSuccess;
   for (int cfg = 0; cfg < conv_num_cfgs(); ++cfg) {
     const TileCfg t = conv_cfg(cfg);
-    if (a.cout % t.bn || !conv_cfg_supported(prec, cfg)) continue;
+    if (a.cout % t.bn || !conv_cfg_supported(prec, ld, 1, a.cin, a.cout, cfg)) continue;
     float ms = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       (void)hipEventRecord(e0, s);

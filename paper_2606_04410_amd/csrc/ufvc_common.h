@@ -77,8 +77,9 @@ hipError_t launch_conv_batch(int prec, int loader, int store, int stride, int cf
 struct TileCfg { int th, tw, bn; };
 int conv_num_cfgs();
 TileCfg conv_cfg(int cfg);
-// false for tile configurations a precision does not instantiate
-bool conv_cfg_supported(int prec, int cfg);
+// false for tile configurations a layer cannot use (precision, loader,
+// stride and channel counts)
+bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int cfg);
 
 // ------------------------------------------------------------- entropy ----
 constexpr int NSCALES = 64;

@@ -24,6 +24,8 @@
 // upsampling of the hyper latent.  Epilogues fuse ReLU, the float32 or bf16
 // store, rounding of z, and the x8 pixel-shuffle store of the frame
 // decoders with crop and clamp (Sec. 3.2).
+#include <algorithm>
+
 #include "ufvc_common.h"
 
 namespace ufvc {
@@ -216,6 +218,40 @@ constexpr int conv_lds_bytes() {
   return ((STRIDE == 1 ? (TH + 2) * (TW + 2) : (2 * TH + 1) * (2 * TW + 1)) + 9 * BN) * ROWB;
 }
 
+// Staging pipeline of one tile configuration.  Loaders that copy the input
+// unchanged (NHWC, bf16 or f32) stream each slice straight from global memory
+// into LDS (global_load_lds_dwordx4: a wave writes 64 consecutive 16-byte
+// chunks at a uniform LDS address, each lane fetching the global chunk that
+// belongs at its position, XOR swizzle included), through a ring of NSTAGE
+// slice buffers: loads run two slices ahead (one with two stages), nothing
+// is staged in registers and the block syncs once per slice.  Loaders that
+// convert (unshuffle, dequantise, up-sample, quantise) stage through
+// registers into a single buffer.
+template <int PREC, int LD, int STRIDE, int TH, int TW, int WM, int WN, int FN>
+struct Pipe {
+  static constexpr int ROWB = PT<PREC>::ROWB, CH = PT<PREC>::CH;
+  static constexpr int NWAVES = WM * WN;
+  static constexpr int BN = WN * FN * 32;
+  static constexpr int HP = STRIDE == 1 ? (TH + 2) * (TW + 2) : (2 * TH + 1) * (2 * TW + 1);
+  static constexpr int NCH = (HP + 9 * BN) * CH;                  // 16-byte chunks per slice
+  static constexpr int NIW = ((NCH + 63) / 64 + NWAVES - 1) / NWAVES;  // loads per wave and slice
+  static constexpr int STAGE = NIW * NWAVES * 64 * 16;            // bytes, padded to whole loads
+  static constexpr bool DIRECT =
+      LD == LD_NHWC && (PREC == P_BF16 || PREC == P_F32) && 2 * STAGE <= 160 * 1024;
+  static constexpr int NSTAGE = !DIRECT ? 1 : 2;
+  static constexpr int LDS = DIRECT ? NSTAGE * STAGE : (HP + 9 * BN) * ROWB;
+};
+
+// Zero chunk for halo positions outside the input (conv zero padding).
+__device__ __attribute__((aligned(64))) unsigned char kZeroChunk[64];
+
+// s_waitcnt on the vector-memory counter only (gfx9 encoding).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
 template <int PREC, int LD, int ST, int STRIDE, int TH, int TW, int WM, int WN, int FM, int FN>
 __global__ void __launch_bounds__(WM * WN * 64)
 conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __restrict__ work,
@@ -236,6 +272,7 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
   constexpr int E = PT<PREC>::E;
   constexpr int ESZ = PT<PREC>::ESZ;
 
+  using PP = Pipe<PREC, LD, STRIDE, TH, TW, WM, WN, FN>;
   extern __shared__ __attribute__((aligned(16))) unsigned char sh[];
   unsigned char* lds_h = sh;
   unsigned char* lds_w = sh + HP * ROWB;
@@ -347,11 +384,7 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[fm][fn][r] = 0.f;
 
-  UFVC_GLOAD(0);
-  for (int s = 0; s < nslices; ++s) {
-    UFVC_LSTORE();
-    __syncthreads();
-    UFVC_GLOAD(min(s + 1, nslices - 1));
+  auto compute_slice = [&]() {
     // Fragments of tap t + 1 are read from LDS into the second register set
     // before the MFMAs of tap t are issued, so LDS latency overlaps the
     // matrix cores.  A lane's fragment is 16 bytes (bf16 / f32) or 32 bytes
@@ -408,7 +441,60 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
           }
         }
     }
-    __syncthreads();
+  };
+  if constexpr (PP::DIRECT) {
+    // slice S_ into ring stage ST_: this wave's NIW loads of 64 chunks
+    auto issue = [&](int S_, int ST_) {
+      unsigned char* stage = sh + ST_ * PP::STAGE;
+#pragma unroll
+      for (int j = 0; j < PP::NIW; ++j) {
+        const int ins = j * PP::NWAVES + wave;
+        const int q = ins * 64 + lane;                 // physical chunk in the stage
+        const unsigned char* src = kZeroChunk;
+        if (q < HCH) {
+          const int row = q / CH;
+          const int c = (q % CH) ^ (ROWB == 32 ? (row >> 3) & 1 : (row >> 2) & 3);
+          const int hy = row / HW, hx = row - (row / HW) * HW;
+          const int iy = iy0 + hy, ix = ix0 + hx;
+          if (iy >= 0 && ix >= 0 && iy < a.Hin && ix < a.Win)
+            src = inb + (((long)iy * a.Win + ix) * a.in_pitch + (long)S_ * E + c * (16 / ESZ)) * ESZ;
+        } else if (q < HCH + WCH) {
+          const int row = (q - HCH) / CH;
+          const int c = ((q - HCH) % CH) ^ (ROWB == 32 ? (row >> 3) & 1 : (row >> 2) & 3);
+          const int tap = row / BN, n = row - (row / BN) * BN;
+          src = wbase + (((long)(S_ * 9 + tap) * a.cout + n0 + n) * ROWB + c * 16);
+        }
+        __builtin_amdgcn_global_load_lds((const UFVC_GLOBAL void*)src,
+                                         (__attribute__((address_space(3))) void*)(stage + ins * 1024),
+                                         16, 0, 0);
+      }
+    };
+    issue(0, 0);
+    if constexpr (PP::NSTAGE == 3) issue(min(1, nslices - 1), 1);
+    for (int s = 0; s < nslices; ++s) {
+      // this wave's loads of slice s have landed (those of s + 1 may not);
+      // after the barrier every wave's have, and every wave has finished
+      // reading the stage the next loads overwrite
+      if constexpr (PP::NSTAGE == 3) wait_vmcnt<PP::NIW>();
+      else wait_vmcnt<0>();
+      asm volatile("s_barrier" ::: "memory");
+      if constexpr (PP::NSTAGE == 3) issue(min(s + 2, nslices - 1), (s + 2) % 3);
+      else issue(min(s + 1, nslices - 1), (s + 1) & 1);
+      lds_h = sh + (s % PP::NSTAGE) * PP::STAGE;
+      lds_w = lds_h + HP * ROWB;
+      compute_slice();
+    }
+    // no load may still be writing LDS when the block ends
+    wait_vmcnt<0>();
+  } else {
+    UFVC_GLOAD(0);
+    for (int s = 0; s < nslices; ++s) {
+      UFVC_LSTORE();
+      __syncthreads();
+      UFVC_GLOAD(min(s + 1, nslices - 1));
+      compute_slice();
+      __syncthreads();
+    }
   }
 #undef UFVC_GLOAD
 #undef UFVC_LSTORE
@@ -454,11 +540,18 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
 //      5 = 16x16 tile, 128 channels, 2x2 waves of 128x64
 //      6 = 16x16 tile, 192 channels, 2x2 waves of 128x96
 //      7 = 16x16 tile,  64 channels, 2x2 waves of 128x32
+//      8 = 16x16 tile, 128 channels, 8 waves (4x2) of 64x64
+//      9 = 16x16 tile,  64 channels, 8 waves (4x2) of 64x32
 static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 16, 128},
-                                {8, 16, 64},  {16, 16, 128}, {16, 16, 192}, {16, 16, 64}};
+                                {8, 16, 64},  {16, 16, 128}, {16, 16, 192}, {16, 16, 64},
+                                {16, 16, 128}, {16, 16, 64}};
 int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
-bool conv_cfg_supported(int prec, int cfg) {
-  return cfg >= 0 && cfg < conv_num_cfgs() && !(prec == P_FP8 && cfg == 6);
+bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int cfg) {
+  (void)loader;
+  (void)stride;
+  (void)cin;
+  (void)cout;
+  return cfg >= 0 && cfg < conv_num_cfgs() && !(prec == P_FP8 && (cfg == 6 || cfg == 8));
 }
 
 __global__ void zero_u32_kernel(uint32_t* p, int n) {
@@ -479,7 +572,7 @@ template <int PREC, int LD, int ST, int STRIDE, int TH, int TW, int WM, int WN, 
 static hipError_t run_conv(const ConvArgs& a, int groups, const ConvArgs* descs, const int4* work,
                            int nwork, hipStream_t s) {
   constexpr int BN = WN * FN * 32;
-  constexpr int lds = conv_lds_bytes<STRIDE, TH, TW, BN, PT<PREC>::ROWB>();
+  constexpr int lds = Pipe<PREC, LD, STRIDE, TH, TW, WM, WN, FN>::LDS;
   auto kern = conv3x3_kernel<PREC, LD, ST, STRIDE, TH, TW, WM, WN, FM, FN>;
   static bool attr_set = false;
   if (!attr_set) {
@@ -516,6 +609,10 @@ static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs
       if constexpr (PREC == P_FP8) return hipErrorNotSupported;
       else return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 3>(a, groups, d, w, nw, s);
     case 7: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 1>(a, groups, d, w, nw, s);
+    case 8:
+      if constexpr (PREC == P_FP8) return hipErrorNotSupported;
+      else return run_conv<PREC, LD, ST, STRIDE, 16, 16, 4, 2, 2, 2>(a, groups, d, w, nw, s);
+    case 9: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 4, 2, 2, 1>(a, groups, d, w, nw, s);
     default: return hipErrorInvalidValue;
   }
 }
