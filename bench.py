@@ -132,6 +132,56 @@ def run_codec(torch, ufvc, weights, prec, chunks, H, W, steps, warmup, seg_log2,
                 y_bytes=int(table[n_seg_z:].sum()))
 
 
+def run_pipelined(torch, ufvc, weights, prec, chunks, H, W, steps, warmup, seg_log2, seg_log2_z,
+                  lanes=2):
+    """The same step (encode one chunk, then decode its stream) with `lanes`
+    chunks in flight: one codec context, HIP stream and host thread per lane,
+    so one chunk's latency-bound entropy coding overlaps another's convs."""
+    import threading
+    T = chunks[0].shape[0]
+    codecs = [ufvc.Codec(T, 128, weights, precision=prec, seg_log2=seg_log2, seg_log2_z=seg_log2_z,
+                         model_tag=0x0800_1080, autotune=True) for _ in range(lanes)]
+    streams = [torch.cuda.Stream() for _ in range(lanes)]
+    cap = codecs[0].max_bitstream_bytes(H, W)
+    bufs = [[torch.empty(cap, dtype=torch.uint8, device="cuda") for _ in chunks] for _ in range(lanes)]
+    outs = [torch.empty((T, 3, H, W), dtype=torch.float32, device="cuda") for _ in range(lanes)]
+    per = steps // lanes
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(per)] for _ in range(lanes)]
+
+    def lane(li, n, timed):
+        c, st = codecs[li], streams[li]
+        for i in range(n):
+            k = (li + i * lanes) % len(chunks)
+            if timed:
+                ev[li][i][0].record(st)
+            _, nb = c.encode(chunks[k], out=bufs[li][k], stream=st)
+            c.decode(bufs[li][k], nb, H, W, out=outs[li], stream=st, check=False)
+            if timed:
+                ev[li][i][1].record(st)
+
+    def run(n, timed):
+        ths = [threading.Thread(target=lane, args=(li, n, timed)) for li in range(lanes)]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+
+    run(max(1, warmup), False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(per, True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for li, c in enumerate(codecs):
+        if c.status(streams[li]) != 0:
+            raise RuntimeError("decode reported an error in the pipelined run")
+    lat = np.array([a.elapsed_time(b) for lv in ev for a, b in lv])
+    for c in codecs:
+        c.close()
+    return dict(seconds=t1 - t0, steps=per * lanes, lat=lat)
+
+
 C3_MIX = [(16, 832, 480), (16, 1280, 720), (12, 1920, 1088), (4, 3840, 2160)]
 
 
@@ -436,7 +486,11 @@ def main():
         r32 = run_codec(torch, ufvc, weights, "fp32", chunks, H, W, args.fp32_steps, 2,
                         args.seg_log2, args.seg_log2_z, profile=True, autotune=not args.no_autotune)
 
+    log("bench: bf16 pipelined (two chunks in flight)")
+    rp = run_pipelined(torch, ufvc, weights, "bf16", chunks, H, W, args.steps, args.warmup,
+                       args.seg_log2, args.seg_log2_z)
     fps16 = T * args.steps / r16["seconds"]
+    fps_pipe = T * rp["steps"] / rp["seconds"]
     src0 = chunks[0]
     p16 = psnr_t(torch, src0, r16["rec"])
 
@@ -466,18 +520,25 @@ def main():
     dec_ms = sum(v for k, v in stage_ms.items() if k not in enc_stages)
 
     result = {
-        "metric": METRIC, "value": round(fps16, 2), "unit": "frames/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(1e3 * r16["seconds"] / args.steps, 4),
+        "metric": METRIC, "value": round(fps_pipe, 2), "unit": "frames/s", "n_gpus": 1,
+        "steps": rp["steps"], "warmup": args.warmup,
+        "ms_per_step": round(1e3 * rp["seconds"] / rp["steps"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": f"1080p chunk codec: T={T} frames {W}x{H} (padded {Hp}), C={C}, "
-                               f"encode+decode per step", "T": T, "H": H, "W": W, "C": C,
+                               f"encode+decode per step, two chunks in flight", "T": T, "H": H,
+                   "W": W, "C": C, "chunks_in_flight": 2,
                    "seg_log2": args.seg_log2, "seg_log2_z": args.seg_log2_z,
                    "chunks_cycled": args.chunks, "precision": "bf16 convs, fp32 entropy params, "
                                                           "fp64 tables"},
-        "latency_ms": {"p50": round(float(np.percentile(r16["lat"], 50)), 4),
-                       "p99": round(float(np.percentile(r16["lat"], 99)), 4)},
+        "latency_ms": {"p50": round(float(np.percentile(rp["lat"], 50)), 4),
+                       "p99": round(float(np.percentile(rp["lat"], 99)), 4)},
+        "sequential": {"value": round(fps16, 2), "unit": "frames/s", "steps": args.steps,
+                       "ms_per_step": round(1e3 * r16["seconds"] / args.steps, 4),
+                       "latency_ms": {"p50": round(float(np.percentile(r16["lat"], 50)), 4),
+                                      "p99": round(float(np.percentile(r16["lat"], 99)), 4)},
+                       "note": "one chunk at a time on one stream (the paper's chunk-by-chunk "
+                               "order); also the run the per-stage timings come from"},
         "roofline": roof,
         "entropy_gbs": hbm_gbs,
         "conv_stack": {"tflop_per_step": round(conv_flop / 1e12, 4), "ms_per_step": round(conv_ms, 4),
