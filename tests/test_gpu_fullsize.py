@@ -165,3 +165,40 @@ def test_fullsize_fp8_synthesis_sampled():
     say(f"  fp8 frames at sampled windows: max abs {worst:.3e}, PSNR vs oracle {psnr:.2f} dB")
     assert np.isfinite(out).all() and psnr >= 20
     c.close()
+
+
+def test_4k_chunk_sampled_parity_bf16():
+    """The largest size of the batch mix (3840x2160, T = 8) on the BF16 path:
+    y and frames at sampled windows against the oracle, decoder indices and
+    symbols equal to the encoder's over the whole latent."""
+    u = pkg()
+    H4, W4 = 2160, 3840
+    fr = video_chunk(T, H4, W4, 16, seed=9, chunk_id=0)
+    w = stand_in_weights(T, C)
+    say(f"full-size 4K bf16: T={T} {W4}x{H4}")
+    c = u.Codec(T, C, w, precision="bf16", model_tag=0x0800_2160, autotune=True)
+    bs, n = c.encode(torch.from_numpy(fr).cuda())
+    h, ww, _, _ = ocodec.latent_size(H4, W4)
+    g_y = chw(c.buffer(u.BUF_Y, H4, W4)).astype(np.float64)
+    g_sym, g_idx = c.buffer(u.BUF_SYM, H4, W4), c.buffer(u.BUF_IDX, H4, W4)
+    wins = [(0, 4, 0, 4), (266, 270, 476, 480), (131, 135, 233, 237)]
+    ymax = float(np.abs(g_y).max())
+    worst = max(float(np.abs(g_y[:, a:b, c0:c1] - wn.analysis_window(fr, w, h, ww, a, b, c0, c1)).max())
+                for a, b, c0, c1 in wins)
+    say(f"  y max abs {worst:.3e} (max |y| {ymax:.2f})")
+    assert worst <= 0.02 * ymax
+    mu = c.buffer(u.BUF_PARAMS, H4, W4)[..., :C]
+    out = c.decode(bs, n, H4, W4).cpu().numpy()
+    np.testing.assert_array_equal(c.buffer(u.BUF_SYM, H4, W4), g_sym)
+    np.testing.assert_array_equal(c.buffer(u.BUF_IDX, H4, W4), g_idx)
+    y_hat = chw(g_sym.astype(np.float32) - 32 + mu).astype(np.float64)
+    sq, cnt = 0.0, 0
+    for a, b, c0, c1 in wins:
+        o = wn.synthesis_window(y_hat, w, T, H4, W4, a, b, c0, c1)
+        g = out[:, :, 8 * a:8 * a + o.shape[2], 8 * c0:8 * c0 + o.shape[3]]
+        sq += float(((g - o) ** 2).sum())
+        cnt += o.size
+    psnr = 10 * np.log10(cnt / sq) if sq else float("inf")
+    say(f"  frames at sampled windows: PSNR vs oracle {psnr:.2f} dB; {n} bytes")
+    assert np.isfinite(out).all() and psnr >= 35
+    c.close()
