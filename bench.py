@@ -451,6 +451,7 @@ def main():
     ap.add_argument("--no-fp8", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 leg (profiling runs)")
+    ap.add_argument("--lanes", type=int, default=2, help="chunks in flight for the headline run")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="finish with three plain device copies of this many MB (counter scaling)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -486,9 +487,9 @@ def main():
         r32 = run_codec(torch, ufvc, weights, "fp32", chunks, H, W, args.fp32_steps, 2,
                         args.seg_log2, args.seg_log2_z, profile=True, autotune=not args.no_autotune)
 
-    log("bench: bf16 pipelined (two chunks in flight)")
+    log(f"bench: bf16 pipelined ({args.lanes} chunks in flight)")
     rp = run_pipelined(torch, ufvc, weights, "bf16", chunks, H, W, args.steps, args.warmup,
-                       args.seg_log2, args.seg_log2_z)
+                       args.seg_log2, args.seg_log2_z, lanes=args.lanes)
     fps16 = T * args.steps / r16["seconds"]
     fps_pipe = T * rp["steps"] / rp["seconds"]
     src0 = chunks[0]
@@ -526,8 +527,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": f"1080p chunk codec: T={T} frames {W}x{H} (padded {Hp}), C={C}, "
-                               f"encode+decode per step, two chunks in flight", "T": T, "H": H,
-                   "W": W, "C": C, "chunks_in_flight": 2,
+                               f"encode+decode per step, {args.lanes} chunks in flight", "T": T,
+                   "H": H, "W": W, "C": C, "chunks_in_flight": args.lanes,
                    "seg_log2": args.seg_log2, "seg_log2_z": args.seg_log2_z,
                    "chunks_cycled": args.chunks, "precision": "bf16 convs, fp32 entropy params, "
                                                           "fp64 tables"},
