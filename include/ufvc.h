@@ -268,6 +268,14 @@ void ufvc_server_destroy(ufvc_server* s);
  * workgroup.  Configurations never change results, only speed. */
 int ufvc_get_tuning(ufvc_ctx* ctx, int H, int W, int* cfg, int n);
 int ufvc_tile_config(int cfg, int* th, int* tw, int* bn);
+/* Number of tile configurations (valid cfg values are 0 .. n - 1). */
+int ufvc_num_tile_configs(void);
+/* Test hook: every conv layer of ctx that supports configuration cfg (its
+ * precision, input loader and stride, and a channel tile dividing its
+ * outputs) uses it, in chunk calls and in batches planned afterwards; the
+ * other layers keep their tuned or default choice.  cfg = -1 clears it.
+ * Returns UFVC_E_INVAL for cfg outside -1 .. n - 1. */
+int ufvc_force_tile_config(ufvc_ctx* ctx, int cfg);
 
 /* ---- Per-stage timing ----
  * With profiling enabled, every kernel launch of the coding calls is

@@ -92,6 +92,8 @@ def _load():
         "ufvc_profile_read": (I, [P, P, P, I]),
         "ufvc_get_tuning": (I, [P, I, I, P, I]),
         "ufvc_tile_config": (I, [I, P, P, P]),
+        "ufvc_num_tile_configs": (I, []),
+        "ufvc_force_tile_config": (I, [P, I]),
         "ufvc_batch_create": (I, [P, I, ctypes.POINTER(P)]),
         "ufvc_batch_destroy": (None, [P]),
         "ufvc_encode_batch": (I, [P, P, I, P]),
@@ -118,7 +120,8 @@ EXPORTS = ("ufvc_weight_count", "ufvc_create", "ufvc_destroy", "ufvc_max_bitstre
            "ufvc_encode_chunk", "ufvc_decode_chunk", "ufvc_sync_status", "ufvc_get_tables",
            "ufvc_rans_encode", "ufvc_rans_decode", "ufvc_synthesize", "ufvc_copy_buffer",
            "ufvc_profile_enable", "ufvc_profile_stage_count", "ufvc_profile_stage_name",
-           "ufvc_profile_read", "ufvc_get_tuning", "ufvc_tile_config", "ufvc_batch_create",
+           "ufvc_profile_read", "ufvc_get_tuning", "ufvc_tile_config", "ufvc_num_tile_configs",
+           "ufvc_force_tile_config", "ufvc_batch_create",
            "ufvc_batch_destroy", "ufvc_encode_batch", "ufvc_decode_batch", "ufvc_batch_sync_status",
            "ufvc_server_create", "ufvc_server_submit", "ufvc_server_poll", "ufvc_server_stats",
            "ufvc_server_destroy")
@@ -274,6 +277,11 @@ class Codec:
             lib.ufvc_tile_config(int(k), ctypes.byref(th), ctypes.byref(tw), ctypes.byref(bn))
             out[name] = (int(k), th.value, tw.value, bn.value)
         return out
+
+    def force_tile_config(self, cfg: int):
+        """Test hook: every conv layer that supports tile configuration cfg uses
+        it (-1 restores the tuned / default choice)."""
+        _check(lib.ufvc_force_tile_config(self._h, int(cfg)), "ufvc_force_tile_config")
 
     # ------------------------------------------------------------ timing
     def profile(self, on: bool = True):

@@ -106,8 +106,11 @@ ConvArgs conv_of(int Hin, int Win, int Hout, int Wout, const Layer& L) {
   return conv_args(Hin, Win, Hout, Wout, L);
 }
 
-int pick_cfg(ufvc_ctx* c, int stage_id, const ConvArgs& a, int fixed) {
+int pick_cfg(ufvc_ctx* c, int stage_id, int prec, int ld, int stride, const ConvArgs& a, int fixed) {
   if (fixed >= 0) return fixed;
+  if (c->force_cfg >= 0 && a.cout % conv_cfg(c->force_cfg).bn == 0 &&
+      conv_cfg_supported(prec, ld, stride, a.cin, a.cout, c->force_cfg))
+    return c->force_cfg;
   auto it = c->tune.find(tune_key(stage_id, a.Hout, a.Wout));
   if (it != c->tune.end()) return it->second;
   return default_cfg(a.cout, (long)a.Hout * a.Wout);
@@ -239,7 +242,7 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
       ConvArgs a = make(i, g);
       per.push_back(a);
       groups.push_back(g);
-      cfgs.push_back(pick_cfg(b->models[P.chunks[i].model], id, a, fixed_cfg));
+      cfgs.push_back(pick_cfg(b->models[P.chunks[i].model], id, prec, ld, stride, a, fixed_cfg));
     }
     add_stage(P, st, descs, work, per, groups, cfgs);
   };

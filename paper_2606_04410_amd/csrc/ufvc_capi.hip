@@ -46,6 +46,9 @@ static hipError_t stage(ufvc_ctx* c, int id, hipStream_t s, F&& launch) {
 // every output in the same order, so the choice never changes results.
 static hipError_t tuned_conv(ufvc_ctx* c, int id, int prec, int ld, int st, const ConvArgs& a,
                              int groups, hipStream_t s) {
+  if (c->force_cfg >= 0 && a.cout % conv_cfg(c->force_cfg).bn == 0 &&
+      conv_cfg_supported(prec, ld, 1, a.cin, a.cout, c->force_cfg))
+    return launch_conv(prec, ld, st, 1, c->force_cfg, a, groups, s);
   const uint64_t key = tune_key(id, a.Hout, a.Wout);
   auto it = c->tune.find(key);
   if (it != c->tune.end()) return launch_conv(prec, ld, st, 1, it->second, a, groups, s);
@@ -599,6 +602,14 @@ int ufvc_get_tuning(ufvc_ctx* c, int H, int W, int* cfg, int n) {
     auto it = c->tune.find(tune_key(ids[i], g.h, g.w));
     cfg[i] = it == c->tune.end() ? -1 : it->second;
   }
+  return UFVC_OK;
+}
+
+int ufvc_num_tile_configs(void) { return conv_num_cfgs(); }
+
+int ufvc_force_tile_config(ufvc_ctx* c, int cfg) {
+  if (!c || cfg < -1 || cfg >= conv_num_cfgs()) return UFVC_E_INVAL;
+  c->force_cfg = cfg;
   return UFVC_OK;
 }
 

@@ -213,6 +213,19 @@ __device__ __forceinline__ int lds_off(int row, int chunk) {
   else return row * 64 + ((chunk ^ ((row >> 2) & 3)) << 4);
 }
 
+// Tile position (row-major index into the TH x TW tile) of element j
+// (0..31) of 32-position block b.  A block covers two tile rows of 16.  A
+// wave-wide 16-byte LDS read runs at full rate only when lanes i and i + 16
+// (and i + 32, i + 48) fall on the same banks, so the second row is rotated
+// by the halo padding (2): lane i + 16 then reads the halo row 16 or 32
+// rows after lane i's, which the swizzle maps to the same banks, for every
+// tap.  Stride-2 tiles keep the plain order.
+template <int STRIDE, int TW>
+__device__ __forceinline__ int blk_pos(int b, int j) {
+  if constexpr (STRIDE == 1 && TW == 16) return b * 32 + (j & 16) + ((j & 16) ? ((j - 2) & 15) : j);
+  else return b * 32 + j;
+}
+
 template <int STRIDE, int TH, int TW, int BN, int ROWB>
 constexpr int conv_lds_bytes() {
   return ((STRIDE == 1 ? (TH + 2) * (TW + 2) : (2 * TH + 1) * (2 * TW + 1)) + 9 * BN) * ROWB;
@@ -370,7 +383,7 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
   int arow[FM];
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm) {
-    const int M = (wm * FM + fm) * 32 + (lane & 31);
+    const int M = blk_pos<STRIDE, TW>(wm * FM + fm, lane & 31);
     const int r = M / TW, c = M - (M / TW) * TW;
     arow[fm] = STRIDE == 1 ? r * HW + c : 2 * r * HW + 2 * c;
   }
@@ -510,7 +523,7 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
       if constexpr (PREC == P_FP8) sc = qscale * ldg(a.wscale + grp * a.cout + n);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int M = (wm * FM + fm) * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int M = blk_pos<STRIDE, TW>(wm * FM + fm, (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3));
         const int oy = oy0 + M / TW, ox = ox0 + M % TW;
         float v = acc[fm][fn][r];
         if constexpr (PREC == P_FP8) v *= sc;
@@ -531,6 +544,273 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
   }
 }
 
+// ------------------------------------------------ ring-staged bf16 conv ----
+// Second kernel family for bf16 NHWC inputs at stride 1 (the synthesis and
+// frame-decoder stacks).  Same GEMM view, slice order and tap order as
+// conv3x3_kernel, with three changes:
+//   * the output block is computed transposed (weights as the MFMA's first
+//     operand), so a lane ends with 16 output channels of one position; one
+//     lane-half exchange (v_permlane32_swap) gives each lane two runs of 8
+//     consecutive channels, stored as 16-byte vectors;
+//   * the input halo of a slice is fetched NH - 1 slices ahead through a ring
+//     of NH halo stages, the weights one slice ahead through two stages, both
+//     straight into LDS, so the activation reads (which miss L2) have several
+//     slices of MFMA work to land in;
+//   * the global address of every 16-byte chunk a lane fetches is computed
+//     once per tile; a slice only adds its offset.
+template <int ST, int TH, int TW, int WM, int WN, int FM, int FN, int NH>
+struct Ring {
+  static constexpr int NWAVES = WM * WN;
+  static constexpr int BN = WN * FN * 32;
+  static constexpr int HW = TW + 2;
+  static constexpr int HP = (TH + 2) * HW;
+  static constexpr int HCH = HP * 2;           // 16-byte chunks of a halo slice
+  static constexpr int WCH = 9 * BN * 2;       // 16-byte chunks of a weight slice
+  static constexpr int NIH = ((HCH + 63) / 64 + NWAVES - 1) / NWAVES;  // loads per wave
+  static constexpr int NIW = ((WCH + 63) / 64 + NWAVES - 1) / NWAVES;
+  static constexpr int HSTAGE = NIH * NWAVES * 1024;
+  static constexpr int WSTAGE = NIW * NWAVES * 1024;
+  static constexpr int LDS = NH * HSTAGE + 2 * WSTAGE;
+  static_assert(NH >= 3, "the wait count assumes the halo runs at least two slices ahead");
+};
+
+template <int ST, int TH, int TW, int WM, int WN, int FM, int FN, int NH>
+__global__ void __launch_bounds__(WM * WN * 64)
+conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __restrict__ work,
+                    int nwork) {
+  using R = Ring<ST, TH, TW, WM, WN, FM, FN, NH>;
+  constexpr int BN = R::BN, HW = R::HW, HCH = R::HCH, WCH = R::WCH;
+  constexpr int NIH = R::NIH, NIW = R::NIW, NWAVES = R::NWAVES;
+  static_assert(TH * TW == WM * FM * 32, "tile positions must match the wave grid");
+  extern __shared__ __attribute__((aligned(16))) unsigned char sh[];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN;
+  const int wn = wave - wm * WN;
+  ConvArgs a;
+  int tile, n0, grp;
+  if (descs) {
+    const int per = (nwork + 7) >> 3;
+    const int wi = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (wi >= nwork) return;
+    const int4 w = work[wi];
+    a = descs[w.x];
+    tile = w.y;
+    n0 = w.z;
+    grp = w.w;
+  } else {
+    a = a0;
+    const int nt = ((a.Hout + TH - 1) / TH) * ((a.Wout + TW - 1) / TW);
+    const int per = (nt + 7) >> 3;
+    tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= nt) return;
+    n0 = blockIdx.y * BN;
+    grp = blockIdx.z;
+  }
+  const int tiles_x = (a.Wout + TW - 1) / TW;
+  const int oy0 = (tile / tiles_x) * TH;
+  const int ox0 = (tile % tiles_x) * TW;
+  const int nslices = a.cin / 16;
+  const unsigned char* wbase = reinterpret_cast<const unsigned char*>(a.wpk) + grp * a.w_gstride;
+  const unsigned char* inb = reinterpret_cast<const unsigned char*>(a.in) + grp * a.in_goff * 2;
+
+  // Source of each chunk this lane fetches.  LDS chunk q of a stage holds
+  // row q / 2, half (q & 1) ^ swizzle(row), the layout the fragment reads
+  // expect; halo rows outside the input read the zero chunk (no slice step).
+  const unsigned char* hsrc[NIH];
+  int hstep[NIH];
+#pragma unroll
+  for (int j = 0; j < NIH; ++j) {
+    const int q = (j * NWAVES + wave) * 64 + lane;
+    hsrc[j] = kZeroChunk;
+    hstep[j] = 0;
+    if (q < HCH) {
+      const int row = q >> 1;
+      const int c = (q & 1) ^ ((row >> 3) & 1);
+      const int iy = oy0 - 1 + row / HW, ix = ox0 - 1 + row % HW;
+      if (iy >= 0 && ix >= 0 && iy < a.Hin && ix < a.Win) {
+        hsrc[j] = inb + (((long)iy * a.Win + ix) * a.in_pitch + c * 8) * 2;
+        hstep[j] = 32;
+      }
+    }
+  }
+  int woff[NIW];
+#pragma unroll
+  for (int j = 0; j < NIW; ++j) {
+    const int q = (j * NWAVES + wave) * 64 + lane;
+    woff[j] = -1;
+    if (q < WCH) {
+      const int row = q >> 1;
+      const int c = (q & 1) ^ ((row >> 3) & 1);
+      const int tap = row / BN, n = row - (row / BN) * BN;
+      woff[j] = ((tap * a.cout + n0 + n) * 32 + c * 16);
+    }
+  }
+  const long wslice = 9L * a.cout * 32;
+  unsigned char* const hring = sh;
+  unsigned char* const wring = sh + NH * R::HSTAGE;
+  auto issue_h = [&](int s, int stage) {
+#pragma unroll
+    for (int j = 0; j < NIH; ++j)
+      __builtin_amdgcn_global_load_lds(
+          (const UFVC_GLOBAL void*)(hsrc[j] + s * hstep[j]),
+          (__attribute__((address_space(3))) void*)(hring + stage * R::HSTAGE + (j * NWAVES + wave) * 1024),
+          16, 0, 0);
+  };
+  auto issue_w = [&](int s, int stage) {
+#pragma unroll
+    for (int j = 0; j < NIW; ++j) {
+      const unsigned char* src = woff[j] >= 0 ? wbase + s * wslice + woff[j] : kZeroChunk;
+      __builtin_amdgcn_global_load_lds(
+          (const UFVC_GLOBAL void*)src,
+          (__attribute__((address_space(3))) void*)(wring + stage * R::WSTAGE + (j * NWAVES + wave) * 1024),
+          16, 0, 0);
+    }
+  };
+
+  // positions (MFMA columns) of this lane in each of the wave's FM blocks
+  int xrow[FM];
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm) {
+    const int M = blk_pos<1, TW>(wm * FM + fm, lane & 31);
+    xrow[fm] = (M / TW) * HW + (M % TW);
+  }
+  const int khalf = lane >> 5;
+  f32x16 acc[FN][FM];
+#pragma unroll
+  for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[fn][fm][r] = 0.f;
+
+  auto compute_slice = [&](const unsigned char* lh, const unsigned char* lw) {
+    v4u xf[2][FM], wf[2][FN];
+    auto read_frags = [&](int buf, int tap) {
+      const int toff = (tap / 3) * HW + (tap % 3);
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+        wf[buf][fn] = lds16(lw + lds_off<32>(tap * BN + (wn * FN + fn) * 32 + (lane & 31), khalf));
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm) xf[buf][fm] = lds16(lh + lds_off<32>(xrow[fm] + toff, khalf));
+    };
+    read_frags(0, 0);
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int cur = tap & 1;
+      if (tap + 1 < 9) read_frags(cur ^ 1, tap + 1);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+          acc[fn][fm] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, wf[cur][fn]),
+                                                               __builtin_bit_cast(bf16x8, xf[cur][fm]),
+                                                               acc[fn][fm], 0, 0, 0);
+    }
+  };
+
+  // Ring schedule: halos 0 .. NH-2 and weights 0 before the loop; iteration s
+  // issues weights s + 1, then halo s + NH - 1.  At the top of iteration s
+  // everything up to and including weights s has landed once only the last
+  // halo group may still be in flight (NH >= 3 puts halo s before weights s).
+#pragma unroll
+  for (int k = 0; k < NH - 1; ++k)
+    if (k < nslices) issue_h(k, k);
+  issue_w(0, 0);
+  for (int s = 0; s < nslices; ++s) {
+    if (s > 0 && s + NH - 2 < nslices) wait_vmcnt<NIH>();
+    else wait_vmcnt<0>();
+    // every wave's chunks of slice s are in LDS, and every wave is done with
+    // slice s - 1, whose stages the next loads overwrite
+    asm volatile("s_barrier" ::: "memory");
+    if (s + 1 < nslices) issue_w(s + 1, (s + 1) & 1);
+    if (s + NH - 1 < nslices) issue_h(s + NH - 1, (s + NH - 1) % NH);
+    compute_slice(hring + (s % NH) * R::HSTAGE, wring + (s & 1) * R::WSTAGE);
+  }
+  wait_vmcnt<0>();
+
+  // Lane l holds, per block, position (l & 31) and channels
+  // 8 (r / 4) + 4 (l / 32) + r % 4.  Swapping registers r and r + 4 (r % 8
+  // < 4) between the lane halves leaves lane l < 32 with channels 0-7 and
+  // 16-23 in registers 0-7 and 8-15, lane l + 32 with 8-15 and 24-31.
+  const int cofs = (lane >> 5) * 8;
+  float vmax = 0.f;
+#pragma unroll
+  for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm) {
+      f32x16 v = acc[fn][fm];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[8 * h + r]),
+                                                          __float_as_uint(v[8 * h + r + 4]), false, false);
+          v[8 * h + r] = __uint_as_float(p[0]);
+          v[8 * h + r + 4] = __uint_as_float(p[1]);
+        }
+      const int M = blk_pos<1, TW>(wm * FM + fm, lane & 31);
+      const int oy = oy0 + M / TW, ox = ox0 + M % TW;
+      if (oy >= a.Hout || ox >= a.Wout) continue;
+      const long pos = (long)oy * a.Wout + ox;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int n = n0 + (wn * FN + fn) * 32 + h * 16 + cofs;   // first of 8 channels
+        float o[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[k] = v[8 * h + k];
+        if constexpr (ST == ST_BF16 || ST == ST_F32) {
+          if (a.relu) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) o[k] = fmaxf(o[k], 0.f);
+          }
+        }
+        if constexpr (ST == ST_BF16) {
+          bf16x8 b;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            b[k] = (__bf16)o[k];
+            vmax = fmaxf(vmax, fabsf(o[k]));
+          }
+          stg(reinterpret_cast<v4u*>(reinterpret_cast<__bf16*>(a.out) + pos * a.out_pitch + grp * a.out_goff + n),
+              __builtin_bit_cast(v4u, b));
+        } else if constexpr (ST == ST_F32) {
+          float* dst = reinterpret_cast<float*>(a.out) + pos * a.out_pitch + grp * a.out_goff + n;
+          stg(reinterpret_cast<v4f*>(dst), v4f{o[0], o[1], o[2], o[3]});
+          stg(reinterpret_cast<v4f*>(dst + 4), v4f{o[4], o[5], o[6], o[7]});
+        } else {
+          static_assert(ST == ST_SHUFFLE, "ring kernel stores bf16, float32 or shuffled frames");
+          // channels n .. n + 7 = c*64 + i*8 + (0..7): pixels (8 oy + i, 8 ox + 0..7)
+          const int c = n >> 6, i = (n >> 3) & 7;
+          const int py = 8 * oy + i, px = 8 * ox;
+          if (py < a.H) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) o[k] = fminf(fmaxf(o[k], 0.f), 1.f);
+            float* dst = reinterpret_cast<float*>(a.out) + (((long)grp * 3 + c) * a.H + py) * a.W + px;
+            if ((a.W & 3) == 0 && (reinterpret_cast<uintptr_t>(a.out) & 15) == 0 && px + 8 <= a.W) {
+              stg(reinterpret_cast<v4f*>(dst), v4f{o[0], o[1], o[2], o[3]});
+              stg(reinterpret_cast<v4f*>(dst + 4), v4f{o[4], o[5], o[6], o[7]});
+            } else {
+#pragma unroll
+              for (int k = 0; k < 8; ++k)
+                if (px + k < a.W) stg(dst + k, o[k]);
+            }
+          }
+        }
+      }
+    }
+  if constexpr (ST == ST_BF16) {
+    if (a.amax_out) {
+      vmax = fmaxf(vmax, 0.f);
+      for (int o = 32; o > 0; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
+      if (lane == 0) atomicMax(a.amax_out, __float_as_uint((float)(__bf16)vmax));
+    }
+  }
+}
+
 // ------------------------------------------------------------ dispatch ----
 // cfg: 0 = 8x16 tile, 128 channels, 2x2 waves of 64x64
 //      1 = 8x16 tile,  32 channels, 4x1 waves of 32x32 (narrow outputs)
@@ -542,16 +822,27 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
 //      7 = 16x16 tile,  64 channels, 2x2 waves of 128x32
 //      8 = 16x16 tile, 128 channels, 8 waves (4x2) of 64x64
 //      9 = 16x16 tile,  64 channels, 8 waves (4x2) of 64x32
+//     ring-staged bf16 NHWC kernel (halo ring of 3 stages):
+//     10 = 16x16 tile, 128 channels, 2x2 waves of 128 positions x 64 channels
+//     11 = 8x16 tile, 128 channels, 2x2 waves of 64x64
+//     12 = 8x16 tile,  64 channels, 2x2 waves of 64x32
+//     13 = 16x16 tile,  64 channels, 2x2 waves of 128x32
+//     14 = 16x16 tile, 128 channels, 8 waves (4x2) of 64x64
+//     15 = 16x16 tile, 192 channels, 2x2 waves of 128x96
+//     16 = 8x16 tile, 192 channels, 2x2 waves of 64x96
+//     17 = 8x16 tile,  32 channels, 4x1 waves of 32x32
 static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 16, 128},
                                 {8, 16, 64},  {16, 16, 128}, {16, 16, 192}, {16, 16, 64},
-                                {16, 16, 128}, {16, 16, 64}};
+                                {16, 16, 128}, {16, 16, 64},
+                                {16, 16, 128}, {8, 16, 128}, {8, 16, 64},  {16, 16, 64},
+                                {16, 16, 128}, {16, 16, 192}, {8, 16, 192}, {8, 16, 32}};
+constexpr int kFirstRing = 10;
 int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int cfg) {
-  (void)loader;
-  (void)stride;
-  (void)cin;
   (void)cout;
-  return cfg >= 0 && cfg < conv_num_cfgs() && !(prec == P_FP8 && (cfg == 6 || cfg == 8));
+  if (cfg >= kFirstRing)
+    return cfg < conv_num_cfgs() && prec == P_BF16 && loader == LD_NHWC && stride == 1 && cin % 16 == 0;
+  return cfg >= 0 && !(prec == P_FP8 && (cfg == 6 || cfg == 8));
 }
 
 __global__ void zero_u32_kernel(uint32_t* p, int n) {
@@ -594,6 +885,31 @@ static hipError_t run_conv(const ConvArgs& a, int groups, const ConvArgs* descs,
   return hipGetLastError();
 }
 
+template <int ST, int TH, int TW, int WM, int WN, int FM, int FN, int NH>
+static hipError_t run_ring(const ConvArgs& a, int groups, const ConvArgs* descs, const int4* work,
+                           int nwork, hipStream_t s) {
+  using R = Ring<ST, TH, TW, WM, WN, FM, FN, NH>;
+  auto kern = conv3x3_ring_kernel<ST, TH, TW, WM, WN, FM, FN, NH>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, R::LDS);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  dim3 grid;
+  if (descs) {
+    if (nwork <= 0) return hipSuccess;
+    grid = dim3(((nwork + 7) / 8) * 8, 1, 1);
+  } else {
+    if (a.cout % R::BN || a.cin % 16) return hipErrorInvalidValue;
+    const int tiles = ((a.Hout + TH - 1) / TH) * ((a.Wout + TW - 1) / TW);
+    grid = dim3(((tiles + 7) / 8) * 8, a.cout / R::BN, groups);
+  }
+  hipLaunchKernelGGL(kern, grid, dim3(WM * WN * 64), R::LDS, s, a, descs, work, nwork);
+  return hipGetLastError();
+}
+
 template <int PREC, int LD, int ST, int STRIDE>
 static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs* d,
                           const int4* w, int nw, hipStream_t s) {
@@ -613,6 +929,22 @@ static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs
       if constexpr (PREC == P_FP8) return hipErrorNotSupported;
       else return run_conv<PREC, LD, ST, STRIDE, 16, 16, 4, 2, 2, 2>(a, groups, d, w, nw, s);
     case 9: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 4, 2, 2, 1>(a, groups, d, w, nw, s);
+    default: break;
+  }
+  if constexpr (PREC == P_BF16 && LD == LD_NHWC && STRIDE == 1 && ST != ST_ZSYM) {
+    switch (cfg) {
+      case 10: return run_ring<ST, 16, 16, 2, 2, 4, 2, 3>(a, groups, d, w, nw, s);
+      case 11: return run_ring<ST, 8, 16, 2, 2, 2, 2, 3>(a, groups, d, w, nw, s);
+      case 12: return run_ring<ST, 8, 16, 2, 2, 2, 1, 3>(a, groups, d, w, nw, s);
+      case 13: return run_ring<ST, 16, 16, 2, 2, 4, 1, 3>(a, groups, d, w, nw, s);
+      case 14: return run_ring<ST, 16, 16, 4, 2, 2, 2, 3>(a, groups, d, w, nw, s);
+      case 15: return run_ring<ST, 16, 16, 2, 2, 4, 3, 3>(a, groups, d, w, nw, s);
+      case 16: return run_ring<ST, 8, 16, 2, 2, 2, 3, 3>(a, groups, d, w, nw, s);
+      case 17: return run_ring<ST, 8, 16, 4, 1, 1, 1, 3>(a, groups, d, w, nw, s);
+      default: break;
+    }
+  }
+  switch (cfg) {
     default: return hipErrorInvalidValue;
   }
 }

@@ -71,6 +71,8 @@ struct ufvc_ctx {
   std::vector<Rec> prof_rec;
   // autotuned tile configuration per (conv stage, output height, width)
   std::map<uint64_t, int> tune;
+  // test hook: tile configuration used by every conv layer that supports it
+  int force_cfg = -1;
 };
 
 #define CK(x)                                   \
