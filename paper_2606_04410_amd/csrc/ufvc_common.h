@@ -17,6 +17,35 @@ __device__ __forceinline__ T ldg(const T* p) { return *(const UFVC_GLOBAL T*)(p)
 template <class T>
 __device__ __forceinline__ void stg(T* p, T v) { *(UFVC_GLOBAL T*)(p) = v; }
 
+// s_waitcnt on the vector-memory counter only (gfx9 encoding).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// Copies `bytes` (a multiple of 16) from device memory to LDS, both 16-byte
+// aligned, with one wave's direct-to-LDS loads: 1 KB per instruction, no
+// registers, all in flight at once.  The data is in LDS once the wave's
+// vector-memory counter has drained (wait_vmcnt<0>).
+__device__ __forceinline__ void lds_fill16(void* dst, const void* src, int bytes) {
+  const int lane = threadIdx.x & 63;
+  for (int o = 0; o < bytes; o += 1024)
+    if (lane * 16 < bytes - o)
+      __builtin_amdgcn_global_load_lds((const UFVC_GLOBAL void*)((const unsigned char*)src + o + lane * 16),
+                                       (__attribute__((address_space(3))) void*)((unsigned char*)dst + o),
+                                       16, 0, 0);
+}
+// The same for `n` dwords at 4-byte alignment.
+__device__ __forceinline__ void lds_fill4(void* dst, const void* src, int n) {
+  const int lane = threadIdx.x & 63;
+  for (int o = 0; o < n; o += 64)
+    if (lane < n - o)
+      __builtin_amdgcn_global_load_lds((const UFVC_GLOBAL void*)((const uint32_t*)src + o + lane),
+                                       (__attribute__((address_space(3))) void*)((uint32_t*)dst + o), 4, 0,
+                                       0);
+}
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 

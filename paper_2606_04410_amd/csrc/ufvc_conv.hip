@@ -258,12 +258,6 @@ struct Pipe {
 // Zero chunk for halo positions outside the input (conv zero padding).
 __device__ __attribute__((aligned(64))) unsigned char kZeroChunk[64];
 
-// s_waitcnt on the vector-memory counter only (gfx9 encoding).
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
-}
 
 template <int PREC, int LD, int ST, int STRIDE, int TH, int TW, int WM, int WN, int FM, int FN>
 __global__ void __launch_bounds__(WM * WN * 64)

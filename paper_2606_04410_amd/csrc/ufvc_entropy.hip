@@ -225,11 +225,11 @@ rans_encode_kernel(Tables t, EncStream z, EncStream y, uint8_t* __restrict__ scr
   uint32_t* s_mg = s_fc + NSCALES * NSYM;
   uint8_t* s_sh = reinterpret_cast<uint8_t*>(s_mg + NSCALES * NSYM);
   EncSegLds* segs = reinterpret_cast<EncSegLds*>(lds + ((ENC_TAB_BYTES + 15) & ~(size_t)15));
-  for (int i = threadIdx.x; i < NSCALES * NSYM; i += blockDim.x) {
-    s_fc[i] = t.fc[i];
-    s_mg[i] = t.magic[i];
-    s_sh[i] = t.shift[i];
-  }
+  // tables straight into LDS (in flight while the segment set-up runs)
+  static_assert((NSCALES * NSYM * 4) % 16 == 0 && NSCALES * NSYM % 16 == 0, "table sizes");
+  lds_fill16(s_fc, t.fc, NSCALES * NSYM * 4);
+  lds_fill16(s_mg, t.magic, NSCALES * NSYM * 4);
+  lds_fill16(s_sh, t.shift, NSCALES * NSYM);
 
   const int half = threadIdx.x >> 5;
   const int lane = threadIdx.x & 31;
@@ -277,6 +277,7 @@ rans_encode_kernel(Tables t, EncStream z, EncStream y, uint8_t* __restrict__ scr
   };
 
   prefetch(nep - 1);
+  wait_vmcnt<0>();   // tables in LDS
   for (int ep = nep - 1; ep >= 0; --ep) {
     // table entry (row * NSYM + symbol) of each step of this epoch
     uint32_t ec[EP];
@@ -612,10 +613,12 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
   uint16_t* s_lut = reinterpret_cast<uint16_t*>(lds + NSCALES * NSYM * 4);
   uint8_t* s_tail = reinterpret_cast<uint8_t*>(s_lut + NSCALES * LUT_BUCKETS);
   DecSegLds* segs = reinterpret_cast<DecSegLds*>(lds + DEC_TAB_BYTES);
-  for (int i = threadIdx.x; i < NSCALES * NSYM; i += blockDim.x) s_fc[i] = t.fc[i];
-  for (int i = threadIdx.x; i < NSCALES * LUT_BUCKETS * 2 / 16; i += blockDim.x)
-    reinterpret_cast<uint4*>(s_lut)[i] = reinterpret_cast<const uint4*>(t.lut)[i];
   s_tail[threadIdx.x] = t.tail[threadIdx.x];
+  if constexpr (!FIXED) {
+    // all rows, straight into LDS (in flight while the segment set-up runs)
+    lds_fill16(s_fc, t.fc, NSCALES * NSYM * 4);
+    lds_fill16(s_lut, t.lut, NSCALES * LUT_BUCKETS * 2);
+  }
 
   const int half = threadIdx.x >> 5;
   const int lane = threadIdx.x & 31;
@@ -680,6 +683,15 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
   // table row offset (row * NSYM) of each step of the next epoch; epochs past
   // this segment's own count re-read epoch 0 (in bounds)
   const uint32_t frow = min(me.fixed_row, 63u);
+  if constexpr (FIXED) {
+    // only the fixed rows of the pair's segments (the same row, normally)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t r = __shfl(frow, h * 32, 64);
+      lds_fill4(s_fc + r * NSYM, t.fc + r * NSYM, NSYM);
+      lds_fill16(s_lut + r * LUT_BUCKETS, t.lut + r * LUT_BUCKETS, LUT_BUCKETS * 2);
+    }
+  }
   uint32_t rn[EP];
   const int nep_own = (nsym + EPB - 1) / EPB;
   auto fetch_rows = [&](int ep) {
@@ -695,6 +707,7 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
   fetch_words();
   commit_words();
   fetch_rows(0);
+  wait_vmcnt<0>();   // tables in LDS
   for (int ep = 0; ep < nep; ++ep) {
     uint32_t rc[EP];
 #pragma unroll
