@@ -67,84 +67,129 @@ __device__ __forceinline__ v4u lds16(const unsigned char* p) { return *reinterpr
 // E4M3 saturates at +-448
 __device__ __forceinline__ float sat448(float x) { return fminf(fmaxf(x, -448.f), 448.f); }
 
-// 16 bytes of compute-type input for channels [slice*E + ch*E/2, +E/2) at
-// input position (iy, ix) (fp8: 16 channels from slice*64 + ch*16); zero
-// outside the input grid (conv zero padding).
+// A halo chunk is fetched in two steps so that the loads of the next slice
+// stay in flight while the current one is multiplied: fetch_raw issues the
+// loads into registers (device-memory words, unconverted), convert_raw turns
+// them into 16 bytes of compute-type input when the chunk is written to LDS.
+// The chunk covers channels [slice*E + ch*E/2, +E/2) (fp8: 16 channels from
+// slice*64 + ch*16) at input position (iy, ix); outside the input grid it is
+// zero (conv zero padding).  The loads are issued for every lane at clamped
+// addresses, and padding and edge replication are applied in convert_raw:
+// a lane-divergent branch around a load would make the next write to its
+// registers wait for it.
+struct Raw {
+  v4u a, b;     // up to 32 bytes of activations, frame pixels or means
+  v2u c;        // up to 8 bytes of symbols
+  unsigned ok;  // inside the input grid
+  unsigned rep; // frame loaders: the chunk lies past the right edge
+};
 
 template <int PREC, int LD>
-__device__ __forceinline__ v4u load_chunk(const ConvArgs& a, const unsigned char* inb,
-                                            int slice, int ch, int iy, int ix, float qinv) {
+__device__ __forceinline__ Raw fetch_raw(const ConvArgs& a, const unsigned char* inb, int slice,
+                                         int ch, int iy, int ix) {
   constexpr int E = PT<PREC>::E;
   constexpr int ESZ = PT<PREC>::ESZ;
-  if (iy < 0 || ix < 0 || iy >= a.Hin || ix >= a.Win) return zero16();
+  Raw r;
+  r.a = zero16();
+  r.b = zero16();
+  r.c = v2u{0u, 0u};
+  r.ok = (iy >= 0 && ix >= 0 && iy < a.Hin && ix < a.Win) ? 1u : 0u;
+  r.rep = 0u;
+  iy = min(max(iy, 0), a.Hin - 1);
+  ix = min(max(ix, 0), a.Win - 1);
   const long pos = (long)iy * a.Win + ix;
   if constexpr (LD == LD_NHWC) {
-    return ld16(inb + (pos * a.in_pitch + slice * E + ch * (E / 2)) * ESZ);
+    r.a = ld16(inb + (pos * a.in_pitch + slice * E + ch * (E / 2)) * ESZ);
   } else if constexpr (LD == LD_Q8) {
-    // 16 bf16 channels -> 16 FP8 E4M3 values of x * qinv (qinv = 448 / amax)
     static_assert(PREC == P_FP8, "Q8 loader feeds FP8 convs");
     const unsigned char* src = inb + (pos * a.in_pitch + slice * 64 + ch * 16) * 2;
-    const v4u u0 = ld16(src), u1 = ld16(src + 16);
-    const bf16x8 b0 = __builtin_bit_cast(bf16x8, u0), b1 = __builtin_bit_cast(bf16x8, u1);
-    v4u r;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const bf16x8& bb = k < 2 ? b0 : b1;
-      const int o = (k & 1) * 4;
-      int w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448((float)bb[o] * qinv), sat448((float)bb[o + 1] * qinv),
-                                              0, false);
-      w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448((float)bb[o + 2] * qinv), sat448((float)bb[o + 3] * qinv),
-                                          w, true);
-      r[k] = (unsigned)w;
-    }
-    return r;
+    r.a = ld16(src);
+    r.b = ld16(src + 16);
   } else if constexpr (LD == LD_F32) {
-    // float32 tensor feeding a bf16 conv (8 channels -> 8 bf16)
     static_assert(PREC == P_BF16, "use LD_NHWC for float32 compute");
     const float* fp = reinterpret_cast<const float*>(inb) + pos * a.in_pitch + slice * E + ch * (E / 2);
-    const v4f u0 = ldg(reinterpret_cast<const v4f*>(fp));
-    const v4f u1 = ldg(reinterpret_cast<const v4f*>(fp + 4));
-    const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-    return cvt8(v);
+    r.a = __builtin_bit_cast(v4u, ldg(reinterpret_cast<const v4f*>(fp)));
+    r.b = __builtin_bit_cast(v4u, ldg(reinterpret_cast<const v4f*>(fp + 4)));
   } else if constexpr (LD == LD_UNSHUFFLE) {
-    // channel cb = t*192 + c*64 + i*8 + j  <->  pixel (8 iy + i, 8 ix + j) of plane t*3 + c
+    // channel cb = t*192 + c*64 + i*8 + j  <->  pixel (8 iy + i, 8 ix + j) of plane t*3 + c,
+    // rows and columns past the frame replicate its last one.  Frame widths
+    // are multiples of 8 (at least 16), so a chunk lies wholly inside the
+    // frame or wholly past its right edge (then every value is the last
+    // column's, the last of the chunk fetched at the edge).
+    constexpr int NPX = PREC == P_BF16 ? 8 : 4;
     const int cb = slice * E + ch * (E / 2);
     const int plane = cb >> 6;             // t*3 + c
     const int i = (cb >> 3) & 7;
     const int j0 = cb & 7;                 // 0 for bf16 (8 pixels), 0 or 4 for f32
     const int py = min(8 * iy + i, a.H - 1);
     const int px = 8 * ix + j0;
-    const float* row = reinterpret_cast<const float*>(a.in) + ((long)plane * a.H + py) * a.W;
-    if constexpr (PREC == P_BF16) {
-      float v[8];
-      if (px + 8 <= a.W) {
-        const v4f u0 = ldg(reinterpret_cast<const v4f*>(row + px));
-        const v4f u1 = ldg(reinterpret_cast<const v4f*>(row + px + 4));
-        v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
-        v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w;
-      } else {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = ldg(row + min(px + k, a.W - 1));
-      }
-      return cvt8(v);
-    } else {
-      v4f r;
-      if (px + 4 <= a.W) {
-        r = ldg(reinterpret_cast<const v4f*>(row + px));
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) r[k] = ldg(row + min(px + k, a.W - 1));
-      }
-      return __builtin_bit_cast(v4u, r);
-    }
+    r.rep = px + NPX > a.W ? 1u : 0u;
+    const float* row = reinterpret_cast<const float*>(a.in) + ((long)plane * a.H + py) * a.W +
+                       min(px, a.W - NPX);
+    r.a = __builtin_bit_cast(v4u, ldg(reinterpret_cast<const v4f*>(row)));
+    if constexpr (PREC == P_BF16) r.b = __builtin_bit_cast(v4u, ldg(reinterpret_cast<const v4f*>(row + 4)));
   } else if constexpr (LD == LD_DEQUANT) {
     const int c0 = slice * E + ch * (E / 2);
     const unsigned char* sp = reinterpret_cast<const unsigned char*>(a.in) + pos * a.cin + c0;
     const float* mp = a.mu + pos * a.mu_pitch + c0;
     if constexpr (PREC == P_BF16) {
-      const v2u sb = ldg(reinterpret_cast<const v2u*>(sp));
-      const v4f m0 = ldg(reinterpret_cast<const v4f*>(mp));
-      const v4f m1 = ldg(reinterpret_cast<const v4f*>(mp + 4));
+      r.c = ldg(reinterpret_cast<const v2u*>(sp));
+      r.a = __builtin_bit_cast(v4u, ldg(reinterpret_cast<const v4f*>(mp)));
+      r.b = __builtin_bit_cast(v4u, ldg(reinterpret_cast<const v4f*>(mp + 4)));
+    } else {
+      r.c.x = ldg(reinterpret_cast<const uint32_t*>(sp));
+      r.a = __builtin_bit_cast(v4u, ldg(reinterpret_cast<const v4f*>(mp)));
+    }
+  } else {  // LD_UP2, float32 compute
+    static_assert(PREC == P_F32, "up2 loader is float32 only");
+    const int c0 = slice * E + ch * (E / 2);
+    const int wz = (a.Win + 1) >> 1;
+    const unsigned char* sp = reinterpret_cast<const unsigned char*>(a.in) +
+                              ((long)(iy >> 1) * wz + (ix >> 1)) * a.cin + c0;
+    r.c.x = ldg(reinterpret_cast<const uint32_t*>(sp));
+  }
+  return r;
+}
+
+template <int PREC, int LD>
+__device__ __forceinline__ v4u convert_raw(const Raw& r, float qinv) {
+  v4u o;
+  if constexpr (LD == LD_NHWC) {
+    o = r.a;
+  } else if constexpr (LD == LD_Q8) {
+    // 16 bf16 channels -> 16 FP8 E4M3 values of x * qinv (qinv = 448 / amax)
+    const bf16x8 b0 = __builtin_bit_cast(bf16x8, r.a), b1 = __builtin_bit_cast(bf16x8, r.b);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bf16x8& bb = k < 2 ? b0 : b1;
+      const int s = (k & 1) * 4;
+      int w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448((float)bb[s] * qinv), sat448((float)bb[s + 1] * qinv),
+                                              0, false);
+      w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448((float)bb[s + 2] * qinv), sat448((float)bb[s + 3] * qinv),
+                                          w, true);
+      o[k] = (unsigned)w;
+    }
+  } else if constexpr (LD == LD_F32) {
+    const v4f u0 = __builtin_bit_cast(v4f, r.a), u1 = __builtin_bit_cast(v4f, r.b);
+    const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+    o = cvt8(v);
+  } else if constexpr (LD == LD_UNSHUFFLE) {
+    if constexpr (PREC == P_BF16) {
+      const v4f u0 = __builtin_bit_cast(v4f, r.a), u1 = __builtin_bit_cast(v4f, r.b);
+      float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+      if (r.rep) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) v[k] = v[7];
+      }
+      o = cvt8(v);
+    } else {
+      o = r.a;
+      if (r.rep) o = v4u{o.w, o.w, o.w, o.w};
+    }
+  } else if constexpr (LD == LD_DEQUANT) {
+    if constexpr (PREC == P_BF16) {
+      const v2u sb = r.c;
+      const v4f m0 = __builtin_bit_cast(v4f, r.a), m1 = __builtin_bit_cast(v4f, r.b);
       float v[8];
       v[0] = (float)((int)(sb.x & 255) - 32) + m0.x;
       v[1] = (float)((int)((sb.x >> 8) & 255) - 32) + m0.y;
@@ -154,31 +199,27 @@ __device__ __forceinline__ v4u load_chunk(const ConvArgs& a, const unsigned char
       v[5] = (float)((int)((sb.y >> 8) & 255) - 32) + m1.y;
       v[6] = (float)((int)((sb.y >> 16) & 255) - 32) + m1.z;
       v[7] = (float)((int)(sb.y >> 24) - 32) + m1.w;
-      return cvt8(v);
+      o = cvt8(v);
     } else {
-      const uint32_t sb = ldg(reinterpret_cast<const uint32_t*>(sp));
-      const v4f m = ldg(reinterpret_cast<const v4f*>(mp));
-      v4f r;
-      r[0] = (float)((int)(sb & 255) - 32) + m.x;
-      r[1] = (float)((int)((sb >> 8) & 255) - 32) + m.y;
-      r[2] = (float)((int)((sb >> 16) & 255) - 32) + m.z;
-      r[3] = (float)((int)(sb >> 24) - 32) + m.w;
-      return __builtin_bit_cast(v4u, r);
+      const uint32_t sb = r.c.x;
+      const v4f m = __builtin_bit_cast(v4f, r.a);
+      v4f f;
+      f[0] = (float)((int)(sb & 255) - 32) + m.x;
+      f[1] = (float)((int)((sb >> 8) & 255) - 32) + m.y;
+      f[2] = (float)((int)((sb >> 16) & 255) - 32) + m.z;
+      f[3] = (float)((int)(sb >> 24) - 32) + m.w;
+      o = __builtin_bit_cast(v4u, f);
     }
-  } else {  // LD_UP2, float32 compute
-    static_assert(PREC == P_F32, "up2 loader is float32 only");
-    const int c0 = slice * E + ch * (E / 2);
-    const int wz = (a.Win + 1) >> 1;
-    const unsigned char* sp = reinterpret_cast<const unsigned char*>(a.in) +
-                              ((long)(iy >> 1) * wz + (ix >> 1)) * a.cin + c0;
-    const uint32_t sb = ldg(reinterpret_cast<const uint32_t*>(sp));
-    v4f r;
-    r[0] = (float)((int)(sb & 255) - 32);
-    r[1] = (float)((int)((sb >> 8) & 255) - 32);
-    r[2] = (float)((int)((sb >> 16) & 255) - 32);
-    r[3] = (float)((int)(sb >> 24) - 32);
-    return __builtin_bit_cast(v4u, r);
+  } else {  // LD_UP2
+    const uint32_t sb = r.c.x;
+    v4f f;
+    f[0] = (float)((int)(sb & 255) - 32);
+    f[1] = (float)((int)((sb >> 8) & 255) - 32);
+    f[2] = (float)((int)((sb >> 16) & 255) - 32);
+    f[3] = (float)((int)(sb >> 24) - 32);
+    o = __builtin_bit_cast(v4u, f);
   }
+  return r.ok ? o : zero16();
 }
 
 template <int ST>
@@ -336,19 +377,18 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
 
   // Staging registers for the next slice.  Written and read only through
   // fully unrolled loops with constant indices so they live in VGPRs.
-  v4u hreg[HIT];
+  Raw hraw[HIT];
   v4u wreg[WIT];
 #define UFVC_GLOAD(S_)                                                                   \
   do {                                                                                   \
     _Pragma("unroll") for (int i = 0; i < HIT; ++i) {                                    \
-      const int q = tid + i * NT;                                                        \
+      /* lanes past the halo fetch its last chunk again (not stored) */                  \
+      const int q = min(tid + i * NT, HCH - 1);                                          \
       int pos, ch;                                                                       \
       if (LD == LD_UNSHUFFLE) { ch = q / HP; pos = q - ch * HP; }                        \
       else { pos = q / CH; ch = q % CH; }                                                \
       const int hy = pos / HW, hx = pos - (pos / HW) * HW;                               \
-      hreg[i] = (HCH % NT == 0 || q < HCH)                                               \
-                    ? load_chunk<PREC, LD>(a, inb, (S_), ch, iy0 + hy, ix0 + hx, qinv)   \
-                    : zero16();                                                          \
+      hraw[i] = fetch_raw<PREC, LD>(a, inb, (S_), ch, iy0 + hy, ix0 + hx);               \
     }                                                                                    \
     _Pragma("unroll") for (int i = 0; i < WIT; ++i) {                                    \
       const int q = min(tid + i * NT, WCH - 1);                                          \
@@ -365,7 +405,8 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
       if (LD == LD_UNSHUFFLE) { ch = q / HP; pos = q - ch * HP; }                        \
       else { pos = q / CH; ch = q % CH; }                                                \
       if (HCH % NT == 0 || q < HCH)                                                      \
-        *reinterpret_cast<v4u*>(lds_h + lds_off<ROWB>(pos, ch)) = hreg[i];               \
+        *reinterpret_cast<v4u*>(lds_h + lds_off<ROWB>(pos, ch)) =                        \
+            convert_raw<PREC, LD>(hraw[i], qinv);                                        \
     }                                                                                    \
     _Pragma("unroll") for (int i = 0; i < WIT; ++i) {                                    \
       const int q = tid + i * NT;                                                        \
