@@ -114,7 +114,7 @@ bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int
 constexpr int NSCALES = 64;
 constexpr int NSYM = 65;
 constexpr int LANES = 32;
-constexpr int LUT_BUCKETS = 512;   // decoder lookup buckets per table row
+constexpr int LUT_BUCKETS = 256;   // decoder lookup buckets per table row
 constexpr int LUT_SLOTS = 65536 / LUT_BUCKETS;
 constexpr int SEG_STATE_BYTES = 4 * LANES;
 

@@ -5,7 +5,7 @@
 //   scale-index thresholds, the multiplier/shift pairs that turn the
 //   encoder's division by a frequency into a multiply-high (Granlund and
 //   Montgomery 1994, "Division by invariant integers using multiplication"),
-//   and a 512-bucket slot -> symbol lookup for the decoder.
+//   and a 256-bucket slot -> symbol lookup for the decoder.
 // * params_epilogue: sigma = clamp(softplus(.), 0.11, 64) in float32 and its
 //   table index for every latent element; in the encoder also the residual
 //   symbol r_hat = round(y - mu).  The mean is never needed for coding.
@@ -66,13 +66,15 @@ __global__ void build_tables_kernel(Tables t) {
     t.shift[k * NSYM + i] = (uint8_t)l;
     cum += fi;
   }
-  // Decoder lookup, 512 buckets of 128 slots per row.  lut[b] (16 bits):
-  // bits 0..6 the symbol s0 holding the bucket's first middle slot, bits
-  // 7..14 the offset in the bucket where s0 + 1 starts (128: s0 fills the rest
-  // of the bucket), bit 15 a slow bucket: it holds three or more symbols, or
-  // frequency-1 tail slots.  The tails (leading run of frequency-1 symbols and
-  // its mirror, fewer than 33 slots) sit in the first and last bucket and map
-  // slot -> symbol in closed form.
+  // Decoder lookup, 256 buckets of 256 slots per row.  lut[b] (16 bits):
+  // bits 0..6 hold base + 1 and bits 7..14 an offset o: a middle slot s of
+  // the bucket decodes to base + (s % 256 >= o).  A bucket whose first middle
+  // slot belongs to s0 and that holds s0 + 1 from offset o > 0 on stores
+  // (s0, o); a bucket wholly inside s0 stores (s0 - 1, 0).  Bit 15 marks a
+  // slow bucket: it holds three or more symbols, or frequency-1 tail slots;
+  // its base is s0, where a scan starts.  The tails (leading run of
+  // frequency-1 symbols and its mirror, fewer than 33 slots) sit in the first
+  // and last bucket and map slot -> symbol in closed form.
   uint32_t tail = 0;
   while (tail < 32 && f[tail] == 1u) ++tail;
   t.tail[k] = (uint8_t)tail;
@@ -83,17 +85,18 @@ __global__ void build_tables_kernel(Tables t) {
     const uint32_t b0 = (uint32_t)b * LUT_SLOTS;
     const uint32_t first = max(b0, tail);
     const uint32_t last = min(b0 + LUT_SLOTS, mid_end);
-    uint32_t entry = 0x8000u;
+    uint32_t entry = 0x8000u | 1u;
     if (first < last) {
       while (sidx + 1 < NSYM && c + f[sidx] <= first) { c += f[sidx]; ++sidx; }
       const uint32_t end0 = c + f[sidx];
-      uint32_t boff = LUT_SLOTS;
       bool slow = tail > 0 && (first > b0 || last < b0 + LUT_SLOTS);
-      if (end0 < last) {
-        boff = end0 - b0;
-        if (sidx + 1 >= NSYM || end0 + f[sidx + 1] < last) slow = true;
+      if (end0 < last && (sidx + 1 >= NSYM || end0 + f[sidx + 1] < last)) slow = true;
+      uint32_t base1 = (uint32_t)sidx + 1u, off = 0;
+      if (!slow) {
+        if (end0 < last) off = end0 - b0;   // 1 .. 255
+        else base1 = (uint32_t)sidx;        // base s0 - 1, offset 0
       }
-      entry = (uint32_t)sidx | (boff << 7) | (slow ? 0x8000u : 0u);
+      entry = base1 | (off << 7) | (slow ? 0x8000u : 0u);
     }
     t.lut[k * LUT_BUCKETS + b] = (uint16_t)entry;
   }
@@ -722,8 +725,8 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
       const bool valid = active && j < nsym;
       const uint32_t row = rc[u];
       const uint32_t slot = x & 0xFFFFu;
-      const uint32_t e = s_lut[row * LUT_BUCKETS + (slot >> 7)];
-      uint32_t sy = (e & 127u) + ((slot & 127u) >= ((e >> 7) & 255u) ? 1u : 0u);
+      const uint32_t e = s_lut[row * LUT_BUCKETS + (slot >> 8)];
+      uint32_t sy = (e & 127u) - 1u + ((slot & 255u) >= ((e >> 7) & 255u) ? 1u : 0u);
       if (e & 0x8000u) {
         // slow bucket: frequency-1 tails in closed form (slot s is symbol s
         // on the left, 64 - (65535 - s) on the right), else a scan from s0
@@ -733,7 +736,7 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
         } else if (slot >= 65536u - tl) {
           sy = slot - (65536u - NSYM);
         } else {
-          sy = e & 127u;
+          sy = (e & 127u) - 1u;
           while (sy < NSYM - 1 && (s_fc[row * NSYM + sy + 1] >> 16) <= slot) ++sy;
         }
       }
