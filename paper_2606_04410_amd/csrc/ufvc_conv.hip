@@ -866,18 +866,21 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
 //     15 = 16x16 tile, 192 channels, 2x2 waves of 128x96
 //     16 = 8x16 tile, 192 channels, 2x2 waves of 64x96
 //     17 = 8x16 tile,  32 channels, 4x1 waves of 32x32
+//     18 = 16x16 tile,  64 channels, 4x1 waves of 64x64
+//     19 = 8x16 tile,  64 channels, 4x1 waves of 32x64
 static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 16, 128},
                                 {8, 16, 64},  {16, 16, 128}, {16, 16, 192}, {16, 16, 64},
                                 {16, 16, 128}, {16, 16, 64},
                                 {16, 16, 128}, {8, 16, 128}, {8, 16, 64},  {16, 16, 64},
-                                {16, 16, 128}, {16, 16, 192}, {8, 16, 192}, {8, 16, 32}};
+                                {16, 16, 128}, {16, 16, 192}, {8, 16, 192}, {8, 16, 32},
+                                {16, 16, 64}, {8, 16, 64}};
 constexpr int kFirstRing = 10;
 int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int cfg) {
   (void)cout;
   if (cfg >= kFirstRing)
     return cfg < conv_num_cfgs() && prec == P_BF16 && loader == LD_NHWC && stride == 1 && cin % 16 == 0;
-  return cfg >= 0 && !(prec == P_FP8 && (cfg == 6 || cfg == 8));
+  return cfg >= 0 && !(prec == P_FP8 && (cfg == 5 || cfg == 6 || cfg == 8));
 }
 
 __global__ void zero_u32_kernel(uint32_t* p, int n) {
@@ -954,7 +957,10 @@ static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs
     case 2: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 3>(a, groups, d, w, nw, s);
     case 3: return run_conv<PREC, LD, ST, STRIDE, 4, 16, 2, 2, 1, 2>(a, groups, d, w, nw, s);
     case 4: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 1>(a, groups, d, w, nw, s);
-    case 5: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 2>(a, groups, d, w, nw, s);
+    case 5:
+      // 128x64 per wave with fp8 staging registers does not fit the registers
+      if constexpr (PREC == P_FP8) return hipErrorNotSupported;
+      else return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 2>(a, groups, d, w, nw, s);
     case 6:
       // 128x96 per wave with 32-byte fp8 fragments does not fit the registers
       if constexpr (PREC == P_FP8) return hipErrorNotSupported;
@@ -976,6 +982,8 @@ static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs
       case 15: return run_ring<ST, 16, 16, 2, 2, 4, 3, 3>(a, groups, d, w, nw, s);
       case 16: return run_ring<ST, 8, 16, 2, 2, 2, 3, 3>(a, groups, d, w, nw, s);
       case 17: return run_ring<ST, 8, 16, 4, 1, 1, 1, 3>(a, groups, d, w, nw, s);
+      case 18: return run_ring<ST, 16, 16, 4, 1, 2, 2, 3>(a, groups, d, w, nw, s);
+      case 19: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3>(a, groups, d, w, nw, s);
       default: break;
     }
   }
