@@ -269,7 +269,7 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
     a.in = A + q.act1; a.in_pitch = C; a.out = A + q.y; a.out_pitch = C; a.relu = 0;
     return a;
   });
-  stage(P.enc_stage[3], S_HYPER, P_F32, LD_NHWC, ST_ZSYM, 2, 1, [&](int i, int&) {
+  stage(P.enc_stage[3], S_HYPER, P_F32, LD_NHWC, ST_ZSYM, 2, -1, [&](int i, int&) {
     const ChunkPlan& q = P.chunks[i];
     ConvArgs a = conv_of(q.g.h, q.g.w, q.g.hz, q.g.wz, b->models[q.model]->h);
     a.in = A + q.y; a.in_pitch = C; a.out = A + q.zsym; a.out_pitch = ZC;

@@ -45,15 +45,15 @@ static hipError_t stage(ufvc_ctx* c, int id, hipStream_t s, F&& launch) {
 // the second counted) and keeps the fastest.  All configurations accumulate
 // every output in the same order, so the choice never changes results.
 static hipError_t tuned_conv(ufvc_ctx* c, int id, int prec, int ld, int st, const ConvArgs& a,
-                             int groups, hipStream_t s) {
+                             int groups, hipStream_t s, int stride = 1) {
   if (c->force_cfg >= 0 && a.cout % conv_cfg(c->force_cfg).bn == 0 &&
-      conv_cfg_supported(prec, ld, 1, a.cin, a.cout, c->force_cfg))
-    return launch_conv(prec, ld, st, 1, c->force_cfg, a, groups, s);
+      conv_cfg_supported(prec, ld, stride, a.cin, a.cout, c->force_cfg))
+    return launch_conv(prec, ld, st, stride, c->force_cfg, a, groups, s);
   const uint64_t key = tune_key(id, a.Hout, a.Wout);
   auto it = c->tune.find(key);
-  if (it != c->tune.end()) return launch_conv(prec, ld, st, 1, it->second, a, groups, s);
+  if (it != c->tune.end()) return launch_conv(prec, ld, st, stride, it->second, a, groups, s);
   if (!c->cfg.autotune)
-    return launch_conv(prec, ld, st, 1, default_cfg(a.cout, (long)a.Hout * a.Wout), a, groups, s);
+    return launch_conv(prec, ld, st, stride, default_cfg(a.cout, (long)a.Hout * a.Wout), a, groups, s);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hipErrorOutOfMemory;
   int best = -1;
@@ -61,11 +61,11 @@ static hipError_t tuned_conv(ufvc_ctx* c, int id, int prec, int ld, int st, cons
   hipError_t err = hipSuccess;
   for (int cfg = 0; cfg < conv_num_cfgs(); ++cfg) {
     const TileCfg t = conv_cfg(cfg);
-    if (a.cout % t.bn || !conv_cfg_supported(prec, ld, 1, a.cin, a.cout, cfg)) continue;
+    if (a.cout % t.bn || !conv_cfg_supported(prec, ld, stride, a.cin, a.cout, cfg)) continue;
     float ms = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       (void)hipEventRecord(e0, s);
-      err = launch_conv(prec, ld, st, 1, cfg, a, groups, s);
+      err = launch_conv(prec, ld, st, stride, cfg, a, groups, s);
       if (err != hipSuccess) break;
       (void)hipEventRecord(e1, s);
       if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
@@ -78,7 +78,7 @@ static hipError_t tuned_conv(ufvc_ctx* c, int id, int prec, int ld, int st, cons
   (void)hipEventDestroy(e1);
   if (err != hipSuccess || best < 0) return err != hipSuccess ? err : hipErrorInvalidValue;
   c->tune[key] = best;
-  return launch_conv(prec, ld, st, 1, best, a, groups, s);
+  return launch_conv(prec, ld, st, stride, best, a, groups, s);
 }
 
 static size_t weight_count_tc(int T, int C) {
@@ -428,7 +428,7 @@ int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uin
   // hyper prior: stride-2 conv, z_hat = clamp(rint(z)) stored as symbols
   a = conv_args(g.h, g.w, g.hz, g.wz, c->h);
   a.in = ws.y; a.in_pitch = C; a.out = ws.zsym; a.out_pitch = ZC;
-  CK(stage(c, S_HYPER, s, [&] { return launch_conv(P_F32, LD_NHWC, ST_ZSYM, 2, 1, a, 1, s); }));
+  CK(stage(c, S_HYPER, s, [&] { return tuned_conv(c, S_HYPER, P_F32, LD_NHWC, ST_ZSYM, a, 1, s, 2); }));
   // entropy parameters in one pass from up2(z_hat)
   a = conv_args(g.h, g.w, g.h, g.w, c->p);
   a.in = ws.zsym; a.out = ws.P; a.out_pitch = 2 * C;

@@ -871,13 +871,15 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
 //     first family again:
 //     20 = 8x16 tile,  64 channels, 4x1 waves of 32x64
 //     21 = 16x16 tile,  64 channels, 4x1 waves of 64x64
+//     22 = 2x16 tile,  32 channels, one wave (small outputs: the stride-2 hyper conv)
+//     23 = 4x16 tile,  32 channels, 2x1 waves of 32x32
 static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 16, 128},
                                 {8, 16, 64},  {16, 16, 128}, {16, 16, 192}, {16, 16, 64},
                                 {16, 16, 128}, {16, 16, 64},
                                 {16, 16, 128}, {8, 16, 128}, {8, 16, 64},  {16, 16, 64},
                                 {16, 16, 128}, {16, 16, 192}, {8, 16, 192}, {8, 16, 32},
                                 {16, 16, 64}, {8, 16, 64},
-                                {8, 16, 64}, {16, 16, 64}};
+                                {8, 16, 64}, {16, 16, 64}, {2, 16, 32}, {4, 16, 32}};
 constexpr int kFirstRing = 10, kLastRing = 19;
 int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int cfg) {
@@ -977,6 +979,8 @@ static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs
     case 9: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 4, 2, 2, 1>(a, groups, d, w, nw, s);
     case 20: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 4, 1, 1, 2>(a, groups, d, w, nw, s);
     case 21: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 4, 1, 2, 2>(a, groups, d, w, nw, s);
+    case 22: return run_conv<PREC, LD, ST, STRIDE, 2, 16, 1, 1, 1, 1>(a, groups, d, w, nw, s);
+    case 23: return run_conv<PREC, LD, ST, STRIDE, 4, 16, 2, 1, 1, 1>(a, groups, d, w, nw, s);
     default: break;
   }
   if constexpr (PREC == P_BF16 && LD == LD_NHWC && STRIDE == 1 && ST != ST_ZSYM) {
