@@ -275,8 +275,9 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
     a.in = A + q.y; a.in_pitch = C; a.out = A + q.zsym; a.out_pitch = ZC;
     return a;
   });
+  // both params stages use the encoder's tuning key (one choice for both)
   auto params_stage = [&](ConvStage& st, int id) {
-    stage(st, id, P_F32, LD_UP2, ST_F32, 1, 0, [&](int i, int&) {
+    stage(st, id, P_F32, LD_UP2, ST_F32, 1, -1, [&](int i, int&) {
       const ChunkPlan& q = P.chunks[i];
       ConvArgs a = conv_of(q.g.h, q.g.w, q.g.h, q.g.w, b->models[q.model]->p);
       a.in = A + q.zsym; a.out = A + q.P; a.out_pitch = 2 * C;
@@ -285,7 +286,7 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
   };
   params_stage(P.enc_stage[4], S_PARAMS_ENC);
   // decoder
-  params_stage(P.dec_stage[0], S_PARAMS_DEC);
+  params_stage(P.dec_stage[0], S_PARAMS_ENC);
   stage(P.dec_stage[1], S_D1, cp_prec, LD_DEQUANT, act_st, 1, -1, [&](int i, int&) {
     const ChunkPlan& q = P.chunks[i];
     ConvArgs a = conv_of(q.g.h, q.g.w, q.g.h, q.g.w, b->models[q.model]->d1);

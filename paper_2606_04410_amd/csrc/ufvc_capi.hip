@@ -232,7 +232,6 @@ static int ensure_pad(ufvc_ctx* c, size_t n) {
   return UFVC_OK;
 }
 
-static int cfg_for(int cout) { return cout % 128 == 0 ? 0 : (cout % 64 == 0 ? 4 : 1); }
 
 static hipError_t run_synthesis(ufvc_ctx* c, const Geom& g, const uint8_t* sym, const float* mu,
                                 long mu_pitch, const float* yhat, int H, int W, float* frames,
@@ -432,7 +431,9 @@ int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uin
   // entropy parameters in one pass from up2(z_hat)
   a = conv_args(g.h, g.w, g.h, g.w, c->p);
   a.in = ws.zsym; a.out = ws.P; a.out_pitch = 2 * C;
-  CK(stage(c, S_PARAMS_ENC, s, [&] { return launch_conv(P_F32, LD_UP2, ST_F32, 1, cfg_for(a.cout), a, 1, s); }));
+  // (tuned under one key for the encoder and the decoder; every configuration
+  // gives the same results in any case)
+  CK(stage(c, S_PARAMS_ENC, s, [&] { return tuned_conv(c, S_PARAMS_ENC, P_F32, LD_UP2, ST_F32, a, 1, s); }));
   CK(stage(c, S_EPI_ENC, s, [&] { return launch_params_epilogue(ws.P, ws.y, c->tab.thresholds, ws.idx, ws.sym, (long)g.h * g.w, C, s); }));
   // rANS: z with the fixed row, y with per-element rows
   EncStream ez{ws.zsym, nullptr, K_Z, g.nz, c->cfg.seg_log2_z, g.nseg_z};
@@ -471,7 +472,7 @@ int ufvc_decode_chunk(ufvc_ctx* c, const uint8_t* bs, size_t len, int T, int H, 
   CK(stage(c, S_RANS_DEC_Z, s, [&] { return launch_rans_decode(c->tab, bs, c->rw.seg_off, c->rw.seg_len, dz, c->status, s); }));
   ConvArgs a = conv_args(g.h, g.w, g.h, g.w, c->p);
   a.in = ws.zsym; a.out = ws.P; a.out_pitch = 2 * C;
-  CK(stage(c, S_PARAMS_DEC, s, [&] { return launch_conv(P_F32, LD_UP2, ST_F32, 1, cfg_for(a.cout), a, 1, s); }));
+  CK(stage(c, S_PARAMS_DEC, s, [&] { return tuned_conv(c, S_PARAMS_ENC, P_F32, LD_UP2, ST_F32, a, 1, s); }));
   CK(stage(c, S_EPI_DEC, s, [&] { return launch_params_epilogue(ws.P, nullptr, c->tab.thresholds, ws.idx, nullptr, (long)g.h * g.w, C, s); }));
   // all of r_hat in one launch: its tables depend on sigma only
   DecStream dy{ws.idx, 0, g.ny, c->cfg.seg_log2, g.nseg_y, g.nseg_z, ws.sym, len};
