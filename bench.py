@@ -485,6 +485,7 @@ def main():
     ap.add_argument("--no-fp8", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 leg (profiling runs)")
+    ap.add_argument("--no-t1", action="store_true", help="skip the one-frame-chunk leg")
     ap.add_argument("--lanes", type=int, default=2, help="chunks in flight for the headline run")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="finish with three plain device copies of this many MB (counter scaling)")
@@ -604,6 +605,26 @@ def main():
                              "bf16_vs_fp32_recon": round(psnr_t(torch, r32["rec"], r16["rec"]), 3)}
         result["fp32_stage_ms"] = {k: round(v[0] / args.fp32_steps, 4)
                                    for k, v in r32["stages"].items()}
+    if not args.no_t1:
+        # one-frame chunks: the chunk size of the paper's low-delay mode (its
+        # temporal context is not built), same stand-in net with T = 1
+        log("bench: one-frame chunks (T=1)")
+        c1_np = [video_chunk(1, H, W, 16, seed=3, chunk_id=k) for k in range(args.chunks)]
+        c1 = [torch.from_numpy(x).cuda() for x in c1_np]
+        w1 = stand_in_weights(1, C)
+        r1 = run_codec(torch, ufvc, w1, "bf16", c1, H, W, args.steps, args.warmup,
+                       args.seg_log2, args.seg_log2_z, profile=False, autotune=not args.no_autotune)
+        p1 = run_pipelined(torch, ufvc, w1, "bf16", c1, H, W, args.steps, args.warmup,
+                           args.seg_log2, args.seg_log2_z, lanes=args.lanes)
+        result["one_frame_chunks"] = {
+            "value": round(args.steps / r1["seconds"], 2), "unit": "frames/s",
+            "latency_ms": {"p50": round(float(np.percentile(r1["lat"], 50)), 4),
+                           "p99": round(float(np.percentile(r1["lat"], 99)), 4)},
+            "in_flight": {"chunks": args.lanes, "value": round(p1["steps"] / p1["seconds"], 2),
+                          "latency_ms_p99": round(float(np.percentile(p1["lat"], 99)), 4)},
+            "psnr_db": round(psnr_t(torch, c1[0], r1["rec"]), 4),
+            "note": "T=1 chunks of 1920x1080 (the low-delay mode's chunk size; its temporal "
+                    "context is not built), bf16, encode+decode per frame, one frame at a time"}
     if not args.no_batch:
         log("bench: 48-chunk batch")
         result["batch_c3"] = run_batch_c3(torch, ufvc, args.batch_steps, args.seg_log2,

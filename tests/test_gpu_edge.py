@@ -75,3 +75,39 @@ def test_sizes_outside_the_format_are_refused():
         c.decode(bs, 27, 64, 64)            # shorter than the header
     assert e.value.code == -1
     c.close()
+
+
+@pytest.mark.parametrize("C,H,W", [(64, 64, 64), (128, 72, 136)])
+def test_one_frame_chunks_match_oracle(C, H, W):
+    """T = 1 (one-frame chunks, the chunk size of the paper's low-delay mode):
+    the analysis conv runs on 192 input channels.  y matches the oracle's
+    analysis, the container is byte-identical to the oracle coding the GPU's
+    own symbols, the decoder recovers them, and the frames match the oracle
+    synthesis of the GPU's y_hat."""
+    u = pkg()
+    T = 1
+    say(f"one-frame chunk C={C} {H}x{W}")
+    w = stand_in_weights(T, C)
+    c = u.Codec(T, C, w, precision="fp32", seg_log2=10, seg_log2_z=7, model_tag=11, autotune=True)
+    fr = video_chunk(T, H, W, 3, seed=C + H)
+    bs, n = c.encode(torch.from_numpy(fr).cuda())
+    stream = bs[:n].cpu().numpy().tobytes()
+    y = c.buffer(u.BUF_Y, H, W)
+    y_ref = np.transpose(nets.analysis(fr, w), (1, 2, 0))
+    assert float(np.abs(y - y_ref).max()) <= 1e-3
+    sym = c.buffer(u.BUF_SYM, H, W)
+    idx = c.buffer(u.BUF_IDX, H, W)
+    zs = c.buffer(u.BUF_ZSYM, H, W).reshape(-1)
+    mu = c.buffer(u.BUF_PARAMS, H, W)[..., :C]
+    z_segs = rans.encode(zs, np.full(zs.size, entropy.K_Z), FREQ, CUM, 1 << 7)
+    y_segs = rans.encode(sym.reshape(-1), idx.reshape(-1), FREQ, CUM, 1 << 10)
+    assert stream == container.pack(T, C, H, W, 10, 7, entropy.K_Z, 11, z_segs, y_segs)
+    out = c.decode(bs, n, H, W).cpu().numpy()
+    np.testing.assert_array_equal(c.buffer(u.BUF_SYM, H, W), sym)
+    np.testing.assert_array_equal(c.buffer(u.BUF_IDX, H, W), idx)
+    y_hat = np.transpose(sym.astype(np.float32) - 32 + mu, (2, 0, 1)).astype(np.float64)
+    ref = nets.synthesis(y_hat, w, T, H, W)
+    err = float(np.abs(out - ref).max())
+    say(f"  {n} bytes, frames max abs {err:.2e}")
+    assert out.shape == (T, 3, H, W) and err <= 1e-3
+    c.close()
