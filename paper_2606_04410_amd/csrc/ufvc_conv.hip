@@ -13,10 +13,12 @@
 // then every wave runs 9 taps of 32x32 MFMA blocks (bf16 32x32x16 or four
 // f32 32x32x2) reading A (positions x channels) from the halo shifted by the
 // tap and B (channels x outputs) from the weight rows.  The next slice is
-// fetched into registers while the current one is multiplied.  Reduction
-// order is fixed: slice, then tap, then the MFMA's own order, and does not
-// depend on the tile configuration's M extent, so results do not depend on
-// how many workgroups cover the output.
+// fetched while the current one is multiplied: straight into a second LDS
+// stage for inputs that are copied unchanged, into registers for inputs that
+// a loader converts.  Reduction order is fixed: slice, then tap, then the
+// MFMA's own order, and does not depend on the tile configuration, so results
+// do not depend on how many workgroups cover the output.  A second kernel
+// family (conv3x3_ring_kernel, below) serves bf16 activations at stride 1.
 //
 // Loaders fuse the producer's layout change into the halo fetch: the x8
 // pixel-unshuffle of the patch embedding with edge-replicated padding
@@ -267,20 +269,14 @@ __device__ __forceinline__ int blk_pos(int b, int j) {
   else return b * 32 + j;
 }
 
-template <int STRIDE, int TH, int TW, int BN, int ROWB>
-constexpr int conv_lds_bytes() {
-  return ((STRIDE == 1 ? (TH + 2) * (TW + 2) : (2 * TH + 1) * (2 * TW + 1)) + 9 * BN) * ROWB;
-}
-
 // Staging pipeline of one tile configuration.  Loaders that copy the input
 // unchanged (NHWC, bf16 or f32) stream each slice straight from global memory
 // into LDS (global_load_lds_dwordx4: a wave writes 64 consecutive 16-byte
 // chunks at a uniform LDS address, each lane fetching the global chunk that
-// belongs at its position, XOR swizzle included), through a ring of NSTAGE
-// slice buffers: loads run two slices ahead (one with two stages), nothing
-// is staged in registers and the block syncs once per slice.  Loaders that
-// convert (unshuffle, dequantise, up-sample, quantise) stage through
-// registers into a single buffer.
+// belongs at its position, XOR swizzle included), through two slice
+// buffers: loads run one slice ahead, nothing is staged in registers and the
+// block syncs once per slice.  Loaders that convert (unshuffle, dequantise,
+// up-sample, quantise) stage through registers into a single buffer.
 template <int PREC, int LD, int STRIDE, int TH, int TW, int WM, int WN, int FN>
 struct Pipe {
   static constexpr int ROWB = PT<PREC>::ROWB, CH = PT<PREC>::CH;
@@ -292,8 +288,7 @@ struct Pipe {
   static constexpr int STAGE = NIW * NWAVES * 64 * 16;            // bytes, padded to whole loads
   static constexpr bool DIRECT =
       LD == LD_NHWC && (PREC == P_BF16 || PREC == P_F32) && 2 * STAGE <= 160 * 1024;
-  static constexpr int NSTAGE = !DIRECT ? 1 : 2;
-  static constexpr int LDS = DIRECT ? NSTAGE * STAGE : (HP + 9 * BN) * ROWB;
+  static constexpr int LDS = DIRECT ? 2 * STAGE : (HP + 9 * BN) * ROWB;
 };
 
 // Zero chunk for halo positions outside the input (conv zero padding).
@@ -518,17 +513,14 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
       }
     };
     issue(0, 0);
-    if constexpr (PP::NSTAGE == 3) issue(min(1, nslices - 1), 1);
     for (int s = 0; s < nslices; ++s) {
-      // this wave's loads of slice s have landed (those of s + 1 may not);
-      // after the barrier every wave's have, and every wave has finished
-      // reading the stage the next loads overwrite
-      if constexpr (PP::NSTAGE == 3) wait_vmcnt<PP::NIW>();
-      else wait_vmcnt<0>();
+      // this wave's loads of slice s have landed; after the barrier every
+      // wave's have, and every wave has finished reading the stage the next
+      // loads overwrite
+      wait_vmcnt<0>();
       asm volatile("s_barrier" ::: "memory");
-      if constexpr (PP::NSTAGE == 3) issue(min(s + 2, nslices - 1), (s + 2) % 3);
-      else issue(min(s + 1, nslices - 1), (s + 1) & 1);
-      lds_h = sh + (s % PP::NSTAGE) * PP::STAGE;
+      if (s + 1 < nslices) issue(s + 1, (s + 1) & 1);
+      lds_h = sh + (s & 1) * PP::STAGE;
       lds_w = lds_h + HP * ROWB;
       compute_slice();
     }
