@@ -108,24 +108,43 @@ hipError_t launch_build_tables(const Tables& t, hipStream_t s) {
 }
 
 // ------------------------------------------------------ params epilogue ----
-__device__ __forceinline__ void params_element(const float* __restrict__ P, const float* __restrict__ y,
-                                               const float* s_thr, uint8_t* __restrict__ idx,
-                                               uint8_t* __restrict__ sym, int C, long e) {
-  const long pos = e / C;
-  const int c = (int)(e - pos * C);
-  const float xs = P[pos * 2 * C + C + c];
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// CDF table index of one scale logit: sigma = clamp(softplus(x), 0.11, 64)
+// in float32, then the number of thresholds <= sigma (thr[63] = +inf).
+__device__ __forceinline__ uint32_t scale_index(float xs, const float* s_thr) {
   const float sp = fmaxf(xs, 0.f) + log1pf(expf(-fabsf(xs)));
   const float sigma = fminf(fmaxf(sp, 0.11f), 64.f);
-  // number of thresholds <= sigma (thr[63] = +inf)
-  int k = 0;
+  uint32_t k = 0;
 #pragma unroll
-  for (int step = 32; step > 0; step >>= 1)
+  for (uint32_t step = 32; step > 0; step >>= 1)
     if (s_thr[k + step - 1] <= sigma) k += step;
-  idx[e] = (uint8_t)k;
+  return k;
+}
+
+// Four consecutive latent elements e .. e + 3 (e % 4 == 0, C % 4 == 0: one
+// position, four channels): 16-byte loads of the scale logits (and, in the
+// encoder, of the means and y), one 4-byte store of indices (and symbols).
+__device__ __forceinline__ void params_quad(const float* __restrict__ P, const float* __restrict__ y,
+                                            const float* s_thr, uint8_t* __restrict__ idx,
+                                            uint8_t* __restrict__ sym, int C, long e) {
+  const long pos = e / C;
+  const int c = (int)(e - pos * C);
+  const v4f xs = ldg(reinterpret_cast<const v4f*>(P + pos * 2 * C + C + c));
+  uint32_t iq = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) iq |= scale_index(xs[k], s_thr) << (8 * k);
+  stg(reinterpret_cast<uint32_t*>(idx + e), iq);
   if (y) {
-    const float mu = P[pos * 2 * C + c];
-    const float r = fminf(fmaxf(rintf(y[e] - mu), -32.f), 32.f);
-    sym[e] = (uint8_t)((int)r + 32);
+    const v4f mu = ldg(reinterpret_cast<const v4f*>(P + pos * 2 * C + c));
+    const v4f yy = ldg(reinterpret_cast<const v4f*>(y + e));
+    uint32_t sq = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float r = fminf(fmaxf(rintf(yy[k] - mu[k]), -32.f), 32.f);
+      sq |= (uint32_t)((int)r + 32) << (8 * k);
+    }
+    stg(reinterpret_cast<uint32_t*>(sym + e), sq);
   }
 }
 
@@ -136,10 +155,10 @@ params_epilogue_kernel(const float* __restrict__ P, const float* __restrict__ y,
   __shared__ float s_thr[64];
   if (threadIdx.x < 64) s_thr[threadIdx.x] = thr[threadIdx.x];
   __syncthreads();
-  const long total = npos * C;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (long)gridDim.x * blockDim.x)
-    params_element(P, y, s_thr, idx, sym, C, e);
+  const long quads = npos * C / 4;
+  for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < quads;
+       q += (long)gridDim.x * blockDim.x)
+    params_quad(P, y, s_thr, idx, sym, C, 4 * q);
 }
 
 __global__ void __launch_bounds__(256)
@@ -153,16 +172,17 @@ params_epilogue_batch_kernel(const EpiDesc* __restrict__ descs, const int2* __re
   const long total = d.npos * d.C;
   const long e0 = (long)w.y * EPI_BLOCK_ELEMS;
   const long e1 = min(e0 + EPI_BLOCK_ELEMS, total);
-  for (long e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-    params_element(d.P, d.y, s_thr, d.idx, d.sym, d.C, e);
+  for (long e = e0 + 4 * threadIdx.x; e < e1; e += 4 * blockDim.x)
+    params_quad(d.P, d.y, s_thr, d.idx, d.sym, d.C, e);
 }
 
 hipError_t launch_params_epilogue(const float* P, const float* y, const float* thr,
                                   uint8_t* idx, uint8_t* sym, long npos, int C,
                                   hipStream_t s) {
-  const long total = npos * C;
-  long blocks = (total + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
+  if (C % 4) return hipErrorInvalidValue;
+  const long quads = npos * C / 4;
+  long blocks = (quads + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(params_epilogue_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
                      P, y, thr, idx, sym, npos, C);
