@@ -277,10 +277,10 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
   });
   // both params stages use the encoder's tuning key (one choice for both)
   auto params_stage = [&](ConvStage& st, int id) {
-    stage(st, id, P_F32, LD_UP2, ST_F32, 1, -1, [&](int i, int&) {
+    stage(st, id, P_BF16, LD_UP2, ST_F32, 1, -1, [&](int i, int&) {
       const ChunkPlan& q = P.chunks[i];
       ConvArgs a = conv_of(q.g.h, q.g.w, q.g.h, q.g.w, b->models[q.model]->p);
-      a.in = A + q.zsym; a.out = A + q.P; a.out_pitch = 2 * C;
+      a.in = A + q.zsym; a.in_pitch = ZC; a.out = A + q.P; a.out_pitch = 2 * C;
       return a;
     });
   };

@@ -161,6 +161,30 @@ static int upload_layer(Layer& L, const std::vector<const float*>& src, int cout
   return UFVC_OK;
 }
 
+// Entropy-parameter conv weights for the bf16 matrix cores: every float32
+// weight w is the exact sum of three bf16 values h + m + l (8 significant
+// bits each cover w's 24), stored as three input-channel blocks [h | m | l]
+// of the [cout][3 cin][3][3] layer whose loader repeats the cin symbol
+// channels three times.  The symbols (-32..32) are exact in bf16 as well, so
+// every product is exact and the sums run in float32 as in a float32 conv.
+static int upload_split_layer(Layer& L, const float* W, int cout, int cin) {
+  std::vector<float> parts((size_t)cout * 3 * cin * 9);
+  for (int n = 0; n < cout; ++n)
+    for (int ci = 0; ci < cin; ++ci)
+      for (int tap = 0; tap < 9; ++tap) {
+        const float w = W[((size_t)n * cin + ci) * 9 + tap];
+        const float h = (float)(__bf16)w;
+        const float r1 = w - h;
+        const float m = (float)(__bf16)r1;
+        const float r2 = r1 - m;
+        const float l = (float)(__bf16)r2;
+        if (l != r2 || (double)h + (double)m + (double)l != (double)w) return UFVC_E_UNSUPPORTED;
+        const float v[3] = {h, m, l};
+        for (int j = 0; j < 3; ++j) parts[((size_t)n * 3 * cin + j * cin + ci) * 9 + tap] = v[j];
+      }
+  return upload_layer(L, {parts.data()}, cout, 3 * cin, P_BF16);
+}
+
 static void free_ws(ufvc_ctx* c) {
   Workspace& w = c->ws;
   void* ptrs[] = {w.act0, w.act1, w.y, w.zsym, w.P, w.idx, w.sym, w.big0, w.big1};
@@ -343,7 +367,7 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
   if (!rc) rc = upload_layer(c->a2, {wa2}, C, C, cp);
   if (!rc) rc = upload_layer(c->a3, {wa3}, C, C, cp);
   if (!rc) rc = upload_layer(c->h, {wh}, ZC, C, P_F32);
-  if (!rc) rc = upload_layer(c->p, {wp}, 2 * C, ZC, P_F32);
+  if (!rc) rc = upload_split_layer(c->p, wp, 2 * C, ZC);
   if (!rc) rc = upload_layer(c->d1, {wd1}, C, C, cp);
   if (!rc) rc = upload_layer(c->d2, {wd2}, C, C, sp);
   if (!rc) rc = upload_layer(c->d3, {wd3}, C, C, sp);
@@ -430,10 +454,10 @@ int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uin
   CK(stage(c, S_HYPER, s, [&] { return tuned_conv(c, S_HYPER, P_F32, LD_NHWC, ST_ZSYM, a, 1, s, 2); }));
   // entropy parameters in one pass from up2(z_hat)
   a = conv_args(g.h, g.w, g.h, g.w, c->p);
-  a.in = ws.zsym; a.out = ws.P; a.out_pitch = 2 * C;
+  a.in = ws.zsym; a.in_pitch = ZC; a.out = ws.P; a.out_pitch = 2 * C;
   // (tuned under one key for the encoder and the decoder; every configuration
   // gives the same results in any case)
-  CK(stage(c, S_PARAMS_ENC, s, [&] { return tuned_conv(c, S_PARAMS_ENC, P_F32, LD_UP2, ST_F32, a, 1, s); }));
+  CK(stage(c, S_PARAMS_ENC, s, [&] { return tuned_conv(c, S_PARAMS_ENC, P_BF16, LD_UP2, ST_F32, a, 1, s); }));
   CK(stage(c, S_EPI_ENC, s, [&] { return launch_params_epilogue(ws.P, ws.y, c->tab.thresholds, ws.idx, ws.sym, (long)g.h * g.w, C, s); }));
   // rANS: z with the fixed row, y with per-element rows
   EncStream ez{ws.zsym, nullptr, K_Z, g.nz, c->cfg.seg_log2_z, g.nseg_z};
@@ -471,8 +495,8 @@ int ufvc_decode_chunk(ufvc_ctx* c, const uint8_t* bs, size_t len, int T, int H, 
   DecStream dz{nullptr, K_Z, g.nz, c->cfg.seg_log2_z, g.nseg_z, 0, ws.zsym, len};
   CK(stage(c, S_RANS_DEC_Z, s, [&] { return launch_rans_decode(c->tab, bs, c->rw.seg_off, c->rw.seg_len, dz, c->status, s); }));
   ConvArgs a = conv_args(g.h, g.w, g.h, g.w, c->p);
-  a.in = ws.zsym; a.out = ws.P; a.out_pitch = 2 * C;
-  CK(stage(c, S_PARAMS_DEC, s, [&] { return tuned_conv(c, S_PARAMS_ENC, P_F32, LD_UP2, ST_F32, a, 1, s); }));
+  a.in = ws.zsym; a.in_pitch = ZC; a.out = ws.P; a.out_pitch = 2 * C;
+  CK(stage(c, S_PARAMS_DEC, s, [&] { return tuned_conv(c, S_PARAMS_ENC, P_BF16, LD_UP2, ST_F32, a, 1, s); }));
   CK(stage(c, S_EPI_DEC, s, [&] { return launch_params_epilogue(ws.P, nullptr, c->tab.thresholds, ws.idx, nullptr, (long)g.h * g.w, C, s); }));
   // all of r_hat in one launch: its tables depend on sigma only
   DecStream dy{ws.idx, 0, g.ny, c->cfg.seg_log2, g.nseg_y, g.nseg_z, ws.sym, len};

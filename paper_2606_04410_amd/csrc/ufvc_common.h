@@ -55,7 +55,8 @@ enum Loader {
   LD_NHWC = 0,       // activation tensor, channels innermost, compute type
   LD_UNSHUFFLE = 1,  // float32 frames [T][3][H][W], pixel-unshuffle x8 + replicate pad
   LD_DEQUANT = 2,    // y_hat = (sym - 32) + mu from uint8 symbols and float32 mu
-  LD_UP2 = 3,        // nearest x2 upsampling of uint8 z symbols (value sym - 32)
+  LD_UP2 = 3,        // nearest x2 upsampling of uint8 z symbols (value sym - 32), bf16;
+                     // input channel c is symbol channel c mod in_pitch
   LD_F32 = 4,        // float32 tensor, channels innermost, feeding a bf16 conv
   LD_Q8 = 5          // bf16 tensor quantised to FP8 E4M3 with the producer's amax scale
 };
@@ -123,7 +124,7 @@ struct Tables {
   uint32_t* fc;      // [64][65] freq | cum << 16
   uint32_t* magic;   // [64][65] division multiplier for freq
   uint8_t* shift;    // [64][65] ceil(log2(freq))
-  uint16_t* lut;     // [64][512] decoder lookup per 128-slot bucket
+  uint16_t* lut;     // [64][256] decoder lookup per 256-slot bucket
   float* thresholds; // [64] (63 used, [63] = +inf)
   uint8_t* tail;     // [64] length of the leading run of frequency-1 symbols
 };

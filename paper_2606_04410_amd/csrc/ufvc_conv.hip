@@ -23,7 +23,8 @@
 // Loaders fuse the producer's layout change into the halo fetch: the x8
 // pixel-unshuffle of the patch embedding with edge-replicated padding
 // (Sec. 3.1), y_hat = r_hat + mu dequantisation (Sec. 3.4), and nearest x2
-// upsampling of the hyper latent.  Epilogues fuse ReLU, the float32 or bf16
+// upsampling of the hyper latent (repeated over the three bf16 parts of the
+// float32 entropy-parameter weights).  Epilogues fuse ReLU, the float32 or bf16
 // store, rounding of z, and the x8 pixel-shuffle store of the frame
 // decoders with crop and clamp (Sec. 3.2).
 #include <algorithm>
@@ -142,13 +143,13 @@ __device__ __forceinline__ Raw fetch_raw(const ConvArgs& a, const unsigned char*
       r.c.x = ldg(reinterpret_cast<const uint32_t*>(sp));
       r.a = __builtin_bit_cast(v4u, ldg(reinterpret_cast<const v4f*>(mp)));
     }
-  } else {  // LD_UP2, float32 compute
-    static_assert(PREC == P_F32, "up2 loader is float32 only");
-    const int c0 = slice * E + ch * (E / 2);
+  } else {  // LD_UP2: input channel c reads symbol channel c mod in_pitch
+    static_assert(PREC == P_BF16, "up2 loader feeds the bf16 split-weight conv");
+    const int c0 = (slice * E + ch * (E / 2)) % (int)a.in_pitch;
     const int wz = (a.Win + 1) >> 1;
     const unsigned char* sp = reinterpret_cast<const unsigned char*>(a.in) +
-                              ((long)(iy >> 1) * wz + (ix >> 1)) * a.cin + c0;
-    r.c.x = ldg(reinterpret_cast<const uint32_t*>(sp));
+                              ((long)(iy >> 1) * wz + (ix >> 1)) * a.in_pitch + c0;
+    r.c = ldg(reinterpret_cast<const v2u*>(sp));
   }
   return r;
 }
@@ -212,14 +213,15 @@ __device__ __forceinline__ v4u convert_raw(const Raw& r, float qinv) {
       f[3] = (float)((int)(sb >> 24) - 32) + m.w;
       o = __builtin_bit_cast(v4u, f);
     }
-  } else {  // LD_UP2
-    const uint32_t sb = r.c.x;
-    v4f f;
-    f[0] = (float)((int)(sb & 255) - 32);
-    f[1] = (float)((int)((sb >> 8) & 255) - 32);
-    f[2] = (float)((int)((sb >> 16) & 255) - 32);
-    f[3] = (float)((int)(sb >> 24) - 32);
-    o = __builtin_bit_cast(v4u, f);
+  } else {  // LD_UP2: symbols -32..32 are exact in bf16
+    const v2u sb = r.c;
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = (float)((int)((sb.x >> (8 * k)) & 255) - 32);
+      v[4 + k] = (float)((int)((sb.y >> (8 * k)) & 255) - 32);
+    }
+    o = cvt8(v);
   }
   return r.ok ? o : zero16();
 }
@@ -1007,15 +1009,16 @@ static hipError_t dispatch(int prec, int loader, int store, int stride, int cfg,
   UFVC_CONV(P_BF16, LD_DEQUANT, ST_BF16, 1)
   UFVC_CONV(P_BF16, LD_NHWC, ST_SHUFFLE, 1)
   UFVC_CONV(P_BF16, LD_F32, ST_BF16, 1)
+  // entropy parameters: float32 weights as three bf16 parts (exact products)
+  UFVC_CONV(P_BF16, LD_UP2, ST_F32, 1)
   // fp8 synthesis
   UFVC_CONV(P_FP8, LD_Q8, ST_BF16, 1)
   UFVC_CONV(P_FP8, LD_Q8, ST_SHUFFLE, 1)
-  // float32 everything, plus hyper prior and entropy parameters
+  // float32 everything, plus the hyper prior
   UFVC_CONV(P_F32, LD_UNSHUFFLE, ST_F32, 1)
   UFVC_CONV(P_F32, LD_NHWC, ST_F32, 1)
   UFVC_CONV(P_F32, LD_DEQUANT, ST_F32, 1)
   UFVC_CONV(P_F32, LD_NHWC, ST_SHUFFLE, 1)
-  UFVC_CONV(P_F32, LD_UP2, ST_F32, 1)
   UFVC_CONV(P_F32, LD_NHWC, ST_ZSYM, 2)
 #undef UFVC_CONV
   return hipErrorInvalidValue;

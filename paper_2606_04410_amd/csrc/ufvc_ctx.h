@@ -148,8 +148,6 @@ inline ConvArgs conv_args(int Hin, int Win, int Hout, int Wout, const Layer& L) 
   return a;
 }
 
-// Tile configuration: the widest channel tile that divides the layer's outputs.
-
 }  // namespace ufvc
 
 // Batch executor hooks used by the request server (defined in ufvc_batch.hip).

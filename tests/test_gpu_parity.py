@@ -139,6 +139,16 @@ def test_rans_rejects_corruption():
 
 
 # ------------------------------------------------------------- end to end
+def _conv_f32(x, wt):
+    """3x3 conv, zero padding 1, as one float32 matrix product (a plain
+    float32 conv, for the size of float32 rounding)."""
+    cin, hh, wd = x.shape
+    xp = np.pad(x.astype(np.float32), ((0, 0), (1, 1), (1, 1)))
+    cols = np.stack([xp[:, dy:dy + hh, dx:dx + wd] for dy in range(3) for dx in range(3)], axis=1)
+    out = wt.astype(np.float32).reshape(wt.shape[0], -1) @ cols.reshape(cin * 9, -1)
+    return out.reshape(-1, hh, wd)
+
+
 def _check_stages(c, fr, w, H, W, y_tol):
     """Compare GPU encoder stages with the oracle, isolating each stage."""
     T = fr.shape[0]
@@ -161,6 +171,18 @@ def _check_stages(c, fr, w, H, W, y_tol):
     z_hat = np.transpose(g_z, (2, 0, 1)).astype(np.float64)
     mu, sigma = nets.params(z_hat, w, h, ww)
     assert float(np.abs(g_P[..., :C] - to_hwc(mu)).max()) < 1e-4
+    # the params conv is float32 arithmetic: exact products (split weights)
+    # and float32 sums, so its distance from the float64 conv is of the size
+    # of a plain float32 conv's.  Without the third weight part the mean
+    # distance would be about 10x that.
+    zu = nets.up2(z_hat, h, ww)
+    P64 = to_hwc(nets.conv(zu, w["p"]))
+    d_gpu = np.abs(g_P.astype(np.float64) - P64)
+    d_f32 = np.abs(to_hwc(_conv_f32(zu, w["p"])).astype(np.float64) - P64)
+    say(f"  params conv distance mean/max {d_gpu.mean():.3e}/{d_gpu.max():.3e} "
+        f"(float32 conv {d_f32.mean():.3e}/{d_f32.max():.3e})")
+    assert d_gpu.mean() <= 3 * d_f32.mean() + 1e-12
+    assert d_gpu.max() <= 8 * d_f32.max() + 1e-9
     o_idx = to_hwc(entropy.scale_index(sigma))
     imis = g_idx != o_idx
     say(f"  idx mismatches {int(imis.sum())} (near-threshold allowed)")
