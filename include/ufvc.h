@@ -48,8 +48,13 @@ typedef enum {
   UFVC_E_UNSUPPORTED = -6  /* configuration outside what the kernels support */
 } ufvc_status;
 
+/* In every mode the hyper conv runs in float32 and the entropy-parameter
+ * conv in float32 arithmetic: its float32 weights are split exactly into
+ * three bf16 parts and its input (the integer hyper latent) is exact in
+ * bf16, so the bf16 matrix cores form every product exactly and the sums
+ * stay float32, in a fixed order (Sec. 3.4). */
 typedef enum {
-  UFVC_FP32 = 0,      /* every convolution in float32 (MFMA f32) */
+  UFVC_FP32 = 0,      /* every other convolution in float32 (MFMA f32) */
   UFVC_BF16 = 1,      /* analysis and synthesis convs bf16 MFMA, fp32 accumulate */
   UFVC_BF16_FP8 = 2   /* as BF16, synthesis convs in FP8 E4M3 */
 } ufvc_precision;
@@ -77,7 +82,9 @@ size_t ufvc_weight_count(int T, int C);
  * host float32 `weights` (n_weights values, layout above; read only during
  * the call, still owned by the caller) into the kernels' layouts, and builds
  * the Gaussian CDF tables in FP64 on the device.  Blocks until done.
- * Errors: INVAL (cfg or n_weights), UNSUPPORTED, NOMEM, DEVICE. */
+ * Errors: INVAL (cfg or n_weights), UNSUPPORTED (also an entropy-parameter
+ * weight that three bf16 parts cannot hold exactly: non-finite, or too close
+ * to the bottom of the float32 range), NOMEM, DEVICE. */
 int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights,
                 ufvc_ctx** out);
 
