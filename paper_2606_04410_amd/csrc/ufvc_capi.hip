@@ -53,7 +53,7 @@ static hipError_t tuned_conv(ufvc_ctx* c, int id, int prec, int ld, int st, cons
   auto it = c->tune.find(key);
   if (it != c->tune.end()) return launch_conv(prec, ld, st, stride, it->second, a, groups, s);
   if (!c->cfg.autotune)
-    return launch_conv(prec, ld, st, stride, default_cfg(a.cout, (long)a.Hout * a.Wout), a, groups, s);
+    return launch_conv(prec, ld, st, stride, default_cfg(a.cout, (long)a.Hout * a.Wout, stride), a, groups, s);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hipErrorOutOfMemory;
   int best = -1;
@@ -183,6 +183,25 @@ static int upload_split_layer(Layer& L, const float* W, int cout, int cin) {
         for (int j = 0; j < 3; ++j) parts[((size_t)n * 3 * cin + j * cin + ci) * 9 + tap] = v[j];
       }
   return upload_layer(L, {parts.data()}, cout, 3 * cin, P_BF16);
+}
+
+// Hyper conv weights for hyper_conv_kernel: OIHW float32 [cout][cin][3][3]
+// to [tap][cin / 4][cout][4] (four consecutive input channels per 16 bytes).
+static int upload_hyper_layer(Layer& L, const float* W, int cout, int cin) {
+  if (cin % 16 || cout % 16) return UFVC_E_UNSUPPORTED;
+  std::vector<float> pk((size_t)9 * cin * cout);
+  for (int tap = 0; tap < 9; ++tap)
+    for (int ci = 0; ci < cin; ++ci)
+      for (int n = 0; n < cout; ++n)
+        pk[(((size_t)tap * (cin / 4) + ci / 4) * cout + n) * 4 + ci % 4] = W[((size_t)n * cin + ci) * 9 + tap];
+  if (hipMalloc(&L.w, pk.size() * 4) != hipSuccess) return UFVC_E_NOMEM;
+  CK(hipMemcpy(L.w, pk.data(), pk.size() * 4, hipMemcpyHostToDevice));
+  L.gstride = (long)pk.size() * 4;
+  L.cin = cin;
+  L.cout = cout;
+  L.groups = 1;
+  L.prec = P_F32;
+  return UFVC_OK;
 }
 
 static void free_ws(ufvc_ctx* c) {
@@ -366,7 +385,7 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
   if (!rc) rc = upload_layer(c->a1, {wa1}, C, 192 * T, cp);
   if (!rc) rc = upload_layer(c->a2, {wa2}, C, C, cp);
   if (!rc) rc = upload_layer(c->a3, {wa3}, C, C, cp);
-  if (!rc) rc = upload_layer(c->h, {wh}, ZC, C, P_F32);
+  if (!rc) rc = upload_hyper_layer(c->h, wh, ZC, C);
   if (!rc) rc = upload_split_layer(c->p, wp, 2 * C, ZC);
   if (!rc) rc = upload_layer(c->d1, {wd1}, C, C, cp);
   if (!rc) rc = upload_layer(c->d2, {wd2}, C, C, sp);

@@ -105,6 +105,7 @@ hipError_t launch_conv_batch(int prec, int loader, int store, int stride, int cf
 
 // Tile configurations: output rows x cols per workgroup and channel tile.
 struct TileCfg { int th, tw, bn; };
+constexpr int kHyperCfg = 24;   // the stride-2 hyper conv's configuration (its own kernel)
 int conv_num_cfgs();
 TileCfg conv_cfg(int cfg);
 // false for tile configurations a layer cannot use (precision, loader,

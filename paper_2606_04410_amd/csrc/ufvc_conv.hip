@@ -18,7 +18,9 @@
 // a loader converts.  Reduction order is fixed: slice, then tap, then the
 // MFMA's own order, and does not depend on the tile configuration, so results
 // do not depend on how many workgroups cover the output.  A second kernel
-// family (conv3x3_ring_kernel, below) serves bf16 activations at stride 1.
+// family (conv3x3_ring_kernel, below) serves bf16 activations at stride 1,
+// and hyper_conv_kernel the stride-2 hyper conv (the first family's stride-2
+// form is not instantiated).
 //
 // Loaders fuse the producer's layout change into the halo fetch: the x8
 // pixel-unshuffle of the patch embedding with edge-replicated padding
@@ -292,6 +294,94 @@ struct Pipe {
       LD == LD_NHWC && (PREC == P_BF16 || PREC == P_F32) && 2 * STAGE <= 160 * 1024;
   static constexpr int LDS = DIRECT ? 2 * STAGE : (HP + 9 * BN) * ROWB;
 };
+
+// Hyper-prior conv (Sec. 3.4): stride 2, pad 1, float32 operands on the
+// matrix cores, z_hat = clamp(rint(z), -32, 32) stored as uint8 z_hat + 32.
+// One wave per unit of 16 output positions of one row x 16 output channels
+// (v_mfma_f32_16x16x4f32): with 32 output channels this gives four times the
+// waves of a 32x32-block tiling, each with a quarter of the serial MFMA
+// chain, and the layer is too small for anything but that chain to matter.
+// Lane l holds position l % 16 of the unit (A row) and channel l % 16 (B
+// column); lane group g = l / 16 holds channels 4g..4g+3 of each 16-channel
+// chunk, and MFMA j of the chunk takes channel 4g + j.  K order: tap, chunk,
+// j, then the MFMA's own sum.  Operands come straight from device memory
+// (L2-resident, 16-byte loads, clamped into bounds, zero outside the input),
+// nine K steps ahead of the multiplications; the steps are unrolled per
+// input-channel count (64 or 128) so that the loads stay where they are.
+// Weights are packed [tap][cin / 4][cout][4] floats.
+template <int NCH>
+__device__ __forceinline__ v4f hyper_mac(const ConvArgs& a, int oy, int ox, int g, const float* y,
+                                         const float* wl) {
+  constexpr int NS = 9 * NCH, D = 9;
+  const long wtap = (long)(16 * NCH) * a.cout;   // floats per tap
+  const long wchunk = 16L * a.cout;               // floats per 16 input channels
+  v4f va[NS], vb[NS];
+  bool ok[NS];
+  auto load = [&](int k) {
+    const int tap = k / NCH, cc = (k % NCH) * 16;
+    const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
+    ok[k] = ox < a.Wout && iy >= 0 && ix >= 0 && iy < a.Hin && ix < a.Win;
+    va[k] = ldg(reinterpret_cast<const v4f*>(
+        y + ((long)min(max(iy, 0), a.Hin - 1) * a.Win + min(max(ix, 0), a.Win - 1)) * a.in_pitch + 4 * g + cc));
+    vb[k] = ldg(reinterpret_cast<const v4f*>(wl + tap * wtap + (k % NCH) * wchunk));
+  };
+#pragma unroll
+  for (int k = 0; k < D; ++k) load(k);
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    if (k + D < NS) load(k + D);
+    // keep the prefetch ahead of this step's multiplications (the scheduler
+    // would otherwise move each load down to its use)
+    __builtin_amdgcn_sched_barrier(0);
+    const v4f av = ok[k] ? va[k] : v4f{0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, vb[k].x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, vb[k].y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, vb[k].z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, vb[k].w, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// (One wave per SIMD is the target: the registers go to loads in flight.)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2)))
+hyper_conv_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __restrict__ work,
+                  int nwork) {
+  ConvArgs a;
+  int tile, n0;
+  if (descs) {
+    const int wi = blockIdx.x;
+    if (wi >= nwork) return;
+    const int4 w = work[wi];
+    a = descs[w.x];
+    tile = w.y;
+    n0 = w.z;
+  } else {
+    a = a0;
+    const int nt = a.Hout * ((a.Wout + 15) / 16);
+    const int per = (nt + 7) >> 3;
+    tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tile >= nt) return;
+    n0 = blockIdx.y * 16;
+  }
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4;
+  const int tiles_x = (a.Wout + 15) / 16;
+  const int oy = tile / tiles_x;
+  const int ox0 = (tile - oy * tiles_x) * 16;
+  const int ox = ox0 + (lane & 15);
+  const float* __restrict__ y = static_cast<const float*>(a.in);
+  const float* __restrict__ wl =
+      static_cast<const float*>(a.wpk) + ((long)g * a.cout + n0 + (lane & 15)) * 4;
+  // cin is 64 or 128 (checked on the host for every problem)
+  const v4f acc = a.cin == 128 ? hyper_mac<8>(a, oy, ox, g, y, wl) : hyper_mac<4>(a, oy, ox, g, y, wl);
+  // acc[r]: position 4g + r of the unit, channel lane % 16
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int px = ox0 + 4 * g + r;
+    if (px < a.Wout) store_out<ST_ZSYM>(a, 0, oy, px, n0 + (lane & 15), acc[r]);
+  }
+}
 
 // Zero chunk for halo positions outside the input (conv zero padding).
 __device__ __attribute__((aligned(64))) unsigned char kZeroChunk[64];
@@ -865,19 +955,26 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
 //     first family again:
 //     20 = 8x16 tile,  64 channels, 4x1 waves of 32x64
 //     21 = 16x16 tile,  64 channels, 4x1 waves of 64x64
-//     22 = 2x16 tile,  32 channels, one wave (small outputs: the stride-2 hyper conv)
+//     22 = 2x16 tile,  32 channels, one wave (small outputs)
 //     23 = 4x16 tile,  32 channels, 2x1 waves of 32x32
+//   hyper_conv_kernel (the stride-2 hyper conv, float32, and nothing else):
+//     24 = 1x16 tile,  16 channels, one wave of 16x16
 static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 16, 128},
                                 {8, 16, 64},  {16, 16, 128}, {16, 16, 192}, {16, 16, 64},
                                 {16, 16, 128}, {16, 16, 64},
                                 {16, 16, 128}, {8, 16, 128}, {8, 16, 64},  {16, 16, 64},
                                 {16, 16, 128}, {16, 16, 192}, {8, 16, 192}, {8, 16, 32},
                                 {16, 16, 64}, {8, 16, 64},
-                                {8, 16, 64}, {16, 16, 64}, {2, 16, 32}, {4, 16, 32}};
+                                {8, 16, 64}, {16, 16, 64}, {2, 16, 32}, {4, 16, 32},
+                                {1, 16, 16}};
 constexpr int kFirstRing = 10, kLastRing = 19;
 int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int cfg) {
-  (void)cout;
+  // stride 2 (the hyper conv) has the one configuration, so its results
+  // cannot depend on the choice either
+  if (stride == 2 || cfg == kHyperCfg)
+    return cfg == kHyperCfg && stride == 2 && prec == P_F32 && loader == LD_NHWC &&
+           (cin == 64 || cin == 128) && cout % 16 == 0;
   if (cfg >= kFirstRing && cfg <= kLastRing)
     return prec == P_BF16 && loader == LD_NHWC && stride == 1 && cin % 16 == 0;
   if (cfg >= conv_num_cfgs()) return false;
@@ -949,9 +1046,30 @@ static hipError_t run_ring(const ConvArgs& a, int groups, const ConvArgs* descs,
   return hipGetLastError();
 }
 
+static hipError_t run_hyper(const ConvArgs& a, int groups, const ConvArgs* descs, const int4* work,
+                            int nwork, hipStream_t s) {
+  dim3 grid;
+  if (descs) {
+    if (nwork <= 0) return hipSuccess;
+    grid = dim3(((nwork + 7) / 8) * 8, 1, 1);
+  } else {
+    if (groups != 1 || a.cout % 16 || (a.cin != 64 && a.cin != 128)) return hipErrorInvalidValue;
+    const int tiles = a.Hout * ((a.Wout + 15) / 16);
+    grid = dim3(((tiles + 7) / 8) * 8, a.cout / 16, 1);
+  }
+  hipLaunchKernelGGL(hyper_conv_kernel, grid, dim3(64), 0, s, a, descs, work, nwork);
+  return hipGetLastError();
+}
+
 template <int PREC, int LD, int ST, int STRIDE>
 static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs* d,
                           const int4* w, int nw, hipStream_t s) {
+  if constexpr (STRIDE == 2) {
+    // the hyper conv: its one configuration
+    if constexpr (PREC == P_F32 && LD == LD_NHWC && ST == ST_ZSYM)
+      if (cfg == kHyperCfg) return run_hyper(a, groups, d, w, nw, s);
+    return hipErrorInvalidValue;
+  }
   switch (cfg) {
     case 0: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 2>(a, groups, d, w, nw, s);
     case 1: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 4, 1, 1, 1>(a, groups, d, w, nw, s);

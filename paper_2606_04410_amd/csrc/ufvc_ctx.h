@@ -92,7 +92,8 @@ static const char* kStageNames[S_COUNT] = {
 
 
 namespace ufvc {
-inline int default_cfg(int cout, long npos) {
+inline int default_cfg(int cout, long npos, int stride = 1) {
+  if (stride == 2) return kHyperCfg;
   if (cout % 128 == 0) return npos >= 16384 ? 5 : 0;
   if (cout % 192 == 0) return 2;
   if (cout % 64 == 0) return 4;
