@@ -324,6 +324,22 @@ def run_fp8_c4(torch, ufvc, steps, seg_log2, seg_log2_z, n_chunks=16):
     if code != 0:
         raise RuntimeError(f"fp8 batch decode status {st}")
     same = all(int(lens[i]) == sizes["bf16_fp8"][i] for i in range(len(frames)))
+    # one chunk at a time: the synthesis convs' HIP-event times, FP8 next to BF16
+    synth = ("d1_conv", "d2_conv", "d3_conv", "k1_conv", "k2_conv", "k3_conv")
+    one_chunk = {}
+    for p in ("bf16_fp8", "bf16"):
+        c = codecs[p]
+        torch.cuda.synchronize()
+        c.profile(True)
+        reps = 5
+        for _ in range(reps):
+            bs, n = c.encode(frames[0])
+            c.decode(bs, n, H, W, check=False)
+        torch.cuda.synchronize()
+        stg = c.profile_read()
+        c.profile(False)
+        one_chunk[p] = {k: round(v[0] / reps, 4) for k, v in stg.items() if k in synth}
+        one_chunk[p]["synthesis"] = round(sum(v[0] for k, v in stg.items() if k in synth) / reps, 4)
     d8 = np.array(per["bf16_fp8"]) - np.array(per["fp32"])
     d16 = np.array(per["bf16"]) - np.array(per["fp32"])
     dsize = np.array(sizes["bf16_fp8"], np.float64) / np.array(sizes["fp32"]) - 1
@@ -337,6 +353,7 @@ def run_fp8_c4(torch, ufvc, steps, seg_log2, seg_log2_z, n_chunks=16):
            "bitstream_size_delta_vs_fp32": {"min": round(float(dsize.min()), 6),
                                             "max": round(float(dsize.max()), 6)},
            "per_chunk_psnr_db": {p: [round(x, 3) for x in v] for p, v in per.items()},
+           "one_chunk_synthesis_ms": one_chunk,
            "precision": "analysis bf16, synthesis fp8 e4m3 (d1 bf16), params fp32, tables fp64"}
     batch.close()
     for c in codecs.values():
