@@ -511,8 +511,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build measures the single-GPU hot path "
-              "(whole chunks shard across GPUs with no exchange; see DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: it measures the single-GPU hot path "
+              "(whole chunks shard across GPUs with no exchange between them).", file=sys.stderr)
         sys.exit(2)
 
     import torch
