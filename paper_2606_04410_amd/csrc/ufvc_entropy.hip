@@ -110,30 +110,44 @@ hipError_t launch_build_tables(const Tables& t, hipStream_t s) {
 // ------------------------------------------------------ params epilogue ----
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// Threshold table of the scale index, in LDS, with its log spacing.  The
+// thresholds are geometric midpoints of log-spaced scales, so the count of
+// thresholds <= sigma is within one of 1 + floor((log sigma - log t0) / step)
+// (step = log(t62 / t0) / 62); one exact float32 comparison each way fixes it.
+struct ThrTable {
+  const float* t;   // 64 floats, t[63] = +inf
+  float lt0, inv_step;
+};
+__device__ __forceinline__ ThrTable thr_table(const float* s_thr) {
+  const float lt0 = __logf(s_thr[0]);
+  return ThrTable{s_thr, lt0, 62.f / (__logf(s_thr[62]) - lt0)};
+}
+
 // CDF table index of one scale logit: sigma = clamp(softplus(x), 0.11, 64)
-// in float32, then the number of thresholds <= sigma (thr[63] = +inf).
-__device__ __forceinline__ uint32_t scale_index(float xs, const float* s_thr) {
-  const float sp = fmaxf(xs, 0.f) + log1pf(expf(-fabsf(xs)));
+// in float32 (softplus as max(x, 0) + log1p(exp(-|x|)), with the hardware
+// exp and log), then the number of thresholds <= sigma.
+__device__ __forceinline__ uint32_t scale_index(float xs, const ThrTable& tt) {
+  const float sp = fmaxf(xs, 0.f) + __logf(1.f + __expf(-fabsf(xs)));
   const float sigma = fminf(fmaxf(sp, 0.11f), 64.f);
-  uint32_t k = 0;
-#pragma unroll
-  for (uint32_t step = 32; step > 0; step >>= 1)
-    if (s_thr[k + step - 1] <= sigma) k += step;
-  return k;
+  const int g = (int)floorf((__logf(sigma) - tt.lt0) * tt.inv_step) + 1;
+  const int k0 = min(max(g, 0), 63);
+  const float lo = tt.t[max(k0 - 1, 0)];
+  const float hi = tt.t[k0];
+  return (uint32_t)(k0 - ((k0 > 0 && lo > sigma) ? 1 : 0) + (hi <= sigma ? 1 : 0));
 }
 
 // Four consecutive latent elements e .. e + 3 (e % 4 == 0, C % 4 == 0: one
 // position, four channels): 16-byte loads of the scale logits (and, in the
 // encoder, of the means and y), one 4-byte store of indices (and symbols).
 __device__ __forceinline__ void params_quad(const float* __restrict__ P, const float* __restrict__ y,
-                                            const float* s_thr, uint8_t* __restrict__ idx,
+                                            const ThrTable& tt, uint8_t* __restrict__ idx,
                                             uint8_t* __restrict__ sym, int C, long e) {
   const long pos = e / C;
   const int c = (int)(e - pos * C);
   const v4f xs = ldg(reinterpret_cast<const v4f*>(P + pos * 2 * C + C + c));
   uint32_t iq = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) iq |= scale_index(xs[k], s_thr) << (8 * k);
+  for (int k = 0; k < 4; ++k) iq |= scale_index(xs[k], tt) << (8 * k);
   stg(reinterpret_cast<uint32_t*>(idx + e), iq);
   if (y) {
     const v4f mu = ldg(reinterpret_cast<const v4f*>(P + pos * 2 * C + c));
@@ -155,10 +169,11 @@ params_epilogue_kernel(const float* __restrict__ P, const float* __restrict__ y,
   __shared__ float s_thr[64];
   if (threadIdx.x < 64) s_thr[threadIdx.x] = thr[threadIdx.x];
   __syncthreads();
+  const ThrTable tt = thr_table(s_thr);
   const long quads = npos * C / 4;
   for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < quads;
        q += (long)gridDim.x * blockDim.x)
-    params_quad(P, y, s_thr, idx, sym, C, 4 * q);
+    params_quad(P, y, tt, idx, sym, C, 4 * q);
 }
 
 __global__ void __launch_bounds__(256)
@@ -167,13 +182,14 @@ params_epilogue_batch_kernel(const EpiDesc* __restrict__ descs, const int2* __re
   __shared__ float s_thr[64];
   if (threadIdx.x < 64) s_thr[threadIdx.x] = thr[threadIdx.x];
   __syncthreads();
+  const ThrTable tt = thr_table(s_thr);
   const int2 w = work[blockIdx.x];
   const EpiDesc d = descs[w.x];
   const long total = d.npos * d.C;
   const long e0 = (long)w.y * EPI_BLOCK_ELEMS;
   const long e1 = min(e0 + EPI_BLOCK_ELEMS, total);
   for (long e = e0 + 4 * threadIdx.x; e < e1; e += 4 * blockDim.x)
-    params_quad(d.P, d.y, s_thr, d.idx, d.sym, d.C, e);
+    params_quad(d.P, d.y, tt, d.idx, d.sym, d.C, e);
 }
 
 hipError_t launch_params_epilogue(const float* P, const float* y, const float* thr,
