@@ -506,10 +506,18 @@ hipError_t launch_compact_batch(const CompDesc* d, const int2* map, int nblocks,
 }
 
 // --------------------------------------------------------------- parse ----
+// One block per stream.  Thread t owns the contiguous run of segment-table
+// entries [t K, t K + K), K = ceil(n_seg / blockDim): it sums its run (the
+// only round of device-memory reads on the path; thread 0 also reads the
+// header meanwhile), one block scan of the run sums gives every run's start
+// offset, and a second pass over the run (cache hits) writes the offsets.
+// A stream is rejected, with every offset 0xFFFFFFFF, for a header that does
+// not match (ST_BAD_HEADER), or sizes below the 128 state bytes, not a
+// multiple of 4, or not tiling the rest of the stream exactly (ST_CORRUPT).
 __global__ void __launch_bounds__(256)
 parse_kernel(ParseDesc d0, const ParseDesc* __restrict__ descs) {
-  __shared__ unsigned long long red[8];
-  __shared__ int s_bad;
+  __shared__ unsigned long long s_wave[4];
+  __shared__ int s_hdr_bad;
   const ParseDesc d = descs ? descs[blockIdx.x] : d0;
   const uint8_t* __restrict__ bs = d.bs;
   const size_t len = (size_t)d.len;
@@ -521,9 +529,9 @@ parse_kernel(ParseDesc d0, const ParseDesc* __restrict__ descs) {
   uint32_t* __restrict__ status = d.status;
   const int nseg = n_seg_z + n_seg_y;
   const size_t h0 = (with_header ? 28u : 0u) + 4u * (size_t)nseg;
+  const bool short_stream = len < h0;   // the table itself is not there: nothing is read
   if (threadIdx.x == 0) {
-    int bad = 0;
-    if (len < h0) bad = 1;
+    int bad = short_stream ? 1 : 0;
     if (!bad && with_header) {
       const uint32_t* h = reinterpret_cast<const uint32_t*>(bs);
       if (h[0] != 0x31564655u) bad = 1;
@@ -533,49 +541,46 @@ parse_kernel(ParseDesc d0, const ParseDesc* __restrict__ descs) {
         bad = 1;
       if (h[4] != ex.model_tag || h[5] != (uint32_t)n_seg_z || h[6] != (uint32_t)n_seg_y) bad = 1;
     }
-    s_bad = bad;
-  }
-  __syncthreads();
-  if (s_bad) {
-    for (int i = threadIdx.x; i < nseg; i += blockDim.x) { seg_off[i] = 0xFFFFFFFFu; seg_len[i] = 0; }
-    if (threadIdx.x == 0) atomicOr(status, ST_BAD_HEADER);
-    return;
+    s_hdr_bad = bad;
   }
   const uint32_t* tab = reinterpret_cast<const uint32_t*>(bs + (with_header ? 28 : 0));
-  // sizes must be >= 128 and multiples of 4, and must tile the rest exactly
-  unsigned long long tot = 0;
+  const int K = (nseg + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int r0 = min((int)threadIdx.x * K, nseg), r1 = min(r0 + K, nseg);
+  unsigned long long run = 0;
   int badsz = 0;
-  for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
-    const uint32_t sb = tab[i];
-    if (sb < (uint32_t)SEG_STATE_BYTES || (sb & 3u)) badsz = 1;
-    tot += sb;
-  }
-  tot = block_sum(tot, red);
-  const unsigned long long nbad = block_sum((unsigned long long)badsz, red);
-  const bool ok = nbad == 0 && h0 + tot == len;
-  // exclusive scan, 256 entries at a time
-  unsigned long long carry = h0;
-  __shared__ unsigned long long sc[256];
-  for (int c0 = 0; c0 < nseg; c0 += 256) {
-    const int i = c0 + threadIdx.x;
-    const unsigned long long v = (i < nseg) ? tab[i] : 0ull;
-    sc[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-      const unsigned long long add = threadIdx.x >= o ? sc[threadIdx.x - o] : 0ull;
-      __syncthreads();
-      sc[threadIdx.x] += add;
-      __syncthreads();
+  if (!short_stream)
+    for (int i = r0; i < r1; ++i) {
+      const uint32_t sb = tab[i];
+      if (sb < (uint32_t)SEG_STATE_BYTES || (sb & 3u)) badsz = 1;
+      run += sb;
     }
-    if (i < nseg) {
-      seg_off[i] = ok ? (uint32_t)(carry + sc[threadIdx.x] - v) : 0xFFFFFFFFu;
-      seg_len[i] = ok ? (uint32_t)v : 0u;
-    }
-    const unsigned long long last = sc[255];
-    __syncthreads();
-    carry += last;
+  // inclusive scan of the run sums: within the wave, then across the waves
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned long long inc = run;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long v = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += v;
   }
-  if (!ok && threadIdx.x == 0) atomicOr(status, ST_CORRUPT);
+  if (lane == 63) s_wave[wave] = inc;
+  const int anybad = __syncthreads_or(badsz);   // also publishes s_wave and s_hdr_bad
+  unsigned long long before = 0, total = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    if (w < wave) before += s_wave[w];
+    total += s_wave[w];
+  }
+  const bool hdr_bad = s_hdr_bad != 0;
+  const bool ok = !hdr_bad && !anybad && h0 + total == len;
+  unsigned long long off = h0 + before + inc - run;   // this run's first offset
+  for (int i = r0; i < r1; ++i) {
+    const uint32_t sb = ok ? tab[i] : 0u;
+    seg_off[i] = ok ? (uint32_t)off : 0xFFFFFFFFu;
+    seg_len[i] = sb;
+    off += sb;
+  }
+  if (threadIdx.x == 0) {
+    if (hdr_bad) atomicOr(status, ST_BAD_HEADER);
+    else if (!ok) atomicOr(status, ST_CORRUPT);
+  }
 }
 
 hipError_t launch_parse(const uint8_t* bs, size_t len, int with_header, HeaderFields expect,
