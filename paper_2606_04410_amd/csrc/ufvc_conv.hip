@@ -373,7 +373,8 @@ hyper_conv_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* _
   const float* __restrict__ y = static_cast<const float*>(a.in);
   const float* __restrict__ wl =
       static_cast<const float*>(a.wpk) + ((long)g * a.cout + n0 + (lane & 15)) * 4;
-  // cin is 64 or 128 (checked on the host for every problem)
+  // cin is 64 or 128: the channel counts a context accepts (the single-launch
+  // form also checks it before the launch)
   const v4f acc = a.cin == 128 ? hyper_mac<8>(a, oy, ox, g, y, wl) : hyper_mac<4>(a, oy, ox, g, y, wl);
   // acc[r]: position 4g + r of the unit, channel lane % 16
 #pragma unroll
