@@ -772,14 +772,11 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
         // slow bucket: frequency-1 tails in closed form (slot s is symbol s
         // on the left, 64 - (65535 - s) on the right), else a scan from s0
         const uint32_t tl = s_tail[row];
-        if (slot < tl) {
-          sy = slot;
-        } else if (slot >= 65536u - tl) {
-          sy = slot - (65536u - NSYM);
-        } else {
-          sy = (e & 127u) - 1u;
-          while (sy < NSYM - 1 && (s_fc[row * NSYM + sy + 1] >> 16) <= slot) ++sy;
-        }
+        const bool left = slot < tl, right = slot >= 65536u - tl;
+        uint32_t sc = (e & 127u) - 1u;
+        if (!left && !right)
+          while (sc < NSYM - 1 && (s_fc[row * NSYM + sc + 1] >> 16) <= slot) ++sc;
+        sy = left ? slot : (right ? slot - (65536u - NSYM) : sc);
       }
       const uint32_t fc = s_fc[row * NSYM + sy];
       const uint32_t f = fc & 0xFFFFu, c = fc >> 16;
@@ -789,7 +786,10 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
       const uint32_t m = (uint32_t)(bal >> shsel);
       const uint32_t cnt = __popc(m);
       const uint32_t rank = __popc(m & ((1u << lane) - 1u));
-      if (need) xn = (xn << 16) | L.ring[(cursor + rank) & (RING - 1)];
+      // every lane reads (an in-bounds ring word; some lane of the wave
+      // renormalises at nearly every step anyway), so no branch is needed
+      const uint32_t wnext = L.ring[(cursor + rank) & (RING - 1)];
+      xn = need ? ((xn << 16) | wnext) : xn;
       if (valid) x = xn;
       L.out[u * LANES + lane] = (uint8_t)sy;
       cursor += cnt;
