@@ -225,7 +225,9 @@ constexpr int EP = 32;                 // steps per epoch
 constexpr int EPB = EP * LANES;        // symbols per epoch and segment
 
 struct EncSegLds {
-  uint16_t words[EPB];                 // at most one word per symbol
+  // at most one word per symbol, then (index EPB) the store target of lanes
+  // that push no word
+  uint16_t words[EPB + 2];
 };
 constexpr size_t ENC_TAB_BYTES = NSCALES * NSYM * 9;  // fc + magic (u32) + shift (u8)
 constexpr size_t ENC_LDS_BYTES = ((ENC_TAB_BYTES + 15) & ~(size_t)15) + 2 * sizeof(EncSegLds);
@@ -338,17 +340,16 @@ rans_encode_kernel(Tables t, EncStream z, EncStream y, uint8_t* __restrict__ scr
       const uint32_t m = (uint32_t)(bal >> shsel);
       const uint32_t cnt = __popc(m);
       const uint32_t rank = __popc(m & ((1u << lane) - 1u));
-      if (emit) {
-        // word goes to slot position cursor - cnt + rank; staged in reverse
-        L.words[cstart - 1u - (cursor - cnt + rank)] = (uint16_t)(x & 0xFFFFu);
-        x >>= 16;
-      }
+      // word goes to slot position cursor - cnt + rank, staged in reverse;
+      // lanes that push none store into the sink, so no branch is needed
+      const uint32_t wi = emit ? cstart - 1u - (cursor - cnt + rank) : (uint32_t)EPB;
+      L.words[wi] = (uint16_t)(x & 0xFFFFu);
+      x = emit ? x >> 16 : x;
       cursor -= cnt;
-      if (valid) {
-        const uint32_t t1 = __umulhi(mg, x);
-        const uint32_t q = (t1 + ((x - t1) >> (l > 0 ? 1u : 0u))) >> (l > 0 ? l - 1u : 0u);
-        x = (q << 16) + (x - q * f) + c;
-      }
+      const uint32_t t1 = __umulhi(mg, x);
+      const uint32_t q = (t1 + ((x - t1) >> (l > 0 ? 1u : 0u))) >> (l > 0 ? l - 1u : 0u);
+      const uint32_t xu = (q << 16) + (x - q * f) + c;
+      x = valid ? xu : x;
     }
     __syncthreads();
     // flush this epoch's words [cursor, cstart) with coalesced stores
