@@ -470,10 +470,16 @@ compact_kernel(CompDesc d0, const CompDesc* __restrict__ descs, const int2* __re
   uint8_t* dst = out + h0 + before;
   if (threadIdx.x < LANES)
     reinterpret_cast<uint32_t*>(dst)[threadIdx.x] = reinterpret_cast<const uint32_t*>(src)[threadIdx.x];
+  // words in pairs: 4-byte stores (dst is 4-byte aligned: every segment's
+  // byte count is a multiple of 4); an odd count ends with the zero pad word
   const uint16_t* ws = reinterpret_cast<const uint16_t*>(src + SEG_STATE_BYTES) + si.start_word;
-  uint16_t* wd = reinterpret_cast<uint16_t*>(dst + SEG_STATE_BYTES);
-  for (uint32_t i = threadIdx.x; i < si.nwords; i += blockDim.x) wd[i] = ws[i];
-  if ((si.nwords & 1u) && threadIdx.x == 0) wd[si.nwords] = 0;
+  uint32_t* wd = reinterpret_cast<uint32_t*>(dst + SEG_STATE_BYTES);
+  const uint32_t npairs = (si.nwords + 1u) >> 1;
+  for (uint32_t k = threadIdx.x; k < npairs; k += blockDim.x) {
+    const uint32_t lo = ws[2 * k];
+    const uint32_t hi = 2 * k + 1 < si.nwords ? ws[2 * k + 1] : 0u;
+    wd[k] = lo | (hi << 16);
+  }
 }
 
 hipError_t launch_compact(const uint8_t* scratch, size_t slot_bytes_z, size_t slot_bytes_y,
