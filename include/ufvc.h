@@ -81,7 +81,9 @@ size_t ufvc_weight_count(int T, int C);
 /* Creates a context on the current HIP device: validates cfg, repacks the
  * host float32 `weights` (n_weights values, layout above; read only during
  * the call, still owned by the caller) into the kernels' layouts, and builds
- * the Gaussian CDF tables in FP64 on the device.  Blocks until done.
+ * the Gaussian CDF tables in FP64 on the device: the quantised distributions
+ * under which r_hat is coded given sigma alone (Sec. 3.4).  Blocks until
+ * done.
  * Errors: INVAL (cfg or n_weights), UNSUPPORTED (also an entropy-parameter
  * weight that three bf16 parts cannot hold exactly: non-finite, or too close
  * to the bottom of the float32 range), NOMEM, DEVICE. */
@@ -122,13 +124,17 @@ int ufvc_sync_status(ufvc_ctx* ctx, void* stream);
 
 /* ---- Stage-level entry points (same kernels; used for parity testing) ---- */
 
-/* Copies the device-built tables to host memory: freq and cum as 64 x 65
- * uint16 each (row = scale index, column = symbol r + 32), thresholds as 63
- * float32 (scale index = number of thresholds <= sigma).  Synchronous. */
+/* Copies the device-built tables to host memory (the Gaussian models of
+ * r_hat given sigma, Sec. 3.4): freq and cum as 64 x 65 uint16 each (row =
+ * scale index, column = symbol r + 32), thresholds as 63 float32 (scale
+ * index = number of thresholds <= sigma).  Synchronous. */
 int ufvc_get_tables(ufvc_ctx* ctx, uint16_t* freq, uint16_t* cum, float* thresholds);
 
-/* rANS-encodes n symbols (device uint8, values 0..64) with per-symbol table
- * rows idx (device uint8, 0..63) in segments of 2^seg_log2 symbols.  Output
+/* The arithmetic coder of the single-step entropy model on its own (Sec. 3.4:
+ * every symbol's table depends on sigma alone, so all of them are coded in
+ * one pass): rANS-encodes n symbols (device uint8, values 0..64) with
+ * per-symbol table rows idx (device uint8, 0..63) in segments of
+ * 2^seg_log2 symbols.  Output
  * (device, `capacity` bytes): uint32 seg_bytes[n_seg] then the segments, in
  * the container's segment format.  *out_len = bytes written (or needed, with
  * NOSPC).  Synchronises `stream`. */
@@ -136,8 +142,10 @@ int ufvc_rans_encode(ufvc_ctx* ctx, const uint8_t* sym, const uint8_t* idx, size
                      int seg_log2, uint8_t* out, size_t capacity, size_t* out_len,
                      void* stream);
 
-/* Inverse of ufvc_rans_encode: `in` (device, len bytes) -> sym (device, n
- * bytes).  Asynchronous; integrity failures set CORRUPT in the status. */
+/* Inverse of ufvc_rans_encode, all segments in one launch (the decoder's
+ * single bit-stream interaction, Sec. 3.4): `in` (device, len bytes) -> sym
+ * (device, n bytes), with the same per-symbol rows idx (device, n bytes).
+ * Asynchronous; integrity failures set CORRUPT in the status. */
 int ufvc_rans_decode(ufvc_ctx* ctx, const uint8_t* in, size_t len, const uint8_t* idx,
                      size_t n, int seg_log2, uint8_t* sym, void* stream);
 

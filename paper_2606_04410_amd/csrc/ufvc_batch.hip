@@ -393,6 +393,7 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
     cd.slot_z = q.slot_z;
     cd.slot_y = q.slot_y;
     cd.info = info;
+    cd.seg_off = at<uint32_t>(A, q.seg_off);
     cd.n_seg_z = q.g.nseg_z;
     cd.n_seg_y = q.g.nseg_y;
     cd.with_header = 1;
@@ -687,7 +688,7 @@ int ufvc_encode_batch(ufvc_batch* b, ufvc_chunk* chunks, int n, void* stream) {
   CK(launch_params_epilogue_batch(at<EpiDesc>(D, P->off_epi_e), at<int2>(D, P->off_epi_work),
                                   P->n_epi_work, m0->tab.thresholds, s));
   CK(launch_rans_encode_batch(m0->tab, at<EncSeg>(D, P->off_encseg), P->n_encseg, s));
-  CK(launch_compact_batch(at<CompDesc>(D, P->off_comp), at<int2>(D, P->off_compmap), P->n_compblk, s));
+  CK(launch_compact_batch(at<CompDesc>(D, P->off_comp), n, at<int2>(D, P->off_compmap), P->n_compblk, s));
   CK(hipMemcpyAsync(b->results_host, D + P->off_result, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
   int worst = UFVC_OK;

@@ -485,7 +485,7 @@ int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uin
   HeaderFields hf{(uint16_t)T, (uint16_t)C, (uint16_t)H, (uint16_t)W, (uint8_t)c->cfg.seg_log2,
                   (uint8_t)c->cfg.seg_log2_z, (uint8_t)K_Z, c->cfg.model_tag};
   CK(stage(c, S_COMPACT, s, [&] { return launch_compact(c->rw.scratch, sbz, sby, c->rw.info, g.nseg_z, g.nseg_y, 1, hf, bs, capacity,
-                    c->result, s); }));
+                    c->result, c->rw.seg_off, s); }));
   CK(hipMemcpyAsync(c->result_host, c->result, 8, hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
   c->last_stream = s;
@@ -571,7 +571,7 @@ int ufvc_rans_encode(ufvc_ctx* c, const uint8_t* sym, const uint8_t* idx, size_t
   CK(launch_rans_encode(c->tab, ez, ey, c->rw.scratch, 0, slot_bytes(sl), c->rw.info, s));
   HeaderFields hf{};
   CK(launch_compact(c->rw.scratch, 0, slot_bytes(sl), c->rw.info, 0, nseg, 0, hf, out, capacity,
-                    c->result, s));
+                    c->result, c->rw.seg_off, s));
   CK(hipMemcpyAsync(c->result_host, c->result, 8, hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
   *out_len = (size_t)c->result_host[0];

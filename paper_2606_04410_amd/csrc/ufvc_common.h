@@ -4,6 +4,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <atomic>
+
 namespace ufvc {
 
 // Device-memory accesses through global (address space 1) pointers: the
@@ -45,6 +47,12 @@ __device__ __forceinline__ void lds_fill4(void* dst, const void* src, int n) {
                                        (__attribute__((address_space(3))) void*)((uint32_t*)dst + o), 4, 0,
                                        0);
 }
+
+// Raises a kernel's dynamic-LDS limit to `bytes` once per device.  `done`
+// is the caller's per-kernel flag word (bit d: device d done); the fast path
+// is one atomic load, the first call on a device sets the attribute under a
+// lock, so concurrent host threads (the server's lanes) never race on it.
+hipError_t set_lds_limit_once(std::atomic<uint32_t>& done, const void* kern, int bytes);
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -160,10 +168,11 @@ struct HeaderFields {
   uint8_t seg_log2, seg_log2_z, k_z;
   uint32_t model_tag;
 };
+// seg_off: n_seg_z + n_seg_y words of scratch for the segments' offsets.
 hipError_t launch_compact(const uint8_t* scratch, size_t slot_bytes_z, size_t slot_bytes_y,
                           const SegInfo* info, int n_seg_z, int n_seg_y, int with_header,
                           HeaderFields hf, uint8_t* out, size_t capacity,
-                          unsigned long long* result, hipStream_t s);
+                          unsigned long long* result, uint32_t* seg_off, hipStream_t s);
 
 // Validates the stream (header if with_header) and computes segment byte
 // offsets into seg_off[n_seg_z + n_seg_y] (0xFFFFFFFF marks unusable).
@@ -241,6 +250,7 @@ struct CompDesc {
   uint8_t* out;
   unsigned long long capacity;
   unsigned long long* result;
+  uint32_t* seg_off;         // scratch: byte offset of each segment in the container
 };
 
 // Stream validation of one chunk.
@@ -258,7 +268,8 @@ hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 hipError_t launch_params_epilogue_batch(const EpiDesc* d, const int2* work, int nwork,
                                         const float* thr, hipStream_t s);
 hipError_t launch_rans_encode_batch(const Tables& t, const EncSeg* segs, int nsegs, hipStream_t s);
-hipError_t launch_compact_batch(const CompDesc* d, const int2* map, int nblocks, hipStream_t s);
+hipError_t launch_compact_batch(const CompDesc* d, int nchunks, const int2* map, int nblocks,
+                                hipStream_t s);
 hipError_t launch_parse_batch(const ParseDesc* d, int nchunks, hipStream_t s);
 hipError_t launch_rans_decode_batch(const Tables& t, const DecSeg* segs, int nsegs, bool fixed,
                                     hipStream_t s);

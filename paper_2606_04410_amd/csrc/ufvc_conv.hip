@@ -30,6 +30,7 @@
 // store, rounding of z, and the x8 pixel-shuffle store of the frame
 // decoders with crop and clamp (Sec. 3.2).
 #include <algorithm>
+#include <mutex>
 
 #include "ufvc_common.h"
 
@@ -982,6 +983,20 @@ bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int
   return cfg >= 0 && !(prec == P_FP8 && (cfg == 5 || cfg == 6 || cfg == 8));
 }
 
+hipError_t set_lds_limit_once(std::atomic<uint32_t>& done, const void* kern, int bytes) {
+  int dev = 0;
+  if (const hipError_t e = hipGetDevice(&dev)) return e;
+  if (dev < 0 || dev >= 32) return hipErrorInvalidDevice;
+  const uint32_t bit = 1u << dev;
+  if (done.load(std::memory_order_acquire) & bit) return hipSuccess;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.load(std::memory_order_relaxed) & bit) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) done.fetch_or(bit, std::memory_order_release);
+  return e;
+}
+
 __global__ void zero_u32_kernel(uint32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -1002,13 +1017,9 @@ static hipError_t run_conv(const ConvArgs& a, int groups, const ConvArgs* descs,
   constexpr int BN = WN * FN * 32;
   constexpr int lds = Pipe<PREC, LD, STRIDE, TH, TW, WM, WN, FN>::LDS;
   auto kern = conv3x3_kernel<PREC, LD, ST, STRIDE, TH, TW, WM, WN, FM, FN>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  static std::atomic<uint32_t> attr_done{0};
+  if (const hipError_t e = set_lds_limit_once(attr_done, reinterpret_cast<const void*>(kern), lds))
+    return e;
   dim3 grid;
   if (descs) {
     if (nwork <= 0) return hipSuccess;
@@ -1027,13 +1038,9 @@ static hipError_t run_ring(const ConvArgs& a, int groups, const ConvArgs* descs,
                            int nwork, hipStream_t s) {
   using R = Ring<ST, TH, TW, WM, WN, FM, FN, NH>;
   auto kern = conv3x3_ring_kernel<ST, TH, TW, WM, WN, FM, FN, NH>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, R::LDS);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  static std::atomic<uint32_t> attr_done{0};
+  if (const hipError_t e = set_lds_limit_once(attr_done, reinterpret_cast<const void*>(kern), R::LDS))
+    return e;
   dim3 grid;
   if (descs) {
     if (nwork <= 0) return hipSuccess;

@@ -371,18 +371,17 @@ rans_encode_kernel(Tables t, EncStream z, EncStream y, uint8_t* __restrict__ scr
   }
 }
 
+static hipError_t set_enc_lds() {
+  static std::atomic<uint32_t> done{0};
+  return set_lds_limit_once(done, reinterpret_cast<const void*>(rans_encode_kernel), (int)ENC_LDS_BYTES);
+}
+
 hipError_t launch_rans_encode(const Tables& t, EncStream z, EncStream y, uint8_t* scratch,
                               size_t slot_bytes_z, size_t slot_bytes_y, SegInfo* info,
                               hipStream_t s) {
   const int nseg = z.n_seg + y.n_seg;
   if (nseg == 0) return hipSuccess;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rans_encode_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)ENC_LDS_BYTES);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  if (const hipError_t e = set_enc_lds()) return e;
   hipLaunchKernelGGL(rans_encode_kernel, dim3((nseg + 1) / 2), dim3(64), ENC_LDS_BYTES, s, t, z, y,
                      scratch, slot_bytes_z, slot_bytes_y, info, nullptr, 0);
   return hipGetLastError();
@@ -391,13 +390,7 @@ hipError_t launch_rans_encode(const Tables& t, EncStream z, EncStream y, uint8_t
 hipError_t launch_rans_encode_batch(const Tables& t, const EncSeg* segs, int nsegs, hipStream_t s) {
   if (nsegs <= 0) return hipSuccess;
   EncStream none{nullptr, nullptr, 0, 0, 5, 0};
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rans_encode_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)ENC_LDS_BYTES);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  if (const hipError_t e = set_enc_lds()) return e;
   hipLaunchKernelGGL(rans_encode_kernel, dim3((nsegs + 1) / 2), dim3(64), ENC_LDS_BYTES, s, t, none,
                      none, nullptr, 0, 0, nullptr, segs, nsegs);
   return hipGetLastError();
@@ -408,21 +401,76 @@ __device__ __forceinline__ uint32_t seg_bytes_of(const SegInfo& si) {
   return (SEG_STATE_BYTES + 2u * si.nwords + 3u) & ~3u;
 }
 
-__device__ unsigned long long block_sum(unsigned long long v, unsigned long long* red) {
+// Exclusive scan of per-thread run sums over a block (at most 1024 threads):
+// returns the sum of the runs of all lower threads; *total gets the block's
+// sum.  s_wave holds one entry per wave.
+__device__ unsigned long long block_exclusive_scan(unsigned long long run, unsigned long long* s_wave,
+                                                   unsigned long long* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  if (lane == 0) red[wave] = v;
+  unsigned long long inc = run;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long v = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += v;
+  }
+  if (lane == 63) s_wave[wave] = inc;
   __syncthreads();
-  unsigned long long tot = 0;
-  const int nw = (blockDim.x + 63) >> 6;
-  for (int i = 0; i < nw; ++i) tot += red[i];
+  unsigned long long before = 0, tot = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    if (w < wave) before += s_wave[w];
+    tot += s_wave[w];
+  }
   __syncthreads();
-  return tot;
+  *total = tot;
+  return before + inc - run;
 }
 
+// Container assembly, step 1, one block per chunk: every segment's byte
+// count from its word count, their exclusive prefix sum (thread t owns the
+// contiguous run of segments [t K, t K + K), K = ceil(n_seg / blockDim); one
+// block scan of the run sums), the segments' byte offsets in the container,
+// the total size, and the header and segment table.  When the container does
+// not fit the capacity nothing is written to the output.
+__global__ void __launch_bounds__(256)
+compact_scan_kernel(CompDesc d0, const CompDesc* __restrict__ descs) {
+  __shared__ unsigned long long s_wave[4];
+  const CompDesc d = descs ? descs[blockIdx.x] : d0;
+  const SegInfo* __restrict__ info = d.info;
+  const int nseg = d.n_seg_z + d.n_seg_y;
+  const size_t h0 = (d.with_header ? 28u : 0u) + 4u * (size_t)nseg;
+  const int K = (nseg + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int r0 = min((int)threadIdx.x * K, nseg), r1 = min(r0 + K, nseg);
+  unsigned long long run = 0;
+  for (int i = r0; i < r1; ++i) run += seg_bytes_of(info[i]);
+  unsigned long long all = 0;
+  unsigned long long off = h0 + block_exclusive_scan(run, s_wave, &all);
+  const unsigned long long total = h0 + all;
+  if (threadIdx.x == 0) d.result[0] = total;
+  if (total > d.capacity) return;
+  uint8_t* __restrict__ out = d.out;
+  uint32_t* tab = reinterpret_cast<uint32_t*>(out + (d.with_header ? 28 : 0));
+  for (int i = r0; i < r1; ++i) {
+    const uint32_t sb = seg_bytes_of(info[i]);
+    d.seg_off[i] = (uint32_t)off;
+    tab[i] = sb;
+    off += sb;
+  }
+  if (d.with_header && threadIdx.x == 0) {
+    const HeaderFields hf = d.hf;
+    uint32_t* h = reinterpret_cast<uint32_t*>(out);
+    h[0] = 0x31564655u;  // "UFV1"
+    h[1] = (uint32_t)hf.T | ((uint32_t)hf.C << 16);
+    h[2] = (uint32_t)hf.H | ((uint32_t)hf.W << 16);
+    h[3] = (uint32_t)hf.seg_log2 | ((uint32_t)hf.seg_log2_z << 8) | ((uint32_t)hf.k_z << 16);
+    h[4] = hf.model_tag;
+    h[5] = (uint32_t)d.n_seg_z;
+    h[6] = (uint32_t)d.n_seg_y;
+  }
+}
+
+// Container assembly, step 2, one block per segment: the 32 final states,
+// then the words, at the offset step 1 computed.
 __global__ void __launch_bounds__(256)
 compact_kernel(CompDesc d0, const CompDesc* __restrict__ descs, const int2* __restrict__ map) {
-  __shared__ unsigned long long red[8];
   int b = blockIdx.x;
   CompDesc d;
   if (descs) {
@@ -432,42 +480,12 @@ compact_kernel(CompDesc d0, const CompDesc* __restrict__ descs, const int2* __re
   } else {
     d = d0;
   }
-  const SegInfo* __restrict__ info = d.info;
   const int n_seg_z = d.n_seg_z;
-  const int nseg = d.n_seg_z + d.n_seg_y;
-  const size_t h0 = (d.with_header ? 28u : 0u) + 4u * (size_t)nseg;
-  unsigned long long before = 0, all = 0;
-  for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
-    const unsigned long long sb = seg_bytes_of(info[i]);
-    all += sb;
-    if (i < b) before += sb;
-  }
-  before = block_sum(before, red);
-  all = block_sum(all, red);
-  const unsigned long long total = h0 + all;
-  if (b == 0 && threadIdx.x == 0) d.result[0] = total;
-  if (total > d.capacity) return;
-  uint8_t* __restrict__ out = d.out;
-  if (b == 0) {
-    if (d.with_header && threadIdx.x == 0) {
-      const HeaderFields hf = d.hf;
-      uint32_t* h = reinterpret_cast<uint32_t*>(out);
-      h[0] = 0x31564655u;  // "UFV1"
-      h[1] = (uint32_t)hf.T | ((uint32_t)hf.C << 16);
-      h[2] = (uint32_t)hf.H | ((uint32_t)hf.W << 16);
-      h[3] = (uint32_t)hf.seg_log2 | ((uint32_t)hf.seg_log2_z << 8) | ((uint32_t)hf.k_z << 16);
-      h[4] = hf.model_tag;
-      h[5] = (uint32_t)n_seg_z;
-      h[6] = (uint32_t)d.n_seg_y;
-    }
-    uint32_t* tab = reinterpret_cast<uint32_t*>(out + (d.with_header ? 28 : 0));
-    for (int i = threadIdx.x; i < nseg; i += blockDim.x) tab[i] = seg_bytes_of(info[i]);
-  }
-  if (b >= nseg) return;
-  const SegInfo si = info[b];
+  if (b >= n_seg_z + d.n_seg_y || ldg(d.result) > d.capacity) return;
+  const SegInfo si = d.info[b];
   const uint8_t* src = b < n_seg_z ? d.scratch_z + (size_t)b * d.slot_z
                                    : d.scratch_y + (size_t)(b - n_seg_z) * d.slot_y;
-  uint8_t* dst = out + h0 + before;
+  uint8_t* dst = d.out + ldg(d.seg_off + b);
   if (threadIdx.x < LANES)
     reinterpret_cast<uint32_t*>(dst)[threadIdx.x] = reinterpret_cast<const uint32_t*>(src)[threadIdx.x];
   // words in pairs: 4-byte stores (dst is 4-byte aligned: every segment's
@@ -485,7 +503,7 @@ compact_kernel(CompDesc d0, const CompDesc* __restrict__ descs, const int2* __re
 hipError_t launch_compact(const uint8_t* scratch, size_t slot_bytes_z, size_t slot_bytes_y,
                           const SegInfo* info, int n_seg_z, int n_seg_y, int with_header,
                           HeaderFields hf, uint8_t* out, size_t capacity,
-                          unsigned long long* result, hipStream_t s) {
+                          unsigned long long* result, uint32_t* seg_off, hipStream_t s) {
   const int nseg = n_seg_z + n_seg_y;
   CompDesc d{};
   d.scratch_z = scratch;
@@ -500,15 +518,20 @@ hipError_t launch_compact(const uint8_t* scratch, size_t slot_bytes_z, size_t sl
   d.out = out;
   d.capacity = capacity;
   d.result = result;
-  hipLaunchKernelGGL(compact_kernel, dim3(nseg > 0 ? nseg : 1), dim3(256), 0, s, d,
-                     (const CompDesc*)nullptr, (const int2*)nullptr);
+  d.seg_off = seg_off;
+  hipLaunchKernelGGL(compact_scan_kernel, dim3(1), dim3(256), 0, s, d, (const CompDesc*)nullptr);
+  if (nseg > 0)
+    hipLaunchKernelGGL(compact_kernel, dim3(nseg), dim3(256), 0, s, d, (const CompDesc*)nullptr,
+                       (const int2*)nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_compact_batch(const CompDesc* d, const int2* map, int nblocks, hipStream_t s) {
-  if (nblocks <= 0) return hipSuccess;
+hipError_t launch_compact_batch(const CompDesc* d, int nchunks, const int2* map, int nblocks,
+                                hipStream_t s) {
+  if (nchunks <= 0) return hipSuccess;
   CompDesc none{};
-  hipLaunchKernelGGL(compact_kernel, dim3(nblocks), dim3(256), 0, s, none, d, map);
+  hipLaunchKernelGGL(compact_scan_kernel, dim3(nchunks), dim3(256), 0, s, none, d);
+  if (nblocks > 0) hipLaunchKernelGGL(compact_kernel, dim3(nblocks), dim3(256), 0, s, none, d, map);
   return hipGetLastError();
 }
 
@@ -561,23 +584,11 @@ parse_kernel(ParseDesc d0, const ParseDesc* __restrict__ descs) {
       if (sb < (uint32_t)SEG_STATE_BYTES || (sb & 3u)) badsz = 1;
       run += sb;
     }
-  // inclusive scan of the run sums: within the wave, then across the waves
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  unsigned long long inc = run;
-  for (int o = 1; o < 64; o <<= 1) {
-    const unsigned long long v = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += v;
-  }
-  if (lane == 63) s_wave[wave] = inc;
-  const int anybad = __syncthreads_or(badsz);   // also publishes s_wave and s_hdr_bad
-  unsigned long long before = 0, total = 0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-    if (w < wave) before += s_wave[w];
-    total += s_wave[w];
-  }
+  const int anybad = __syncthreads_or(badsz);   // also publishes s_hdr_bad
+  unsigned long long total = 0;
+  unsigned long long off = h0 + block_exclusive_scan(run, s_wave, &total);   // this run's first offset
   const bool hdr_bad = s_hdr_bad != 0;
   const bool ok = !hdr_bad && !anybad && h0 + total == len;
-  unsigned long long off = h0 + before + inc - run;   // this run's first offset
   for (int i = r0; i < r1; ++i) {
     const uint32_t sb = ok ? tab[i] : 0u;
     seg_off[i] = ok ? (uint32_t)off : 0xFFFFFFFFu;
@@ -835,14 +846,9 @@ rans_decode_kernel(Tables t, const uint8_t* __restrict__ bs0, const uint32_t* __
 
 template <bool FIXED>
 static hipError_t set_dec_lds() {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rans_decode_kernel<FIXED>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)DEC_LDS_BYTES);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  return hipSuccess;
+  static std::atomic<uint32_t> done{0};
+  return set_lds_limit_once(done, reinterpret_cast<const void*>(rans_decode_kernel<FIXED>),
+                            (int)DEC_LDS_BYTES);
 }
 
 hipError_t launch_rans_decode(const Tables& t, const uint8_t* bs, const uint32_t* seg_off,

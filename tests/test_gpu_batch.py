@@ -69,3 +69,55 @@ def test_batch_equals_single_and_graph_equals_eager(prec):
     batch.close()
     for m in models:
         m.close()
+
+
+C3_BUCKETS = [(480, 832), (720, 1280), (1088, 1920), (2160, 3840)]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16_fp8"])
+def test_batch_c3_buckets_at_c128(prec):
+    """One chunk per bucket of the 48-chunk batch mix (832x480, 1280x720,
+    1920x1088, 3840x2160), each at T = 4 and T = 8, C = 128, default segment
+    sizes and autotuned tiles (the batch benchmark's configuration): batch
+    results equal single-chunk results bit for bit, and graph replays equal
+    eager decode."""
+    import paper_2606_04410_amd as u
+    C = 128
+    models = [u.Codec(T, C, stand_in_weights(T, C), precision=prec, model_tag=0x0C30_0000 + T,
+                      autotune=True) for T in (4, 8)]
+    shapes = [(m, H, W) for H, W in C3_BUCKETS for m in (0, 1)]
+    say(f"batch C3 buckets {prec}: {shapes}")
+    frames = [torch.from_numpy(video_chunk(models[m].T, H, W, 16, seed=3, chunk_id=i)).cuda()
+              for i, (m, H, W) in enumerate(shapes)]
+    ref_bs, ref_fr = [], []
+    for (m, H, W), fr in zip(shapes, frames):
+        bs, n = models[m].encode(fr)
+        ref_bs.append(bs[:n].clone())
+        ref_fr.append(models[m].decode(bs, n, H, W).clone())
+    torch.cuda.synchronize()
+    batch = u.Batch(models)
+    outs = [torch.zeros(models[m].max_bitstream_bytes(H, W), dtype=torch.uint8, device="cuda")
+            for (m, H, W) in shapes]
+    lens = batch.encode([(m, fr, o) for (m, _, _), fr, o in zip(shapes, frames, outs)])
+    for i in range(len(shapes)):
+        assert lens[i] == ref_bs[i].numel() and torch.equal(outs[i][:lens[i]], ref_bs[i]), i
+    rec = [torch.full((models[m].T, 3, H, W), -1.0, device="cuda") for (m, H, W) in shapes]
+    items = [(m, o, n, H, W, r) for (m, H, W), o, n, r in zip(shapes, outs, lens, rec)]
+    st, code = batch.decode(items, graph=False)
+    assert code == 0 and all(x == 0 for x in st)
+    for i in range(len(shapes)):
+        assert torch.equal(rec[i], ref_fr[i]), i
+    for rep in range(3):
+        for r in rec:
+            r.fill_(-1.0)
+        st, code = batch.decode(items, graph=True)
+        assert code == 0 and all(x == 0 for x in st), (rep, st)
+        for i in range(len(shapes)):
+            assert torch.equal(rec[i], ref_fr[i]), (rep, i)
+        models[1].encode(frames[1])
+        torch.cuda.synchronize()
+    say(f"  {len(shapes)} chunks: batch == single, graph x3 == eager; "
+        f"k1 tiles {[models[m].tuning(H, W)['k1'] for m, H, W in shapes]}")
+    batch.close()
+    for m in models:
+        m.close()

@@ -2,9 +2,11 @@
 
 Bars
   * rANS, tables, container: bit-exact.
-  * Scale index and symbols: identical except at provable near-ties (the
-    oracle works in float64, the kernels in float32): a scale within 1e-4
-    (relative) of a threshold, a value within 1e-3 of a half-integer.
+  * Scale index and symbols: identical except at near-ties (the oracle
+    works in float64, the kernels in float32): a scale within 1e-5
+    (relative) of a threshold, a value within 1e-4 of a half-integer.
+  * The oracle's rANS decoder, given the GPU's indices, recovers the GPU's
+    symbols from the GPU's stream.
   * Encoder and decoder indices on the GPU: identical, always.
   * Float32 reconstruction on an identical y_hat: max abs <= 1e-3 on [0, 1].
   * BF16 vs float32 reconstruction: |PSNR delta| <= 0.05 dB.
@@ -51,12 +53,12 @@ def to_hwc(a):
     return np.ascontiguousarray(np.transpose(a, (1, 2, 0)))
 
 
-def near_half(v, tol=1e-3):
+def near_half(v, tol=1e-4):
     f = np.abs(v - np.floor(v) - 0.5)
     return f < tol
 
 
-def near_threshold(sigma, tol=1e-4):
+def near_threshold(sigma, tol=1e-5):
     rel = np.abs(sigma[..., None] - THR) / THR
     return (rel < tol).any(axis=-1)
 
@@ -219,9 +221,20 @@ def test_c1_chunk_end_to_end(prec):
     d_sym = c.buffer(pkg().BUF_SYM, H, W)
     np.testing.assert_array_equal(d_idx, g_idx)
     np.testing.assert_array_equal(d_sym, g_sym)
-    # the oracle decodes the GPU stream to the same symbols
+    # the oracle's coder decodes the GPU stream to the GPU's symbols, given
+    # the GPU's indices
+    hdr = container.parse(g_bs)
+    zsd = rans.decode(hdr["z_segs"], np.full(zs.size, entropy.K_Z), FREQ, CUM, 1 << 10)
+    np.testing.assert_array_equal(zsd, zs)
+    ysd = rans.decode(hdr["y_segs"], g_idx.reshape(-1), FREQ, CUM, 1 << 14)
+    np.testing.assert_array_equal(ysd, g_sym.reshape(-1))
+    # and the oracle's own decoder derives the same indices (differences only
+    # at near-threshold scales, as in the encoder check), so its symbols
+    # agree wherever its indices do
     _, od = ocodec.decode_latent(g_bs, w)
-    if np.array_equal(od["y_idx"], g_idx.reshape(-1)):
+    same = od["y_idx"] == g_idx.reshape(-1)
+    assert not (~same & ~near_threshold(od["sigma"].transpose(1, 2, 0).reshape(-1))).any()
+    if same.all():
         np.testing.assert_array_equal(od["y_sym"], g_sym.reshape(-1))
     x_hat = out.cpu().numpy()
     assert x_hat.shape == fr.shape and np.isfinite(x_hat).all()

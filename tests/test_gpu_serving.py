@@ -135,3 +135,51 @@ def test_server_admission_by_hbm_footprint():
     srv.close()
     for mm in ms:
         mm.close()
+
+
+def test_server_c128_two_resolutions():
+    """C = 128, T = 8, default segment sizes (the serving benchmark's
+    configuration), two resolutions of the mix: every result is bitwise the
+    single-chunk call's, alone and in the mix."""
+    u = pkg()
+    T, C = 8, 128
+    codec = u.Codec(T, C, stand_in_weights(T, C), precision="bf16", model_tag=0x0C50_0000,
+                    autotune=True)
+    sizes = [(480, 832), (1088, 1920), (480, 832), (1088, 1920)]
+    frames = [torch.from_numpy(video_chunk(T, H, W, 16, seed=13, chunk_id=i)).cuda()
+              for i, (H, W) in enumerate(sizes)]
+    ref_bs, ref_fr = [], []
+    for (H, W), fr in zip(sizes, frames):
+        bs, n = codec.encode(fr)
+        ref_bs.append(bs[:n].clone())
+        ref_fr.append(codec.decode(bs, n, H, W).clone())
+    torch.cuda.synchronize()
+    say(f"server C=128: {len(sizes)} encodes + {len(sizes)} decodes, {sizes}")
+    srv = u.Server([codec], lanes=2, max_batch=4, graph=True)
+    enc_out = [torch.zeros(codec.max_bitstream_bytes(H, W), dtype=torch.uint8, device="cuda")
+               for (H, W) in sizes]
+    dec_out = [torch.full((T, 3, H, W), -1.0, device="cuda") for (H, W) in sizes]
+    tickets = {}
+    for rnd in range(2):      # the second round reuses the cached plans
+        for i, (H, W) in enumerate(sizes):
+            tickets[srv.submit_encode(0, frames[i], enc_out[i], tag=i)] = ("enc", i)
+            tickets[srv.submit_decode(0, ref_bs[i], ref_bs[i].numel(), H, W, dec_out[i],
+                                      tag=100 + i)] = ("dec", i)
+        got = collect(srv, len(tickets), timeout_s=120.0)
+        for t, (kind, i) in tickets.items():
+            c = got[t]
+            assert c["status"] == 0
+            if kind == "enc":
+                assert c["len"] == ref_bs[i].numel() and torch.equal(enc_out[i][:c["len"]], ref_bs[i])
+            else:
+                assert torch.equal(dec_out[i], ref_fr[i])
+        say(f"  round {rnd}: batch sizes {sorted(got[t]['batch_size'] for t in tickets)}")
+        for o in dec_out:
+            o.fill_(-1.0)
+        for o in enc_out:
+            o.zero_()
+        tickets = {}
+    st = srv.stats()
+    assert st["peak_footprint"] <= st["budget"]
+    srv.close()
+    codec.close()

@@ -74,3 +74,20 @@ def test_scale_index_of_decoder_matches_encoder_exactly(c1):
     _, w, bs, enc = c1
     _, dec = codec.decode_latent(bs, w)
     assert np.array_equal(dec["idx"], entropy.scale_index(enc["sigma"]))
+
+
+def test_psnr_closed_forms():
+    """PSNR = 10 log10(1 / MSE) with peak 1: a uniform error d gives
+    -20 log10 d; the same error on half the values adds 10 log10 2; identical
+    inputs give infinity; the result does not depend on the array's shape."""
+    a = np.zeros((2, 3, 8, 8))
+    for d in (0.5, 0.1, 1e-3):
+        assert abs(codec.psnr(a, a + d) - (-20.0 * np.log10(d))) < 1e-9
+        b = a.copy()
+        b[0] += d                      # half of the values
+        assert abs(codec.psnr(a, b) - (-20.0 * np.log10(d) + 10.0 * np.log10(2.0))) < 1e-9
+    assert abs(codec.psnr(a.reshape(6, 64), (a + 0.1).reshape(6, 64)) - 20.0) < 1e-9
+    assert codec.psnr(a + 0.3, a + 0.3) == float("inf")
+    # symmetric in its arguments, and float32 inputs are promoted
+    r = np.random.default_rng(0).random((3, 5)).astype(np.float32)
+    assert codec.psnr(r, r * 0.5) == codec.psnr(r * 0.5, r)
