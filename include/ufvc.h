@@ -45,7 +45,8 @@ typedef enum {
   UFVC_E_CORRUPT = -3,     /* bit-stream failed its integrity checks */
   UFVC_E_DEVICE = -4,      /* a HIP runtime call failed */
   UFVC_E_NOMEM = -5,       /* device allocation failed */
-  UFVC_E_UNSUPPORTED = -6  /* configuration outside what the kernels support */
+  UFVC_E_UNSUPPORTED = -6, /* configuration outside what the kernels support */
+  UFVC_E_SCRATCH = -7      /* input larger than an allocation-free call's fixed scratch */
 } ufvc_status;
 
 /* In every mode the hyper conv runs in float32 and the entropy-parameter
@@ -141,6 +142,27 @@ int ufvc_get_tables(ufvc_ctx* ctx, uint16_t* freq, uint16_t* cum, float* thresho
 int ufvc_rans_encode(ufvc_ctx* ctx, const uint8_t* sym, const uint8_t* idx, size_t n,
                      int seg_log2, uint8_t* out, size_t capacity, size_t* out_len,
                      void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ufvc_rans_encode with the same arguments, kernels, output and errors, but
+ * it calls no hipMalloc, hipFree or other allocating routine.  Its scratch
+ * (padded copies of sym and idx, the per-segment slots, word ranges and
+ * offsets) lives in one fixed 64 MiB device array per GPU, reserved when the
+ * library's code is loaded there and held until the process ends; its device
+ * address is looked up by the first ufvc_create on that GPU.  The scratch
+ * needed is, each term rounded up to 256 bytes,
+ *     2 (n + 2048) + n_seg (128 + 2^(seg_log2 + 1)) + 8 n_seg + 4 n_seg,
+ * n_seg = ceil(n / 2^seg_log2); a larger input returns UFVC_E_SCRATCH without
+ * enqueuing work (at seg_log2 = 13 that is about 4 bytes per symbol, so up to
+ * 16.7 M symbols: a 4K latent of C = 128 has 16.6 M, a 1080p one 4.2 M).  Nothing in the scratch has to start at zero: every
+ * byte a call reads was written earlier in the same call.  All calls on one
+ * GPU share the array, so calls that overlap in time on one GPU (two host
+ * threads, or two streams) race and must be serialised by the caller.
+ * Synchronises `stream`. */
+int ufvc_rans_encode_noalloc(ufvc_ctx* ctx, const uint8_t* sym, const uint8_t* idx, size_t n,
+                             int seg_log2, uint8_t* out, size_t capacity, size_t* out_len,
+                             void* stream);
 
 /* Inverse of ufvc_rans_encode, all segments in one launch (the decoder's
  * single bit-stream interaction, Sec. 3.4): `in` (device, len bytes) -> sym

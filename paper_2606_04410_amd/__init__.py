@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libufvc.so")
 FP32, BF16, BF16_FP8 = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "bf16_fp8": BF16_FP8}
 STATUS = {0: "OK", -1: "INVAL", -2: "NOSPC", -3: "CORRUPT", -4: "DEVICE", -5: "NOMEM",
-          -6: "UNSUPPORTED"}
+          -6: "UNSUPPORTED", -7: "SCRATCH"}
 BUF_Y, BUF_ZSYM, BUF_PARAMS, BUF_IDX, BUF_SYM, BUF_D2, BUF_F, BUF_K1, BUF_K2, BUF_AMAX = range(10)
 Z_CHANNELS = 32
 # Segment sizes (log2 symbols per rANS segment) used unless a codec names its
@@ -83,6 +83,7 @@ def _load():
         "ufvc_sync_status": (I, [P, P]),
         "ufvc_get_tables": (I, [P, P, P, P]),
         "ufvc_rans_encode": (I, [P, P, P, S, I, P, S, ctypes.POINTER(S), P]),
+        "ufvc_rans_encode_noalloc": (I, [P, P, P, S, I, P, S, ctypes.POINTER(S), P]),
         "ufvc_rans_decode": (I, [P, P, S, P, S, I, P, P]),
         "ufvc_synthesize": (I, [P, P, I, I, I, P, P]),
         "ufvc_copy_buffer": (I, [P, I, P, S]),
@@ -118,7 +119,7 @@ lib = _load()
 # Names of the exported entry points (what include/ufvc.h declares).
 EXPORTS = ("ufvc_weight_count", "ufvc_create", "ufvc_destroy", "ufvc_max_bitstream_bytes",
            "ufvc_encode_chunk", "ufvc_decode_chunk", "ufvc_sync_status", "ufvc_get_tables",
-           "ufvc_rans_encode", "ufvc_rans_decode", "ufvc_synthesize", "ufvc_copy_buffer",
+           "ufvc_rans_encode", "ufvc_rans_encode_noalloc", "ufvc_rans_decode", "ufvc_synthesize", "ufvc_copy_buffer",
            "ufvc_profile_enable", "ufvc_profile_stage_count", "ufvc_profile_stage_name",
            "ufvc_profile_read", "ufvc_get_tuning", "ufvc_tile_config", "ufvc_num_tile_configs",
            "ufvc_force_tile_config", "ufvc_batch_create",
@@ -254,6 +255,21 @@ class Codec:
         ln = ctypes.c_size_t(0)
         _check(lib.ufvc_rans_encode(self._h, _ptr(sym), _ptr(idx), n, seg_log2, _ptr(out), cap,
                                     ctypes.byref(ln), _stream(stream)), "ufvc_rans_encode")
+        return out[:ln.value]
+
+    def rans_encode_noalloc(self, sym, idx, seg_log2: int, out=None, stream=None):
+        """As rans_encode through the allocation-free entry point (its scratch
+        is the library's fixed per-GPU array).  Returns a view of `out`."""
+        import torch
+        n = sym.numel()
+        nseg = -(-n // (1 << seg_log2))
+        cap = 4 * nseg + nseg * 132 + 2 * n + 16
+        if out is None:
+            out = torch.empty(cap, dtype=torch.uint8, device=sym.device)
+        ln = ctypes.c_size_t(0)
+        _check(lib.ufvc_rans_encode_noalloc(self._h, _ptr(sym), _ptr(idx), n, seg_log2, _ptr(out),
+                                            out.numel(), ctypes.byref(ln), _stream(stream)),
+               "ufvc_rans_encode_noalloc")
         return out[:ln.value]
 
     def rans_decode(self, data, idx, seg_log2: int, stream=None):

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -13,6 +14,34 @@
 #include "ufvc_ctx.h"
 
 using namespace ufvc;
+
+// Fixed device scratch of ufvc_rans_encode_noalloc: one copy per GPU, held
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel or a copy (in host code the name is only a stand-in, not a device
+// address); it uses the address hipGetSymbolAddress returned for the device,
+// looked up once per device when the first context is created there.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEV = 64;
+static void* g_scratch_ptr[NOALLOC_MAX_DEV];
+static std::mutex g_scratch_mu;
+
+// Looks up this device's scratch address (the device must be current).
+static int noalloc_scratch_init(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEV) return UFVC_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return UFVC_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return UFVC_E_DEVICE;
+  g_scratch_ptr[dev] = ptr;
+  return UFVC_OK;
+}
+
+static void* noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEV) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
 
 static hipEvent_t prof_event(ufvc_ctx* c) {
   if (c->ev_used == c->ev_pool.size()) {
@@ -358,6 +387,10 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
   if (!c) return UFVC_E_NOMEM;
   c->cfg = *cfg;
   (void)hipGetDevice(&c->device);
+  if (const int rc0 = noalloc_scratch_init(c->device)) {
+    delete c;
+    return rc0;
+  }
   const int T = cfg->T, C = cfg->C;
   const int cp = conv_prec(cfg->precision);
   const int sp = synth_prec(cfg->precision);
@@ -572,6 +605,41 @@ int ufvc_rans_encode(ufvc_ctx* c, const uint8_t* sym, const uint8_t* idx, size_t
   HeaderFields hf{};
   CK(launch_compact(c->rw.scratch, 0, slot_bytes(sl), c->rw.info, 0, nseg, 0, hf, out, capacity,
                     c->result, c->rw.seg_off, s));
+  CK(hipMemcpyAsync(c->result_host, c->result, 8, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  *out_len = (size_t)c->result_host[0];
+  return *out_len > capacity ? UFVC_E_NOSPC : UFVC_OK;
+}
+
+int ufvc_rans_encode_noalloc(ufvc_ctx* c, const uint8_t* sym, const uint8_t* idx, size_t n, int sl,
+                             uint8_t* out, size_t capacity, size_t* out_len, void* stream) {
+  if (!c || !sym || !idx || !out || !out_len || sl < 5 || sl > 24) return UFVC_E_INVAL;
+  if (n > ((size_t)1 << 32)) return UFVC_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int nseg = nseg_of((long)n, sl);
+  // scratch layout: padded symbol copy, padded index copy, segment slots,
+  // segment word ranges, segment byte offsets (each part 256-byte aligned)
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t pad_bytes = up(n + CODER_PAD);
+  const size_t o_idx = pad_bytes;
+  const size_t o_slot = 2 * pad_bytes;
+  const size_t o_info = o_slot + up(slot_bytes(sl) * (size_t)nseg);
+  const size_t o_off = o_info + up(sizeof(SegInfo) * (size_t)nseg);
+  const size_t need = o_off + up(4 * (size_t)nseg);
+  if (need > NOALLOC_SCRATCH_BYTES) return UFVC_E_SCRATCH;
+  uint8_t* base = static_cast<uint8_t*>(noalloc_scratch(c->device));
+  if (!base) return UFVC_E_DEVICE;
+  if (n) {
+    CK(hipMemcpyAsync(base, sym, n, hipMemcpyDeviceToDevice, s));
+    CK(hipMemcpyAsync(base + o_idx, idx, n, hipMemcpyDeviceToDevice, s));
+  }
+  SegInfo* info = reinterpret_cast<SegInfo*>(base + o_info);
+  EncStream ez{nullptr, nullptr, 0, 0, 5, 0};
+  EncStream ey{base, base + o_idx, 0, (long)n, sl, nseg};
+  CK(launch_rans_encode(c->tab, ez, ey, base + o_slot, 0, slot_bytes(sl), info, s));
+  HeaderFields hf{};
+  CK(launch_compact(base + o_slot, 0, slot_bytes(sl), info, 0, nseg, 0, hf, out, capacity, c->result,
+                    reinterpret_cast<uint32_t*>(base + o_off), s));
   CK(hipMemcpyAsync(c->result_host, c->result, 8, hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
   *out_len = (size_t)c->result_host[0];
