@@ -9,6 +9,8 @@ never does, and this package imports nothing from the product.
 Modules
   nets      stand-in transforms: pad, patchify, direct-sum conv, analysis,
             hyper prior, entropy parameters, synthesis (Sec. 3.1-3.4)
+  quadtree  quadtree partition and four-step progressive means (Sec. 3.4,
+            Fig. 3 (a))
   entropy   scale table, index thresholds, symbolisation, Gaussian CDF tables
             (Sec. 3.4, the r = round(y - mu) / y = r + mu equations)
   rans      interleaved 32-lane rANS, per segment (arithmetic coder "AE/AD"
@@ -21,4 +23,4 @@ network itself has no counterpart in the paper (its trained weights are not
 used), so its *behaviour* versus the paper's codec is parity unpinned by
 construction; every operation it is built from is pinned.
 """
-from . import nets, entropy, rans, container, codec  # noqa: F401
+from . import nets, entropy, rans, container, quadtree, codec  # noqa: F401

@@ -5,11 +5,15 @@ Test infrastructure only (see the package docstring).
   offset  field
    0      u32 magic, the bytes "UFV1"
    4      u16 T, u16 C, u16 H, u16 W        (H, W unpadded)
-  12      u8 seg_log2 (y), u8 seg_log2_z (z), u8 k_z, u8 reserved = 0
+  12      u8 seg_log2 (y), u8 seg_log2_z (z), u8 k_z, u8 flags
   16      u32 model_tag                     (identifies the weights)
   20      u32 n_seg_z, u32 n_seg_y
   28      u32 seg_bytes[n_seg_z + n_seg_y]
   ...     z segments, then y segments, each a multiple of 4 bytes
+
+flags names the model structure the stream needs (the decoder must run the
+same one): bit 0 (FLAG_QUADTREE) = four-step progressive means over the
+quadtree partition (Sec. 3.4, Fig. 3 (a)).  Other bits must be zero.
 
 The paper only says the latent is written to a bit-stream in one interaction
 (Sec. 3.4); this layout is this codec's own.  Pins: round trip, and every
@@ -24,12 +28,18 @@ HEADER = struct.Struct("<4sHHHHBBBBIII")
 assert HEADER.size == 28
 
 
+FLAG_QUADTREE = 1
+KNOWN_FLAGS = FLAG_QUADTREE
+
+
 class BadContainer(ValueError):
     pass
 
 
-def pack(T, C, H, W, seg_log2, seg_log2_z, k_z, model_tag, z_segs, y_segs) -> bytes:
-    hdr = HEADER.pack(MAGIC, T, C, H, W, seg_log2, seg_log2_z, k_z, 0,
+def pack(T, C, H, W, seg_log2, seg_log2_z, k_z, model_tag, z_segs, y_segs, flags=0) -> bytes:
+    if flags & ~KNOWN_FLAGS:
+        raise ValueError("unknown flags")
+    hdr = HEADER.pack(MAGIC, T, C, H, W, seg_log2, seg_log2_z, k_z, flags,
                       model_tag & 0xFFFFFFFF, len(z_segs), len(y_segs))
     table = struct.pack(f"<{len(z_segs) + len(y_segs)}I", *[len(s) for s in z_segs + y_segs])
     return hdr + table + b"".join(z_segs) + b"".join(y_segs)
@@ -38,9 +48,11 @@ def pack(T, C, H, W, seg_log2, seg_log2_z, k_z, model_tag, z_segs, y_segs) -> by
 def parse(data: bytes) -> dict:
     if len(data) < HEADER.size:
         raise BadContainer("truncated header")
-    (magic, T, C, H, W, sl, slz, kz, rsv, tag, nz, ny) = HEADER.unpack_from(data, 0)
-    if magic != MAGIC or rsv != 0:
+    (magic, T, C, H, W, sl, slz, kz, flags, tag, nz, ny) = HEADER.unpack_from(data, 0)
+    if magic != MAGIC:
         raise BadContainer("bad magic")
+    if flags & ~KNOWN_FLAGS:
+        raise BadContainer("unknown flags")
     nt = nz + ny
     off = HEADER.size + 4 * nt
     if len(data) < off:
@@ -54,5 +66,5 @@ def parse(data: bytes) -> dict:
         off += sz
     if off != len(data):
         raise BadContainer("trailing bytes")
-    return dict(T=T, C=C, H=H, W=W, seg_log2=sl, seg_log2_z=slz, k_z=kz, model_tag=tag,
-                z_segs=segs[:nz], y_segs=segs[nz:])
+    return dict(T=T, C=C, H=H, W=W, seg_log2=sl, seg_log2_z=slz, k_z=kz, flags=flags,
+                model_tag=tag, z_segs=segs[:nz], y_segs=segs[nz:])

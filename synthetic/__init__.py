@@ -69,8 +69,13 @@ def video_chunk(T: int, H: int, W: int, max_shift: int, seed: int = 1,
     return frames
 
 
-def weight_shapes(T: int, C: int) -> list[tuple[str, tuple[int, int, int, int]]]:
-    """Names and OIHW shapes of the stand-in network's conv layers, in draw order."""
+def weight_shapes(T: int, C: int, quadtree: bool = False
+                  ) -> list[tuple[str, tuple[int, int, int, int]]]:
+    """Names and OIHW shapes of the stand-in network's conv layers, in draw order.
+
+    quadtree adds the three mean-step layers m1, m2, m3 (C x C), drawn after
+    the frame heads, so the other layers' draws are those of the base model.
+    """
     shapes = [
         ("a1", (C, 192 * T, 3, 3)),
         ("a2", (C, C, 3, 3)),
@@ -85,14 +90,16 @@ def weight_shapes(T: int, C: int) -> list[tuple[str, tuple[int, int, int, int]]]
         shapes.append((f"k1_{t}", (C, C, 3, 3)))
         shapes.append((f"k2_{t}", (C, C, 3, 3)))
         shapes.append((f"k3_{t}", (192, C, 3, 3)))
+    if quadtree:
+        shapes += [(f"m{k}", (C, C, 3, 3)) for k in (1, 2, 3)]
     return shapes
 
 
-def stand_in_weights(T: int, C: int) -> dict[str, np.ndarray]:
+def stand_in_weights(T: int, C: int, quadtree: bool = False) -> dict[str, np.ndarray]:
     """Seeded He-normal weights for the (T, C) stand-in model, float32 OIHW."""
     rng = np.random.default_rng([0, T, C])
     out: dict[str, np.ndarray] = {}
-    for name, shape in weight_shapes(T, C):
+    for name, shape in weight_shapes(T, C, quadtree):
         cin = shape[1]
         out[name] = (rng.standard_normal(shape) * np.sqrt(2.0 / (cin * 9))).astype(np.float32)
     return out

@@ -23,6 +23,12 @@ def test_container_round_trip_and_errors():
     for bad in (bs[:20], bs[:-1], bs + b"\0\0\0\0", b"XFV1" + bs[4:]):
         with pytest.raises(container.BadContainer):
             container.parse(bad)
+    # the flags byte: the quadtree bit round-trips, unknown bits are refused
+    assert d["flags"] == 0
+    q = container.pack(4, 64, 64, 64, 14, 10, 22, 1, z, y, flags=container.FLAG_QUADTREE)
+    assert q[15] == 1 and container.parse(q)["flags"] == container.FLAG_QUADTREE
+    with pytest.raises(container.BadContainer):
+        container.parse(q[:15] + b"\x02" + q[16:])
 
 
 @pytest.fixture(scope="module")
