@@ -81,6 +81,13 @@ def conv_flops(T, C, h, w):
     }
 
 
+def mean_step_flops(C, h, w):
+    """Algorithmic FLOPs of the three quadtree mean steps of one side: step k
+    gives C / 4 outputs per position from the k earlier partitions (k C / 4
+    input channels per tap)."""
+    return sum(2.0 * h * w * (C // 4) * 9 * k * (C // 4) for k in (1, 2, 3))
+
+
 def a1_algorithmic_bytes(T, C, H, W, h, w):
     """Bytes a1 must move once: the float32 frames and its bf16 weights read,
     its bf16 activation written."""
@@ -279,6 +286,43 @@ def run_batch_c3(torch, ufvc, steps, seg_log2, seg_log2_z):
     for m in models.values():
         m.close()
     return res
+
+
+def run_quadtree(torch, ufvc, chunks, H, W, steps, warmup, seg_log2, seg_log2_z, lanes,
+                 autotune=True):
+    """The quadtree model (four-step progressive means): the headline's
+    workload and step, one chunk at a time (with the mean steps' HIP-event
+    times) and with `lanes` chunks in flight."""
+    from synthetic import stand_in_weights
+    T, C = chunks[0].shape[0], 128
+    wq = stand_in_weights(T, C, quadtree=True)
+    r = run_codec(torch, ufvc, wq, "bf16", chunks, H, W, steps, warmup, seg_log2, seg_log2_z,
+                  profile=True, autotune=autotune)
+    rp = run_pipelined(torch, ufvc, wq, "bf16", chunks, H, W, steps, warmup, seg_log2,
+                       seg_log2_z, lanes=lanes)
+    h, w = -(-H // 16) * 2, -(-W // 16) * 2
+    fl = mean_step_flops(C, h, w)
+    st = r["stages"]
+    out = {"value": round(T * rp["steps"] / rp["seconds"], 2), "unit": "frames/s",
+           "chunks_in_flight": lanes,
+           "sequential": round(T * steps / r["seconds"], 2),
+           "latency_ms_p99": round(float(np.percentile(rp["lat"], 99)), 4),
+           "bytes": r["bytes"]}
+    for side in ("enc", "dec"):
+        k = f"mean_steps_{side}"
+        if k in st:
+            ms = st[k][0] / steps
+            out[f"{k}_ms"] = round(ms, 4)
+            out[f"{k}_tflops"] = round(fl / (ms * 1e-3) / 1e12, 2)
+    if "mean_steps_dec_ms" in out:
+        a = out["mean_steps_dec_tflops"]
+        out["roofline"] = {"kernel": "mean_step_kernel (3 launches per side)", "bound": "mfma",
+                           "achieved": a, "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                           "frac": round(a / PEAK_TFLOPS["fp32"], 4),
+                           "flop_per_side": fl}
+    out["note"] = ("bf16 convs; partitions 1-3 refined by 3 float32 MFMA mean steps per side "
+                   "(Sec. 3.4 quadtree means); same 1080p T=8 chunks and step as the headline")
+    return out
 
 
 def run_fp8_c4(torch, ufvc, steps, seg_log2, seg_log2_z, n_chunks=16):
@@ -504,6 +548,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 leg (profiling runs)")
     ap.add_argument("--no-t1", action="store_true", help="skip the one-frame-chunk leg")
+    ap.add_argument("--no-quadtree", action="store_true", help="skip the quadtree-means leg")
     ap.add_argument("--lanes", type=int, default=2, help="chunks in flight for the headline run")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="finish with three plain device copies of this many MB (counter scaling)")
@@ -643,6 +688,11 @@ def main():
             "psnr_db": round(psnr_t(torch, c1[0], r1["rec"]), 4),
             "note": "T=1 chunks of 1920x1080 (the low-delay mode's chunk size; its temporal "
                     "context is not built), bf16, encode+decode per frame, one frame at a time"}
+    if not args.no_quadtree:
+        log("bench: quadtree progressive means")
+        result["quadtree"] = run_quadtree(torch, ufvc, chunks, H, W, args.steps, args.warmup,
+                                          args.seg_log2, args.seg_log2_z, args.lanes,
+                                          autotune=not args.no_autotune)
     if not args.no_batch:
         log("bench: 48-chunk batch")
         result["batch_c3"] = run_batch_c3(torch, ufvc, args.batch_steps, args.seg_log2,

@@ -69,6 +69,9 @@ typedef struct {
   uint32_t model_tag;  /* written to and checked against every bit-stream */
   int autotune;        /* 1: the first call for an (H, W) bucket times every conv
                           tile configuration per layer and keeps the fastest */
+  int quadtree;        /* 1: four-step progressive means over the quadtree
+                          partition (Sec. 3.4, Fig. 3 (a)); 0: every mean from
+                          the single pass.  See "Quadtree means" below. */
 } ufvc_config;
 
 typedef struct ufvc_ctx ufvc_ctx;
@@ -76,7 +79,20 @@ typedef struct ufvc_ctx ufvc_ctx;
 /* Number of float32 weights ufvc_create expects for (T, C): the layers
  * a1 (C x 192T x 3 x 3), a2, a3 (C x C), h (32 x C), p (2C x 32), d1, d2, d3
  * (C x C), then for t = 0..T-1: k1_t, k2_t (C x C), k3_t (192 x C), each
- * OIHW, concatenated in that order.  Returns 0 for unsupported (T, C). */
+ * OIHW, concatenated in that order.  A quadtree model (cfg.quadtree = 1)
+ * appends the mean-step layers m1, m2, m3 (C x C x 3 x 3 each), 27 C^2 more
+ * values.  Returns 0 for unsupported (T, C).
+ *
+ * Quadtree means (Sec. 3.4 with Fig. 3 (a)).  The latent is split into four
+ * partitions: element (c, v, u) has channel group g = 4c / C and spatial
+ * phase q = 2 (v mod 2) + (u mod 2), and lies in partition
+ * ({0, 2, 3, 1}[q] + g) mod 4.  The single pass gives every scale and the base
+ * mean of every element; partition k = 1, 2, 3 then gets the mean
+ * mu_base + conv3x3(r_hat restricted to partitions < k, m_k), computed on the
+ * GPU after the one-step decode of all of r_hat (and, in the encoder, before
+ * partition k is quantised).  Streams of such models carry header flag bit 0
+ * and decode only with a quadtree model; batches and the server take
+ * single-pass models only (UNSUPPORTED otherwise). */
 size_t ufvc_weight_count(int T, int C);
 
 /* Creates a context on the current HIP device: validates cfg, repacks the

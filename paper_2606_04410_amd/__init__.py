@@ -39,7 +39,8 @@ class UfvcError(RuntimeError):
 class _Config(ctypes.Structure):
     _fields_ = [("T", ctypes.c_int), ("C", ctypes.c_int), ("precision", ctypes.c_int),
                 ("seg_log2", ctypes.c_int), ("seg_log2_z", ctypes.c_int),
-                ("model_tag", ctypes.c_uint32), ("autotune", ctypes.c_int)]
+                ("model_tag", ctypes.c_uint32), ("autotune", ctypes.c_int),
+                ("quadtree", ctypes.c_int)]
 
 
 class _Chunk(ctypes.Structure):
@@ -130,17 +131,20 @@ REQ_ENCODE, REQ_DECODE = 0, 1
 TUNED_LAYERS = ("a1", "a2", "a3", "d1", "d2", "d3", "k1", "k2", "k3")
 
 
-def layer_order(T: int) -> list[str]:
+def layer_order(T: int, quadtree: bool = False) -> list[str]:
     """Layer names in the order ufvc_create expects them."""
     names = ["a1", "a2", "a3", "h", "p", "d1", "d2", "d3"]
     for t in range(T):
         names += [f"k1_{t}", f"k2_{t}", f"k3_{t}"]
+    if quadtree:
+        names += ["m1", "m2", "m3"]
     return names
 
 
-def flatten_weights(weights: dict, T: int) -> np.ndarray:
+def flatten_weights(weights: dict, T: int, quadtree: bool = False) -> np.ndarray:
     return np.ascontiguousarray(
-        np.concatenate([np.asarray(weights[n], np.float32).reshape(-1) for n in layer_order(T)]))
+        np.concatenate([np.asarray(weights[n], np.float32).reshape(-1)
+                        for n in layer_order(T, quadtree)]))
 
 
 def _check(code: int, what: str):
@@ -163,15 +167,18 @@ class Codec:
 
     def __init__(self, T: int, C: int, weights: dict, precision: str = "bf16",
                  seg_log2: int = None, seg_log2_z: int = None, model_tag: int = 0,
-                 autotune: bool = False):
+                 autotune: bool = False, quadtree: bool = None):
+        """quadtree: four-step progressive means over the quadtree partition;
+        by default on exactly when the weights hold the mean-step layers."""
         self.T, self.C = T, C
+        self.quadtree = ("m1" in weights) if quadtree is None else bool(quadtree)
         self.precision = precision
         seg_log2 = DEFAULT_SEG_LOG2 if seg_log2 is None else seg_log2
         seg_log2_z = DEFAULT_SEG_LOG2_Z if seg_log2_z is None else seg_log2_z
         self.seg_log2, self.seg_log2_z, self.model_tag = seg_log2, seg_log2_z, model_tag
-        flat = flatten_weights(weights, T)
+        flat = flatten_weights(weights, T, self.quadtree)
         cfg = _Config(T, C, PRECISIONS[precision], seg_log2, seg_log2_z, model_tag & 0xFFFFFFFF,
-                      1 if autotune else 0)
+                      1 if autotune else 0, 1 if self.quadtree else 0)
         h = ctypes.c_void_p()
         _check(lib.ufvc_create(ctypes.byref(cfg), flat.ctypes.data, flat.size, ctypes.byref(h)),
                "ufvc_create")

@@ -12,6 +12,7 @@
 
 #include "ufvc_common.h"
 #include "ufvc_ctx.h"
+#include "ufvc_means.h"
 
 using namespace ufvc;
 
@@ -233,6 +234,43 @@ static int upload_hyper_layer(Layer& L, const float* W, int cout, int cin) {
   return UFVC_OK;
 }
 
+// Mean-step weights for mean_step_kernel: three OIHW float32 C x C layers
+// to [step][tap][C / 4][C][4] (four consecutive input channels per 16 bytes).
+static int upload_mean_layers(ufvc_ctx* c, const float* W, int C) {
+  const size_t per = (size_t)9 * C * C;
+  std::vector<float> pk(3 * per);
+  for (int k = 0; k < 3; ++k)
+    for (int tap = 0; tap < 9; ++tap)
+      for (int ci = 0; ci < C; ++ci)
+        for (int n = 0; n < C; ++n)
+          pk[k * per + (((size_t)tap * (C / 4) + ci / 4) * C + n) * 4 + ci % 4] =
+              W[k * per + ((size_t)n * C + ci) * 9 + tap];
+  if (hipMalloc(&c->mw, pk.size() * 4) != hipSuccess) return UFVC_E_NOMEM;
+  CK(hipMemcpy(c->mw, pk.data(), pk.size() * 4, hipMemcpyHostToDevice));
+  c->mw_kstride = per * 4;
+  return UFVC_OK;
+}
+
+// Steps 1..3 of the quadtree means on the workspace (encoder: y != null).
+static hipError_t run_mean_steps(ufvc_ctx* c, const Geom& g, const float* y, int stage_id,
+                                 hipStream_t s) {
+  MeanArgs m{};
+  m.C = c->cfg.C;
+  m.h = g.h;
+  m.w = g.w;
+  m.sym = c->ws.sym;
+  m.P = c->ws.P;
+  m.y = y;
+  m.sym_out = c->ws.sym;
+  m.wpk = c->mw;
+  m.w_kstride = c->mw_kstride;
+  for (int k = 1; k <= 3; ++k) {
+    const hipError_t e = stage(c, stage_id, s, [&] { return launch_mean_step(k, m, s); });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 static void free_ws(ufvc_ctx* c) {
   Workspace& w = c->ws;
   void* ptrs[] = {w.act0, w.act1, w.y, w.zsym, w.P, w.idx, w.sym, w.big0, w.big1};
@@ -382,7 +420,9 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
     return UFVC_E_INVAL;
   if (cfg->precision != UFVC_FP32 && cfg->precision != UFVC_BF16 && cfg->precision != UFVC_BF16_FP8)
     return UFVC_E_UNSUPPORTED;
-  if (n_weights != weight_count_tc(cfg->T, cfg->C)) return UFVC_E_INVAL;
+  if (cfg->quadtree != 0 && cfg->quadtree != 1) return UFVC_E_INVAL;
+  const size_t n_mean = cfg->quadtree ? (size_t)27 * cfg->C * cfg->C : 0;
+  if (n_weights != weight_count_tc(cfg->T, cfg->C) + n_mean) return UFVC_E_INVAL;
   ufvc_ctx* c = new (std::nothrow) ufvc_ctx();
   if (!c) return UFVC_E_NOMEM;
   c->cfg = *cfg;
@@ -426,6 +466,7 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
   if (!rc) rc = upload_layer(c->k1, {k1cat.data()}, T * C, C, sp);
   if (!rc) rc = upload_layer(c->k2, k2s, C, C, sp);
   if (!rc) rc = upload_layer(c->k3, k3s, 192, C, sp);
+  if (!rc && cfg->quadtree) rc = upload_mean_layers(c, p, C);
   if (!rc) {
     Tables& t = c->tab;
     if (hipMalloc(&t.fc, 4 * NSCALES * NSYM) || hipMalloc(&t.magic, 4 * NSCALES * NSYM) ||
@@ -456,6 +497,7 @@ void ufvc_destroy(ufvc_ctx* c) {
     if (l->wscale) (void)hipFree(l->wscale);
   }
   free_ws(c);
+  if (c->mw) (void)hipFree(c->mw);
   void* dp[] = {c->tab.fc, c->tab.magic, c->tab.shift, c->tab.lut, c->tab.thresholds, c->tab.tail,
                 c->rw.pad_a, c->rw.pad_b, c->result, c->amax,
                 c->status, c->rw.scratch, c->rw.info, c->rw.seg_off, c->rw.seg_len};
@@ -511,12 +553,14 @@ int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uin
   // gives the same results in any case)
   CK(stage(c, S_PARAMS_ENC, s, [&] { return tuned_conv(c, S_PARAMS_ENC, P_BF16, LD_UP2, ST_F32, a, 1, s); }));
   CK(stage(c, S_EPI_ENC, s, [&] { return launch_params_epilogue(ws.P, ws.y, c->tab.thresholds, ws.idx, ws.sym, (long)g.h * g.w, C, s); }));
+  // quadtree: partitions 1..3 re-quantised with their refined means
+  if (c->cfg.quadtree) CK(run_mean_steps(c, g, ws.y, S_MEANS_ENC, s));
   // rANS: z with the fixed row, y with per-element rows
   EncStream ez{ws.zsym, nullptr, K_Z, g.nz, c->cfg.seg_log2_z, g.nseg_z};
   EncStream ey{ws.sym, ws.idx, 0, g.ny, c->cfg.seg_log2, g.nseg_y};
   CK(stage(c, S_RANS_ENC, s, [&] { return launch_rans_encode(c->tab, ez, ey, c->rw.scratch, sbz, sby, c->rw.info, s); }));
   HeaderFields hf{(uint16_t)T, (uint16_t)C, (uint16_t)H, (uint16_t)W, (uint8_t)c->cfg.seg_log2,
-                  (uint8_t)c->cfg.seg_log2_z, (uint8_t)K_Z, c->cfg.model_tag};
+                  (uint8_t)c->cfg.seg_log2_z, (uint8_t)K_Z, c->cfg.model_tag, header_flags(c)};
   CK(stage(c, S_COMPACT, s, [&] { return launch_compact(c->rw.scratch, sbz, sby, c->rw.info, g.nseg_z, g.nseg_y, 1, hf, bs, capacity,
                     c->result, c->rw.seg_off, s); }));
   CK(hipMemcpyAsync(c->result_host, c->result, 8, hipMemcpyDeviceToHost, s));
@@ -542,7 +586,7 @@ int ufvc_decode_chunk(ufvc_ctx* c, const uint8_t* bs, size_t len, int T, int H, 
   const int C = c->cfg.C;
   Workspace& ws = c->ws;
   HeaderFields ex{(uint16_t)T, (uint16_t)C, (uint16_t)H, (uint16_t)W, (uint8_t)c->cfg.seg_log2,
-                  (uint8_t)c->cfg.seg_log2_z, (uint8_t)K_Z, c->cfg.model_tag};
+                  (uint8_t)c->cfg.seg_log2_z, (uint8_t)K_Z, c->cfg.model_tag, header_flags(c)};
   CK(stage(c, S_PARSE, s, [&] { return launch_parse(bs, len, 1, ex, g.nseg_z, g.nseg_y, c->rw.seg_off, c->rw.seg_len, c->status, s); }));
   DecStream dz{nullptr, K_Z, g.nz, c->cfg.seg_log2_z, g.nseg_z, 0, ws.zsym, len};
   CK(stage(c, S_RANS_DEC_Z, s, [&] { return launch_rans_decode(c->tab, bs, c->rw.seg_off, c->rw.seg_len, dz, c->status, s); }));
@@ -553,6 +597,8 @@ int ufvc_decode_chunk(ufvc_ctx* c, const uint8_t* bs, size_t len, int T, int H, 
   // all of r_hat in one launch: its tables depend on sigma only
   DecStream dy{ws.idx, 0, g.ny, c->cfg.seg_log2, g.nseg_y, g.nseg_z, ws.sym, len};
   CK(stage(c, S_RANS_DEC_Y, s, [&] { return launch_rans_decode(c->tab, bs, c->rw.seg_off, c->rw.seg_len, dy, c->status, s); }));
+  // quadtree: the means of partitions 1..3 from the decoded residuals
+  if (c->cfg.quadtree) CK(run_mean_steps(c, g, nullptr, S_MEANS_DEC, s));
   CK(run_synthesis(c, g, ws.sym, ws.P, 2 * C, nullptr, H, W, frames, s));
   c->last_stream = s;
   c->last_h = g.h;

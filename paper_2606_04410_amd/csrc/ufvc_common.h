@@ -167,7 +167,9 @@ struct HeaderFields {
   uint16_t T, C, H, W;
   uint8_t seg_log2, seg_log2_z, k_z;
   uint32_t model_tag;
+  uint8_t flags;   // model structure bits (HDR_FLAG_*), header byte 15
 };
+constexpr uint8_t HDR_FLAG_QUADTREE = 1;   // four-step progressive means
 // seg_off: n_seg_z + n_seg_y words of scratch for the segments' offsets.
 hipError_t launch_compact(const uint8_t* scratch, size_t slot_bytes_z, size_t slot_bytes_y,
                           const SegInfo* info, int n_seg_z, int n_seg_y, int with_header,

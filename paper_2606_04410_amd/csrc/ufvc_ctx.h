@@ -54,6 +54,9 @@ struct ufvc_ctx {
   int device = 0;
   Tables tab{};
   Layer a1, a2, a3, h, p, d1, d2, d3, k1, k2, k3;
+  // quadtree progressive means: steps 1..3, each [tap][C / 4][C][4] float32
+  float* mw = nullptr;
+  size_t mw_kstride = 0;
   Workspace ws;
   RansWs rw;
   unsigned long long* result = nullptr;      // device
@@ -83,12 +86,13 @@ struct ufvc_ctx {
 enum Stage {
   S_A1, S_A2, S_A3, S_HYPER, S_PARAMS_ENC, S_EPI_ENC, S_RANS_ENC, S_COMPACT, S_PARSE,
   S_RANS_DEC_Z, S_PARAMS_DEC, S_EPI_DEC, S_RANS_DEC_Y, S_D1, S_D2, S_D3, S_K1, S_K2, S_K3,
-  S_COUNT
+  S_MEANS_ENC, S_MEANS_DEC, S_COUNT
 };
 static const char* kStageNames[S_COUNT] = {
     "a1_conv", "a2_conv", "a3_conv", "hyper_conv", "params_conv_enc", "params_epilogue_enc",
     "rans_encode", "compact", "parse", "rans_decode_z", "params_conv_dec", "params_epilogue_dec",
-    "rans_decode_y", "d1_conv", "d2_conv", "d3_conv", "k1_conv", "k2_conv", "k3_conv"};
+    "rans_decode_y", "d1_conv", "d2_conv", "d3_conv", "k1_conv", "k2_conv", "k3_conv",
+    "mean_steps_enc", "mean_steps_dec"};
 
 
 namespace ufvc {
@@ -134,6 +138,9 @@ inline bool geom(const ufvc_ctx* c, int H, int W, Geom& g) {
   g.nseg_z = nseg_of(g.nz, c->cfg.seg_log2_z);
   return true;
 }
+
+// Header flag bits of the model structure a stream needs.
+inline uint8_t header_flags(const ufvc_ctx* c) { return c->cfg.quadtree ? HDR_FLAG_QUADTREE : 0; }
 
 inline ConvArgs conv_args(int Hin, int Win, int Hout, int Wout, const Layer& L) {
   ConvArgs a{};

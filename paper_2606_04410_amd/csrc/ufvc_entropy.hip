@@ -460,7 +460,8 @@ compact_scan_kernel(CompDesc d0, const CompDesc* __restrict__ descs) {
     h[0] = 0x31564655u;  // "UFV1"
     h[1] = (uint32_t)hf.T | ((uint32_t)hf.C << 16);
     h[2] = (uint32_t)hf.H | ((uint32_t)hf.W << 16);
-    h[3] = (uint32_t)hf.seg_log2 | ((uint32_t)hf.seg_log2_z << 8) | ((uint32_t)hf.k_z << 16);
+    h[3] = (uint32_t)hf.seg_log2 | ((uint32_t)hf.seg_log2_z << 8) | ((uint32_t)hf.k_z << 16) |
+           ((uint32_t)hf.flags << 24);
     h[4] = hf.model_tag;
     h[5] = (uint32_t)d.n_seg_z;
     h[6] = (uint32_t)d.n_seg_y;
@@ -567,7 +568,8 @@ parse_kernel(ParseDesc d0, const ParseDesc* __restrict__ descs) {
       if (h[0] != 0x31564655u) bad = 1;
       if (h[1] != ((uint32_t)ex.T | ((uint32_t)ex.C << 16))) bad = 1;
       if (h[2] != ((uint32_t)ex.H | ((uint32_t)ex.W << 16))) bad = 1;
-      if (h[3] != ((uint32_t)ex.seg_log2 | ((uint32_t)ex.seg_log2_z << 8) | ((uint32_t)ex.k_z << 16)))
+      if (h[3] != ((uint32_t)ex.seg_log2 | ((uint32_t)ex.seg_log2_z << 8) | ((uint32_t)ex.k_z << 16) |
+                   ((uint32_t)ex.flags << 24)))
         bad = 1;
       if (h[4] != ex.model_tag || h[5] != (uint32_t)n_seg_z || h[6] != (uint32_t)n_seg_y) bad = 1;
     }
