@@ -16,6 +16,7 @@ Modules
   rans      interleaved 32-lane rANS, per segment (arithmetic coder "AE/AD"
             of Fig. 3; the paper does not name its coder)
   container bit-stream layout
+  dcblock   the depth-wise convolution block (supplementary DC-block section)
   color     RGB (BT.709) and YUV420 around the YUV444 interface (supplementary
             RGB section)
   codec     encode_chunk / decode_chunk end to end, metrics
@@ -25,4 +26,4 @@ network itself has no counterpart in the paper (its trained weights are not
 used), so its *behaviour* versus the paper's codec is parity unpinned by
 construction; every operation it is built from is pinned.
 """
-from . import nets, entropy, rans, container, quadtree, codec, color  # noqa: F401
+from . import nets, entropy, rans, container, quadtree, codec, color, dcblock  # noqa: F401

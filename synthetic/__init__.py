@@ -25,7 +25,8 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["video_chunk", "weight_shapes", "stand_in_weights", "Z_CHANNELS"]
+__all__ = ["video_chunk", "weight_shapes", "stand_in_weights", "dc_block_weights",
+           "feature_map", "Z_CHANNELS"]
 
 # Channels of the hyper latent z in the stand-in network.
 Z_CHANNELS = 32
@@ -103,3 +104,24 @@ def stand_in_weights(T: int, C: int, quadtree: bool = False) -> dict[str, np.nda
         cin = shape[1]
         out[name] = (rng.standard_normal(shape) * np.sqrt(2.0 / (cin * 9))).astype(np.float32)
     return out
+
+
+def dc_block_weights(C: int, seed: int = 0) -> dict[str, np.ndarray]:
+    """Seeded He-normal weights of one DC block (C channels), float32.
+
+    ``rng = numpy.random.default_rng([1, C, seed])``; drawn in the order pw1
+    (C, C), dw (C, 3, 3), pw2 (C, C), pw3 (2C, C), pw4 (C, 2C), each
+    ``standard_normal(shape) * sqrt(2 / fan_in)`` (fan_in = C, 9, C, C, 2C)
+    rounded to float32, (out, in) order.
+    """
+    rng = np.random.default_rng([1, C, seed])
+    shapes = [("pw1", (C, C), C), ("dw", (C, 3, 3), 9), ("pw2", (C, C), C),
+              ("pw3", (2 * C, C), C), ("pw4", (C, 2 * C), 2 * C)]
+    return {n: (rng.standard_normal(s) * np.sqrt(2.0 / f)).astype(np.float32) for n, s, f in shapes}
+
+
+def feature_map(C: int, h: int, w: int, seed: int = 0) -> np.ndarray:
+    """A seeded (C, h, w) float32 latent-resolution feature map: unit-variance
+    Gaussian values (the scale of the stand-in network's activations)."""
+    rng = np.random.default_rng([2, C, h, w, seed])
+    return rng.standard_normal((C, h, w)).astype(np.float32)
