@@ -325,6 +325,65 @@ def run_quadtree(torch, ufvc, chunks, H, W, steps, warmup, seg_log2, seg_log2_z,
     return out
 
 
+def run_color(torch, ufvc, chunks, H, W, steps, seg_log2, seg_log2_z):
+    """Format conversions around the YUV444 interface (BT.709 RGB, 4:2:0) on
+    the headline's 1080p T=8 frames: each kernel's HBM rate (HIP events on the
+    stream it runs on; algorithmic bytes = every value read once and written
+    once), and the RGB-in / RGB-out codec step one chunk at a time."""
+    T = chunks[0].shape[0]
+    px = T * H * W
+    nbytes = {"rgb_to_yuv444": 24.0 * px, "yuv444_to_rgb": 24.0 * px,
+              "yuv420_to_444": 18.0 * px, "yuv444_to_420": 18.0 * px}
+    src = {"rgb_to_yuv444": ("rgb", "yuv444"), "yuv444_to_rgb": ("yuv444", "rgb"),
+           "yuv420_to_444": ("yuv420", "yuv444"), "yuv444_to_420": ("yuv444", "yuv420")}
+    yuv = ufvc.convert_frames(chunks[0], "rgb", "yuv444", T, H, W)
+    f420 = ufvc.convert_frames(yuv, "yuv444", "yuv420", T, H, W)
+    inputs = {"rgb": chunks[0], "yuv444": yuv, "yuv420": f420}
+    stream = torch.cuda.current_stream()
+    out = {}
+    reps = 20
+    for k, (a, b) in src.items():
+        dst = ufvc.convert_frames(inputs[a], a, b, T, H, W)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            ufvc.convert_frames(inputs[a], a, b, T, H, W, out=dst)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = nbytes[k] / (ms * 1e-3) / 1e9
+        out[k] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
+                  "bytes": nbytes[k]}
+    from synthetic import stand_in_weights
+    c = ufvc.Codec(T, 128, stand_in_weights(T, 128), precision="bf16", seg_log2=seg_log2,
+                   seg_log2_z=seg_log2_z, model_tag=0x0800_1080, autotune=True)
+    bs = torch.empty(c.max_bitstream_bytes(H, W), dtype=torch.uint8, device="cuda")
+    rgb_out = torch.empty_like(chunks[0])
+    yuv_in = torch.empty_like(chunks[0])
+    yuv_out = torch.empty_like(chunks[0])
+
+    def step(i):
+        ufvc.convert_frames(chunks[i % len(chunks)], "rgb", "yuv444", T, H, W, out=yuv_in)
+        _, n = c.encode(yuv_in, out=bs)
+        c.decode(bs, n, H, W, out=yuv_out, check=False)
+        ufvc.convert_frames(yuv_out, "yuv444", "rgb", T, H, W, out=rgb_out)
+
+    for i in range(3):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if c.status() != 0:
+        raise RuntimeError("decode reported an error in the rgb run")
+    c.close()
+    return {"kernels": out, "rgb_codec_sequential": {"value": round(T * steps / dt, 2),
+                                                      "unit": "frames/s", "steps": steps},
+            "note": "RGB in and out (BT.709 to and from YUV444 on the GPU), one chunk at a time"}
+
+
 def run_fp8_c4(torch, ufvc, steps, seg_log2, seg_log2_z, n_chunks=16):
     """16 chunks of 1920x1088, T = 8: analysis convs BF16, synthesis convs FP8
     E4M3 (per-output-channel weight scales), entropy params FP32, tables FP64
@@ -549,6 +608,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 leg (profiling runs)")
     ap.add_argument("--no-t1", action="store_true", help="skip the one-frame-chunk leg")
     ap.add_argument("--no-quadtree", action="store_true", help="skip the quadtree-means leg")
+    ap.add_argument("--no-color", action="store_true", help="skip the format-conversion leg")
     ap.add_argument("--lanes", type=int, default=2, help="chunks in flight for the headline run")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="finish with three plain device copies of this many MB (counter scaling)")
@@ -693,6 +753,9 @@ def main():
         result["quadtree"] = run_quadtree(torch, ufvc, chunks, H, W, args.steps, args.warmup,
                                           args.seg_log2, args.seg_log2_z, args.lanes,
                                           autotune=not args.no_autotune)
+    if not args.no_color:
+        log("bench: format conversions (BT.709 RGB, 4:2:0)")
+        result["color"] = run_color(torch, ufvc, chunks, H, W, 20, args.seg_log2, args.seg_log2_z)
     if not args.no_batch:
         log("bench: 48-chunk batch")
         result["batch_c3"] = run_batch_c3(torch, ufvc, args.batch_steps, args.seg_log2,

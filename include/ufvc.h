@@ -217,6 +217,26 @@ enum { UFVC_BUF_Y = 0, UFVC_BUF_ZSYM = 1, UFVC_BUF_PARAMS = 2, UFVC_BUF_IDX = 3,
        UFVC_BUF_AMAX = 9 };
 int ufvc_copy_buffer(ufvc_ctx* ctx, int which, void* host_dst, size_t bytes);
 
+/* ---- Frame formats around the YUV444 interface ----
+ * The codec's frames are YUV444 planes (the one interface of the
+ * supplementary RGB section: RGB and YUV420 video are converted to YUV444 for
+ * inference and back afterwards, RGB with BT.709).  Full range, [0, 1],
+ * chroma centred at 1/2; BT.709 luma weights Kr = 0.2126, Kb = 0.0722.
+ * Layouts (device float32): UFVC_FMT_YUV444 and UFVC_FMT_RGB709 are
+ * [T][3][H][W] planes; UFVC_FMT_YUV420 is T planar frames, each Y [H][W]
+ * followed by Cb and Cr [H/2][W/2].  4:2:0 -> 4:4:4 repeats each chroma
+ * sample over its 2 x 2 block, 4:4:4 -> 4:2:0 takes the block mean; RGB
+ * output is clamped to [0, 1]. */
+enum { UFVC_FMT_YUV444 = 0, UFVC_FMT_RGB709 = 1, UFVC_FMT_YUV420 = 2 };
+
+/* Converts T frames of H x W (H even, W a multiple of 4) from src_fmt to
+ * dst_fmt: RGB709 <-> YUV444 (src may equal dst) and YUV420 <-> YUV444
+ * (distinct buffers).  Device pointers, caller-owned; asynchronous on
+ * `stream`.  INVAL for bad sizes or an aliased 4:2:0 conversion,
+ * UNSUPPORTED for other format pairs. */
+int ufvc_convert_frames(const float* src, int src_fmt, float* dst, int dst_fmt, int T, int H,
+                        int W, void* stream);
+
 /* ---- Batches: many chunks of uneven size per launch ----
  * A batch object runs encode or decode of n chunks (each with its own model,
  * i.e. its own T, and its own H x W) with one launch per pipeline stage and

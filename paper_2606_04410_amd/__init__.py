@@ -87,6 +87,7 @@ def _load():
         "ufvc_rans_encode_noalloc": (I, [P, P, P, S, I, P, S, ctypes.POINTER(S), P]),
         "ufvc_rans_decode": (I, [P, P, S, P, S, I, P, P]),
         "ufvc_synthesize": (I, [P, P, I, I, I, P, P]),
+        "ufvc_convert_frames": (I, [P, I, P, I, I, I, I, P]),
         "ufvc_copy_buffer": (I, [P, I, P, S]),
         "ufvc_profile_enable": (I, [P, I]),
         "ufvc_profile_stage_count": (I, []),
@@ -123,11 +124,34 @@ EXPORTS = ("ufvc_weight_count", "ufvc_create", "ufvc_destroy", "ufvc_max_bitstre
            "ufvc_rans_encode", "ufvc_rans_encode_noalloc", "ufvc_rans_decode", "ufvc_synthesize", "ufvc_copy_buffer",
            "ufvc_profile_enable", "ufvc_profile_stage_count", "ufvc_profile_stage_name",
            "ufvc_profile_read", "ufvc_get_tuning", "ufvc_tile_config", "ufvc_num_tile_configs",
-           "ufvc_force_tile_config", "ufvc_batch_create",
+           "ufvc_force_tile_config", "ufvc_convert_frames", "ufvc_batch_create",
            "ufvc_batch_destroy", "ufvc_encode_batch", "ufvc_decode_batch", "ufvc_batch_sync_status",
            "ufvc_server_create", "ufvc_server_submit", "ufvc_server_poll", "ufvc_server_stats",
            "ufvc_server_destroy")
 REQ_ENCODE, REQ_DECODE = 0, 1
+FMT_YUV444, FMT_RGB709, FMT_YUV420 = 0, 1, 2
+FORMATS = {"yuv444": FMT_YUV444, "rgb": FMT_RGB709, "yuv420": FMT_YUV420}
+
+
+def frame_elems(fmt: str, T: int, H: int, W: int) -> int:
+    """float32 values of T frames of H x W in a format."""
+    return T * H * W * 3 if fmt != "yuv420" else T * H * W * 3 // 2
+
+
+def convert_frames(src, src_fmt: str, dst_fmt: str, T: int, H: int, W: int, out=None,
+                   stream=None):
+    """Format conversion on the GPU (ufvc_convert_frames); src and the result
+    are cuda float32 (T, 3, H, W) for yuv444 / rgb, flat (T * 1.5 H W) for
+    yuv420."""
+    import torch
+    if out is None:
+        shape = (T, 3, H, W) if dst_fmt != "yuv420" else (frame_elems("yuv420", T, H, W),)
+        out = torch.empty(shape, dtype=torch.float32, device=src.device)
+    assert src.is_contiguous() and out.is_contiguous()
+    assert src.numel() == frame_elems(src_fmt, T, H, W) and out.numel() == frame_elems(dst_fmt, T, H, W)
+    _check(lib.ufvc_convert_frames(_ptr(src), FORMATS[src_fmt], _ptr(out), FORMATS[dst_fmt], T, H, W,
+                                   _stream(stream)), "ufvc_convert_frames")
+    return out
 TUNED_LAYERS = ("a1", "a2", "a3", "d1", "d2", "d3", "k1", "k2", "k3")
 
 
@@ -205,9 +229,16 @@ class Codec:
         return int(lib.ufvc_max_bitstream_bytes(self._h, H, W))
 
     # ----------------------------------------------------------- coding API
-    def encode(self, frames, out=None, stream=None):
-        """frames: cuda float32 (T, 3, H, W).  Returns (uint8 cuda buffer, nbytes)."""
+    def encode(self, frames, out=None, stream=None, fmt: str = "yuv444", H: int = None,
+               W: int = None):
+        """frames: cuda float32 (T, 3, H, W) YUV444 planes (the codec's
+        interface); fmt "rgb" (BT.709) or "yuv420" (flat, give H and W)
+        converts on the GPU first.  Returns (uint8 cuda buffer, nbytes)."""
         import torch
+        if fmt != "yuv444":
+            if fmt == "rgb":
+                H, W = frames.shape[2], frames.shape[3]
+            frames = convert_frames(frames, fmt, "yuv444", self.T, H, W, stream=stream)
         T, _, H, W = frames.shape
         assert frames.is_cuda and frames.dtype == torch.float32 and frames.is_contiguous()
         if out is None:
@@ -218,16 +249,23 @@ class Codec:
         _check(code, "ufvc_encode_chunk")
         return out, n.value
 
-    def decode(self, bitstream, nbytes: int, H: int, W: int, out=None, stream=None, check=True):
-        """bitstream: cuda uint8.  Returns cuda float32 (T, 3, H, W)."""
+    def decode(self, bitstream, nbytes: int, H: int, W: int, out=None, stream=None, check=True,
+               fmt: str = "yuv444"):
+        """bitstream: cuda uint8.  Returns cuda float32 (T, 3, H, W) YUV444
+        planes, or the frames converted on the GPU to fmt ("rgb", or "yuv420"
+        as a flat array)."""
         import torch
-        if out is None:
-            out = torch.empty((self.T, 3, H, W), dtype=torch.float32, device=bitstream.device)
-        _check(lib.ufvc_decode_chunk(self._h, _ptr(bitstream), nbytes, self.T, H, W, _ptr(out),
+        yuv = out if (out is not None and fmt == "yuv444") else None
+        if yuv is None:
+            yuv = torch.empty((self.T, 3, H, W), dtype=torch.float32, device=bitstream.device)
+        _check(lib.ufvc_decode_chunk(self._h, _ptr(bitstream), nbytes, self.T, H, W, _ptr(yuv),
                                      _stream(stream)), "ufvc_decode_chunk")
+        res = yuv
+        if fmt != "yuv444":
+            res = convert_frames(yuv, "yuv444", fmt, self.T, H, W, out=out, stream=stream)
         if check:
             self.sync_status(stream)
-        return out
+        return res
 
     def sync_status(self, stream=None):
         _check(lib.ufvc_sync_status(self._h, _stream(stream)), "decode status")
