@@ -384,6 +384,42 @@ def run_color(torch, ufvc, chunks, H, W, steps, seg_log2, seg_log2_z):
             "note": "RGB in and out (BT.709 to and from YUV444 on the GPU), one chunk at a time"}
 
 
+def run_dc_block(torch, ufvc, h, w, C=128, reps=50):
+    """One fused DC block on the 1080p latent (h x w x C, bf16): HIP-event
+    time per launch on the stream it runs on, against the bf16 matrix-core
+    peak (algorithmic FLOPs: 2 (6 C^2 + 9 C) per position) and HBM (input
+    read and output written once, plus the weights)."""
+    from synthetic import dc_block_weights, feature_map
+    blk = ufvc.DcBlock(C, dc_block_weights(C, seed=1))
+    x = torch.from_numpy(np.ascontiguousarray(np.transpose(feature_map(C, h, w, seed=3), (1, 2, 0))))
+    x = x.to(torch.bfloat16).cuda()
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        blk.run(x, out=y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        blk.run(x, out=y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    blk.close()
+    ms = e0.elapsed_time(e1) / reps
+    npos = h * w
+    flop = 2.0 * (6 * C * C + 9 * C) * npos
+    nbytes = 4.0 * C * npos + 12.0 * C * C + 36.0 * C
+    tf = flop / (ms * 1e-3) / 1e12
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"latent": f"{h}x{w}x{C}", "ms": round(ms, 4),
+            "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": PEAK_TFLOPS["bf16"],
+                         "unit": "TFLOP/s", "frac": round(tf / PEAK_TFLOPS["bf16"], 4),
+                         "flop_per_launch": flop},
+            "hbm": {"achieved_gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
+                    "bytes_per_launch": nbytes},
+            "note": "fused DC block (pw1, depth-wise 3x3, pw2, pw3, pw4 with residuals), "
+                    "bf16 in and out; intensity 2 (6C + 9) / 4 FLOP per byte"}
+
+
 def run_fp8_c4(torch, ufvc, steps, seg_log2, seg_log2_z, n_chunks=16):
     """16 chunks of 1920x1088, T = 8: analysis convs BF16, synthesis convs FP8
     E4M3 (per-output-channel weight scales), entropy params FP32, tables FP64
@@ -609,6 +645,7 @@ def main():
     ap.add_argument("--no-t1", action="store_true", help="skip the one-frame-chunk leg")
     ap.add_argument("--no-quadtree", action="store_true", help="skip the quadtree-means leg")
     ap.add_argument("--no-color", action="store_true", help="skip the format-conversion leg")
+    ap.add_argument("--no-dcblock", action="store_true", help="skip the DC-block leg")
     ap.add_argument("--lanes", type=int, default=2, help="chunks in flight for the headline run")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="finish with three plain device copies of this many MB (counter scaling)")
@@ -756,6 +793,9 @@ def main():
     if not args.no_color:
         log("bench: format conversions (BT.709 RGB, 4:2:0)")
         result["color"] = run_color(torch, ufvc, chunks, H, W, 20, args.seg_log2, args.seg_log2_z)
+    if not args.no_dcblock:
+        log("bench: DC block")
+        result["dc_block"] = run_dc_block(torch, ufvc, h, w, C)
     if not args.no_batch:
         log("bench: 48-chunk batch")
         result["batch_c3"] = run_batch_c3(torch, ufvc, args.batch_steps, args.seg_log2,

@@ -237,6 +237,31 @@ enum { UFVC_FMT_YUV444 = 0, UFVC_FMT_RGB709 = 1, UFVC_FMT_YUV420 = 2 };
 int ufvc_convert_frames(const float* src, int src_fmt, float* dst, int dst_fmt, int T, int H,
                         int W, void* stream);
 
+/* ---- The DC block ----
+ * The paper builds every module from one primitive, the depth-wise
+ * convolution (DC) block of DCVC-RT (supplementary material, DC-block
+ * section; the figure with its structure is missing, so the structure is a
+ * reading):  t = relu(pw1 x), x1 = x + pw2 dw3x3(t), y = x1 + pw4 relu(pw3 x1)
+ * with 1 x 1 convs pw1, pw2 (C -> C), pw3 (C -> 2C), pw4 (2C -> C), one 3 x 3
+ * depth-wise filter per channel (zero padding) and no biases.  One fused
+ * kernel per call: bf16 operands on the matrix cores, float32 accumulation,
+ * t, d, x1 (as pw3's input) and u rounded to bf16, the residual sums float32
+ * until the bf16 output.
+ *
+ * ufvc_dcblock_create uploads one block's weights for C = 64 or 128: host
+ * float32, concatenated pw1 (C x C), dw (C x 3 x 3), pw2 (C x C), pw3
+ * (2C x C), pw4 (C x 2C), each (out, in) order: 6 C^2 + 9 C values, read
+ * only during the call.  INVAL for other C or counts, NOMEM, DEVICE. */
+typedef struct ufvc_dcblock ufvc_dcblock;
+int ufvc_dcblock_create(int C, const float* weights, size_t n_weights, ufvc_dcblock** out);
+/* Frees the block's weights (after a device sync). */
+void ufvc_dcblock_destroy(ufvc_dcblock* b);
+/* y = DC block(x) on an h x w latent: x and y are device bf16 bit patterns,
+ * [h][w][C] (channels innermost), distinct caller-owned buffers.
+ * Asynchronous on `stream`.  INVAL for null or aliased pointers or empty
+ * sizes. */
+int ufvc_dcblock_run(ufvc_dcblock* b, const uint16_t* x, uint16_t* y, int h, int w, void* stream);
+
 /* ---- Batches: many chunks of uneven size per launch ----
  * A batch object runs encode or decode of n chunks (each with its own model,
  * i.e. its own T, and its own H x W) with one launch per pipeline stage and

@@ -97,6 +97,9 @@ def _load():
         "ufvc_tile_config": (I, [I, P, P, P]),
         "ufvc_num_tile_configs": (I, []),
         "ufvc_force_tile_config": (I, [P, I]),
+        "ufvc_dcblock_create": (I, [I, P, S, ctypes.POINTER(P)]),
+        "ufvc_dcblock_destroy": (None, [P]),
+        "ufvc_dcblock_run": (I, [P, P, P, I, I, P]),
         "ufvc_batch_create": (I, [P, I, ctypes.POINTER(P)]),
         "ufvc_batch_destroy": (None, [P]),
         "ufvc_encode_batch": (I, [P, P, I, P]),
@@ -124,7 +127,8 @@ EXPORTS = ("ufvc_weight_count", "ufvc_create", "ufvc_destroy", "ufvc_max_bitstre
            "ufvc_rans_encode", "ufvc_rans_encode_noalloc", "ufvc_rans_decode", "ufvc_synthesize", "ufvc_copy_buffer",
            "ufvc_profile_enable", "ufvc_profile_stage_count", "ufvc_profile_stage_name",
            "ufvc_profile_read", "ufvc_get_tuning", "ufvc_tile_config", "ufvc_num_tile_configs",
-           "ufvc_force_tile_config", "ufvc_convert_frames", "ufvc_batch_create",
+           "ufvc_force_tile_config", "ufvc_convert_frames", "ufvc_dcblock_create",
+           "ufvc_dcblock_destroy", "ufvc_dcblock_run", "ufvc_batch_create",
            "ufvc_batch_destroy", "ufvc_encode_batch", "ufvc_decode_batch", "ufvc_batch_sync_status",
            "ufvc_server_create", "ufvc_server_submit", "ufvc_server_poll", "ufvc_server_stats",
            "ufvc_server_destroy")
@@ -373,6 +377,44 @@ class Codec:
         elif which == BUF_AMAX:
             a = a.view(np.float32)
         return a
+
+
+DC_BLOCK_LAYERS = ("pw1", "dw", "pw2", "pw3", "pw4")
+
+
+class DcBlock:
+    """One fused DC block (depth-wise 3x3 between point-wise mixings, then a
+    point-wise feed-forward stage) on bf16 [h][w][C] feature maps."""
+
+    def __init__(self, C: int, weights: dict):
+        self.C = C
+        flat = np.ascontiguousarray(np.concatenate(
+            [np.asarray(weights[n], np.float32).reshape(-1) for n in DC_BLOCK_LAYERS]))
+        h = ctypes.c_void_p()
+        _check(lib.ufvc_dcblock_create(C, flat.ctypes.data, flat.size, ctypes.byref(h)),
+               "ufvc_dcblock_create")
+        self._h = h
+
+    def run(self, x, out=None, stream=None):
+        """x: cuda bfloat16 (h, w, C) contiguous.  Returns bfloat16 (h, w, C)."""
+        import torch
+        assert x.is_cuda and x.dtype == torch.bfloat16 and x.is_contiguous() and x.shape[2] == self.C
+        if out is None:
+            out = torch.empty_like(x)
+        _check(lib.ufvc_dcblock_run(self._h, _ptr(x), _ptr(out), x.shape[0], x.shape[1],
+                                    _stream(stream)), "ufvc_dcblock_run")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.ufvc_dcblock_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libufvc.so")
-SOURCES = ["ufvc_conv.hip", "ufvc_entropy.hip", "ufvc_means.hip", "ufvc_color.hip",
+SOURCES = ["ufvc_conv.hip", "ufvc_entropy.hip", "ufvc_means.hip", "ufvc_color.hip", "ufvc_dcblock.hip",
            "ufvc_capi.hip", "ufvc_batch.hip", "ufvc_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

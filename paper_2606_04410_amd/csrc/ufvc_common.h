@@ -120,6 +120,23 @@ TileCfg conv_cfg(int cfg);
 // stride and channel counts)
 bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int cfg);
 
+// ------------------------------------------------------------ DC block ----
+// One fused DC block (ufvc_dcblock.hip): bf16 [h][w][C] in and out, weights
+// bf16 (out, in) matrices pw1 (C x C), pw2 (C x C), pw3 (2C x C), pw4
+// (C x 2C) and float32 depth-wise taps dw [C][9].
+struct DcBlockArgs {
+  const __bf16* x;
+  __bf16* y;
+  int h, w;
+  const __bf16* pw1;
+  const __bf16* pw2;
+  const __bf16* pw3;
+  const __bf16* pw4;
+  const float* dw;
+};
+// tile_rows: 4 or 8 (positions per workgroup: tile_rows x 16)
+hipError_t launch_dc_block(int C, const DcBlockArgs& a, hipStream_t s, int tile_rows = 8);
+
 // ------------------------------------------------------------- entropy ----
 constexpr int NSCALES = 64;
 constexpr int NSYM = 65;
