@@ -8,7 +8,8 @@ never does, and this package imports nothing from the product.
 
 Modules
   nets      stand-in transforms: pad, patchify, direct-sum conv, analysis,
-            hyper prior, entropy parameters, synthesis (Sec. 3.1-3.4)
+            hyper prior, entropy parameters, synthesis, temporal context
+            (Sec. 3.1-3.4)
   quadtree  quadtree partition and four-step progressive means (Sec. 3.4,
             Fig. 3 (a))
   entropy   scale table, index thresholds, symbolisation, Gaussian CDF tables

@@ -13,7 +13,9 @@ Test infrastructure only (see the package docstring).
 
 flags names the model structure the stream needs (the decoder must run the
 same one): bit 0 (FLAG_QUADTREE) = four-step progressive means over the
-quadtree partition (Sec. 3.4, Fig. 3 (a)).  Other bits must be zero.
+quadtree partition (Sec. 3.4, Fig. 3 (a)); bit 1 (FLAG_TEMPORAL) = the chunk
+is coded conditioned on the temporal context of its stream (Sec. 3.1).
+Other bits must be zero.
 
 The paper only says the latent is written to a bit-stream in one interaction
 (Sec. 3.4); this layout is this codec's own.  Pins: round trip, and every
@@ -29,7 +31,8 @@ assert HEADER.size == 28
 
 
 FLAG_QUADTREE = 1
-KNOWN_FLAGS = FLAG_QUADTREE
+FLAG_TEMPORAL = 2
+KNOWN_FLAGS = FLAG_QUADTREE | FLAG_TEMPORAL
 
 
 class BadContainer(ValueError):

@@ -17,6 +17,17 @@ plain 3x3 convolutions with seeded random weights:
              o_t = conv(relu(conv(relu(conv(F, k1_t)), k2_t)), k3_t)
              x_hat_t = clamp(crop(pixel_shuffle8(o_t)), 0, 1)
 
+Temporal chunk context (Sec. 3.1 with the Fig. 2 caption, Sec. 3.3, Sec. 3.4):
+a model whose weights hold the context layers (c1, c2, a1c, pc, d1c) carries
+the context C_i of chunk i.  It conditions the chunk encoder (a1 also sees
+C_i), the prior s_i of the entropy parameters (P also sees C_i) and the chunk
+decoder (d1 also sees C_i); each "also sees" is a concatenation along
+channels, i.e. one more conv summed in before the activation.  The joint
+feature F_i of chunk i forms the next context through the context network,
+C_{i+1} = relu(conv(relu(conv(F_i, c1)), c2)); the first chunk of a stream
+has C_0 = 0 (so it is coded exactly as by the base model).  The paper gives
+no internals (readings).
+
 Pins: ``conv`` against a brute-force seven-loop sum and torch's float64
 conv2d; ``patchify`` / ``pixel_shuffle8`` / ``up2`` / ``pad16`` against torch's
 pixel_unshuffle / pixel_shuffle / nearest interpolate / replicate pad;
@@ -111,10 +122,14 @@ def rint_clamp(x: np.ndarray) -> np.ndarray:
     return np.clip(np.rint(x), -RMAX, RMAX)
 
 
-def analysis(frames: np.ndarray, wts: dict) -> np.ndarray:
-    """Chunk encoder: frames (T, 3, H, W) in [0, 1] -> latent y (C, h, w)."""
+def analysis(frames: np.ndarray, wts: dict, ctx: np.ndarray = None) -> np.ndarray:
+    """Chunk encoder: frames (T, 3, H, W) in [0, 1] -> latent y (C, h, w);
+    with a temporal context ctx (C, h, w), a1 sees concat(X, ctx)."""
     X = patchify(pad16(frames.astype(np.float64)))
-    a1 = relu(conv(X, wts["a1"]))
+    pre = conv(X, wts["a1"])
+    if ctx is not None:
+        pre = pre + conv(ctx, wts["a1c"])
+    a1 = relu(pre)
     a2 = relu(conv(a1, wts["a2"]))
     return conv(a2, wts["a3"])
 
@@ -124,18 +139,25 @@ def hyper(y: np.ndarray, wts: dict) -> np.ndarray:
     return rint_clamp(conv(y, wts["h"], stride=2))
 
 
-def params(z_hat: np.ndarray, wts: dict, h: int, w: int):
-    """Entropy parameters in one pass (Sec. 3.4): returns (mu, sigma)."""
+def params(z_hat: np.ndarray, wts: dict, h: int, w: int, ctx: np.ndarray = None):
+    """Entropy parameters in one pass (Sec. 3.4): returns (mu, sigma).  With a
+    temporal context the prior is s = concat(up2(z_hat), ctx)."""
     C = wts["p"].shape[0] // 2
     P = conv(up2(z_hat, h, w), wts["p"])
+    if ctx is not None:
+        P = P + conv(ctx, wts["pc"])
     mu = P[:C]
     sigma = np.clip(softplus(P[C:]), SIGMA_MIN, SIGMA_MAX)
     return mu, sigma
 
 
-def chunk_decoder(y_hat: np.ndarray, wts: dict) -> np.ndarray:
-    """Cross-frame stack producing the joint feature F (Sec. 3.1)."""
-    f = relu(conv(y_hat, wts["d1"]))
+def chunk_decoder(y_hat: np.ndarray, wts: dict, ctx: np.ndarray = None) -> np.ndarray:
+    """Cross-frame stack producing the joint feature F (Sec. 3.1); with a
+    temporal context, d1 sees concat(y_hat, ctx)."""
+    pre = conv(y_hat, wts["d1"])
+    if ctx is not None:
+        pre = pre + conv(ctx, wts["d1c"])
+    f = relu(pre)
     f = relu(conv(f, wts["d2"]))
     return relu(conv(f, wts["d3"]))
 
@@ -148,10 +170,15 @@ def frame_decoder(F: np.ndarray, wts: dict, t: int, H: int, W: int) -> np.ndarra
     return np.clip(pixel_shuffle8(o)[:, :H, :W], 0.0, 1.0)
 
 
+def context(F: np.ndarray, wts: dict) -> np.ndarray:
+    """Temporal context of the next chunk from this chunk's joint feature."""
+    return relu(conv(relu(conv(F, wts["c1"])), wts["c2"]))
+
+
 def synthesis(y_hat: np.ndarray, wts: dict, T: int, H: int, W: int,
-              clamp: bool = True) -> np.ndarray:
+              clamp: bool = True, ctx: np.ndarray = None) -> np.ndarray:
     """Chunk decoder + T frame-specific decoders -> frames (T, 3, H, W)."""
-    F = chunk_decoder(y_hat, wts)
+    F = chunk_decoder(y_hat, wts, ctx)
     out = np.empty((T, 3, H, W), dtype=np.float64)
     for t in range(T):
         if clamp:

@@ -70,12 +70,15 @@ def video_chunk(T: int, H: int, W: int, max_shift: int, seed: int = 1,
     return frames
 
 
-def weight_shapes(T: int, C: int, quadtree: bool = False
+def weight_shapes(T: int, C: int, quadtree: bool = False, temporal: bool = False
                   ) -> list[tuple[str, tuple[int, int, int, int]]]:
     """Names and OIHW shapes of the stand-in network's conv layers, in draw order.
 
     quadtree adds the three mean-step layers m1, m2, m3 (C x C), drawn after
     the frame heads, so the other layers' draws are those of the base model.
+    temporal adds, after those, the context network c1, c2 (C x C) and the
+    context inputs of a1 (a1c, C x C), of the entropy parameters (pc, 2C x C)
+    and of d1 (d1c, C x C).
     """
     shapes = [
         ("a1", (C, 192 * T, 3, 3)),
@@ -93,14 +96,18 @@ def weight_shapes(T: int, C: int, quadtree: bool = False
         shapes.append((f"k3_{t}", (192, C, 3, 3)))
     if quadtree:
         shapes += [(f"m{k}", (C, C, 3, 3)) for k in (1, 2, 3)]
+    if temporal:
+        shapes += [("c1", (C, C, 3, 3)), ("c2", (C, C, 3, 3)), ("a1c", (C, C, 3, 3)),
+                   ("pc", (2 * C, C, 3, 3)), ("d1c", (C, C, 3, 3))]
     return shapes
 
 
-def stand_in_weights(T: int, C: int, quadtree: bool = False) -> dict[str, np.ndarray]:
+def stand_in_weights(T: int, C: int, quadtree: bool = False, temporal: bool = False
+                     ) -> dict[str, np.ndarray]:
     """Seeded He-normal weights for the (T, C) stand-in model, float32 OIHW."""
     rng = np.random.default_rng([0, T, C])
     out: dict[str, np.ndarray] = {}
-    for name, shape in weight_shapes(T, C, quadtree):
+    for name, shape in weight_shapes(T, C, quadtree, temporal):
         cin = shape[1]
         out[name] = (rng.standard_normal(shape) * np.sqrt(2.0 / (cin * 9))).astype(np.float32)
     return out

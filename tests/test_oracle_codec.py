@@ -28,7 +28,7 @@ def test_container_round_trip_and_errors():
     q = container.pack(4, 64, 64, 64, 14, 10, 22, 1, z, y, flags=container.FLAG_QUADTREE)
     assert q[15] == 1 and container.parse(q)["flags"] == container.FLAG_QUADTREE
     with pytest.raises(container.BadContainer):
-        container.parse(q[:15] + b"\x02" + q[16:])
+        container.parse(q[:15] + b"\x04" + q[16:])
 
 
 @pytest.fixture(scope="module")
