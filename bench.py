@@ -325,6 +325,71 @@ def run_quadtree(torch, ufvc, chunks, H, W, steps, warmup, seg_log2, seg_log2_z,
     return out
 
 
+def run_temporal(torch, ufvc, chunks, H, W, steps, warmup, seg_log2, seg_log2_z, lanes):
+    """The temporal-context model: each lane codes one stream of 1080p T=8
+    chunks in order (its encoder and decoder stream objects carry the
+    context), one chunk's encode + decode per step; one lane, then `lanes`
+    streams in flight on their own HIP streams and host threads."""
+    import threading
+    from synthetic import stand_in_weights
+    T, C = chunks[0].shape[0], 128
+    wt = stand_in_weights(T, C, temporal=True)
+
+    def run(n_lanes, n_steps, profile):
+        codecs = [ufvc.Codec(T, C, wt, precision="bf16", seg_log2=seg_log2, seg_log2_z=seg_log2_z,
+                             model_tag=0x7E00_1080, autotune=True) for _ in range(n_lanes)]
+        encs = [ufvc.Stream(c, H, W) for c in codecs]
+        decs = [ufvc.Stream(c, H, W) for c in codecs]
+        hs = [torch.cuda.Stream() for _ in range(n_lanes)]
+        cap = codecs[0].max_bitstream_bytes(H, W)
+        bufs = [torch.empty(cap, dtype=torch.uint8, device="cuda") for _ in range(n_lanes)]
+        outs = [torch.empty((T, 3, H, W), dtype=torch.float32, device="cuda") for _ in range(n_lanes)]
+        sizes = [[] for _ in range(n_lanes)]
+
+        def lane(li, n, off):
+            for i in range(n):
+                _, nb = encs[li].encode(chunks[(off + i * n_lanes + li) % len(chunks)], out=bufs[li],
+                                        stream=hs[li])
+                sizes[li].append(nb)
+                decs[li].decode(bufs[li], nb, out=outs[li], stream=hs[li], check=False)
+
+        def go(n, off):
+            ths = [threading.Thread(target=lane, args=(li, n, off)) for li in range(n_lanes)]
+            for t in ths:
+                t.start()
+            for t in ths:
+                t.join()
+
+        go(warmup, 0)
+        torch.cuda.synchronize()
+        if profile:
+            codecs[0].profile(True)
+        per = n_steps // n_lanes
+        t0 = time.perf_counter()
+        go(per, warmup)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = codecs[0].profile_read() if profile else {}
+        for li, c in enumerate(codecs):
+            if c.status(hs[li]) != 0:
+                raise RuntimeError("temporal decode reported an error")
+            if not np.array_equal(encs[li].context().view(np.uint32), decs[li].context().view(np.uint32)):
+                raise RuntimeError("encoder and decoder contexts differ")
+        for o in encs + decs + codecs:
+            o.close()
+        return T * per * n_lanes / dt, st, int(np.mean(sizes[0][warmup:]))
+
+    seq, st, nbytes = run(1, steps, True)
+    pipe, _, _ = run(lanes, steps, False)
+    extra = {k: round(v[0] / steps, 4) for k, v in st.items()
+             if k.startswith("context") or k == "chunk_decoder_enc"}
+    return {"value": round(pipe, 2), "unit": "frames/s", "chunks_in_flight": lanes,
+            "sequential": round(seq, 2), "mean_bytes": nbytes, "context_stage_ms": extra,
+            "note": "bf16; each step encodes the stream's next 1080p T=8 chunk with its context "
+                    "and decodes it (the encoder also runs the chunk decoder and the context "
+                    "network); encoder and decoder contexts checked equal after the run"}
+
+
 def run_color(torch, ufvc, chunks, H, W, steps, seg_log2, seg_log2_z):
     """Format conversions around the YUV444 interface (BT.709 RGB, 4:2:0) on
     the headline's 1080p T=8 frames: each kernel's HBM rate (HIP events on the
@@ -646,6 +711,7 @@ def main():
     ap.add_argument("--no-quadtree", action="store_true", help="skip the quadtree-means leg")
     ap.add_argument("--no-color", action="store_true", help="skip the format-conversion leg")
     ap.add_argument("--no-dcblock", action="store_true", help="skip the DC-block leg")
+    ap.add_argument("--no-temporal", action="store_true", help="skip the temporal-context leg")
     ap.add_argument("--lanes", type=int, default=2, help="chunks in flight for the headline run")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="finish with three plain device copies of this many MB (counter scaling)")
@@ -793,6 +859,10 @@ def main():
     if not args.no_color:
         log("bench: format conversions (BT.709 RGB, 4:2:0)")
         result["color"] = run_color(torch, ufvc, chunks, H, W, 20, args.seg_log2, args.seg_log2_z)
+    if not args.no_temporal:
+        log("bench: temporal context")
+        result["temporal"] = run_temporal(torch, ufvc, chunks, H, W, args.steps, args.warmup,
+                                          args.seg_log2, args.seg_log2_z, args.lanes)
     if not args.no_dcblock:
         log("bench: DC block")
         result["dc_block"] = run_dc_block(torch, ufvc, h, w, C)

@@ -72,6 +72,9 @@ typedef struct {
   int quadtree;        /* 1: four-step progressive means over the quadtree
                           partition (Sec. 3.4, Fig. 3 (a)); 0: every mean from
                           the single pass.  See "Quadtree means" below. */
+  int temporal;        /* 1: chunks are coded conditioned on the temporal
+                          context of their stream (Sec. 3.1); such models code
+                          through ufvc_stream objects.  See "Temporal context". */
 } ufvc_config;
 
 typedef struct ufvc_ctx ufvc_ctx;
@@ -92,7 +95,21 @@ typedef struct ufvc_ctx ufvc_ctx;
  * GPU after the one-step decode of all of r_hat (and, in the encoder, before
  * partition k is quantised).  Streams of such models carry header flag bit 0
  * and decode only with a quadtree model; batches and the server take
- * single-pass models only (UNSUPPORTED otherwise). */
+ * single-pass models only (UNSUPPORTED otherwise).
+ *
+ * Temporal context (Sec. 3.1 with the Fig. 2 caption, Sec. 3.3, and the
+ * prior s_i of Sec. 3.4).  A temporal model (cfg.temporal = 1) appends, after
+ * the mean-step layers if any, the context network c1, c2 (C x C), and the
+ * context inputs a1c (C x C), pc (2C x C) and d1c (C x C), each 3 x 3 OIHW:
+ * 54 C^2 more values.  Chunk i of a stream is coded conditioned on a context
+ * C_i ([h][w][C], zero for the first chunk): a1 adds conv(C_i, a1c), the
+ * entropy parameters add conv(C_i, pc) (float32 arithmetic like the rest of
+ * that conv), d1 adds conv(C_i, d1c), each before its activation; the joint
+ * feature F_i then gives C_{i+1} = relu(conv(relu(conv(F_i, c1)), c2)).  The
+ * encoder runs the chunk decoder on its own y_hat to follow the decoder's
+ * contexts exactly.  Streams carry header flag bit 1; such models code only
+ * through ufvc_stream objects (ufvc_encode_chunk / ufvc_decode_chunk, batches
+ * and the server return UNSUPPORTED). */
 size_t ufvc_weight_count(int T, int C);
 
 /* Creates a context on the current HIP device: validates cfg, repacks the
@@ -138,6 +155,36 @@ int ufvc_decode_chunk(ufvc_ctx* ctx, const uint8_t* bitstream, size_t len,
 /* Synchronises `stream`, returns the first device-side error recorded since
  * the last call (UFVC_OK if none) and clears it. */
 int ufvc_sync_status(ufvc_ctx* ctx, void* stream);
+
+/* ---- Streams of a temporal model (Sec. 3.1: the chunk context) ----
+ * A stream object holds the temporal context of one video stream at one
+ * size on one side (an encoder and a decoder each keep their own): C_i, the
+ * context of the next chunk, in the activation type, resident on the device.
+ * Chunks must be coded and decoded in stream order.  One stream object per
+ * host thread at a time; it keeps its context pointer valid until destroyed.
+ * ufvc_stream_create: INVAL for a model that is not temporal or a bad size,
+ * NOMEM.  The context starts at zero (a stream's first chunk). */
+typedef struct ufvc_stream ufvc_stream;
+int ufvc_stream_create(ufvc_ctx* ctx, int H, int W, ufvc_stream** out);
+void ufvc_stream_destroy(ufvc_stream* st);
+/* Sets the context back to zero (the next chunk starts a new stream). */
+int ufvc_stream_reset(ufvc_stream* st);
+/* Copies the current context ([h][w][C], bf16 bits or float32 as the
+ * model's activations) to host memory; `bytes` must equal its size.
+ * Synchronises the stream's last HIP stream. */
+int ufvc_stream_copy_context(ufvc_stream* st, void* host_dst, size_t bytes);
+/* Encodes the stream's next chunk (frames as for ufvc_encode_chunk) with its
+ * context, then forms the next context.  Synchronises `stream` once.  On
+ * success the context advances; on NOSPC (nothing written past the header,
+ * *out_len = size needed) it does not. */
+int ufvc_encode_next(ufvc_stream* st, const float* frames, uint8_t* bitstream, size_t capacity,
+                     size_t* out_len, void* stream);
+/* Decodes the stream's next chunk into frames_out, then forms the next
+ * context.  Asynchronous; errors as for ufvc_decode_chunk (read with
+ * ufvc_sync_status on the model).  The context always advances: after a
+ * decode error reset the stream. */
+int ufvc_decode_next(ufvc_stream* st, const uint8_t* bitstream, size_t len, float* frames_out,
+                     void* stream);
 
 /* ---- Stage-level entry points (same kernels; used for parity testing) ---- */
 

@@ -40,7 +40,7 @@ class _Config(ctypes.Structure):
     _fields_ = [("T", ctypes.c_int), ("C", ctypes.c_int), ("precision", ctypes.c_int),
                 ("seg_log2", ctypes.c_int), ("seg_log2_z", ctypes.c_int),
                 ("model_tag", ctypes.c_uint32), ("autotune", ctypes.c_int),
-                ("quadtree", ctypes.c_int)]
+                ("quadtree", ctypes.c_int), ("temporal", ctypes.c_int)]
 
 
 class _Chunk(ctypes.Structure):
@@ -82,6 +82,12 @@ def _load():
         "ufvc_encode_chunk": (I, [P, P, I, I, I, P, S, ctypes.POINTER(S), P]),
         "ufvc_decode_chunk": (I, [P, P, S, I, I, I, P, P]),
         "ufvc_sync_status": (I, [P, P]),
+        "ufvc_stream_create": (I, [P, I, I, ctypes.POINTER(P)]),
+        "ufvc_stream_destroy": (None, [P]),
+        "ufvc_stream_reset": (I, [P]),
+        "ufvc_stream_copy_context": (I, [P, P, S]),
+        "ufvc_encode_next": (I, [P, P, P, S, ctypes.POINTER(S), P]),
+        "ufvc_decode_next": (I, [P, P, S, P, P]),
         "ufvc_get_tables": (I, [P, P, P, P]),
         "ufvc_rans_encode": (I, [P, P, P, S, I, P, S, ctypes.POINTER(S), P]),
         "ufvc_rans_encode_noalloc": (I, [P, P, P, S, I, P, S, ctypes.POINTER(S), P]),
@@ -123,7 +129,9 @@ lib = _load()
 
 # Names of the exported entry points (what include/ufvc.h declares).
 EXPORTS = ("ufvc_weight_count", "ufvc_create", "ufvc_destroy", "ufvc_max_bitstream_bytes",
-           "ufvc_encode_chunk", "ufvc_decode_chunk", "ufvc_sync_status", "ufvc_get_tables",
+           "ufvc_encode_chunk", "ufvc_decode_chunk", "ufvc_sync_status", "ufvc_stream_create",
+           "ufvc_stream_destroy", "ufvc_stream_reset", "ufvc_stream_copy_context",
+           "ufvc_encode_next", "ufvc_decode_next", "ufvc_get_tables",
            "ufvc_rans_encode", "ufvc_rans_encode_noalloc", "ufvc_rans_decode", "ufvc_synthesize", "ufvc_copy_buffer",
            "ufvc_profile_enable", "ufvc_profile_stage_count", "ufvc_profile_stage_name",
            "ufvc_profile_read", "ufvc_get_tuning", "ufvc_tile_config", "ufvc_num_tile_configs",
@@ -159,20 +167,23 @@ def convert_frames(src, src_fmt: str, dst_fmt: str, T: int, H: int, W: int, out=
 TUNED_LAYERS = ("a1", "a2", "a3", "d1", "d2", "d3", "k1", "k2", "k3")
 
 
-def layer_order(T: int, quadtree: bool = False) -> list[str]:
+def layer_order(T: int, quadtree: bool = False, temporal: bool = False) -> list[str]:
     """Layer names in the order ufvc_create expects them."""
     names = ["a1", "a2", "a3", "h", "p", "d1", "d2", "d3"]
     for t in range(T):
         names += [f"k1_{t}", f"k2_{t}", f"k3_{t}"]
     if quadtree:
         names += ["m1", "m2", "m3"]
+    if temporal:
+        names += ["c1", "c2", "a1c", "pc", "d1c"]
     return names
 
 
-def flatten_weights(weights: dict, T: int, quadtree: bool = False) -> np.ndarray:
+def flatten_weights(weights: dict, T: int, quadtree: bool = False,
+                    temporal: bool = False) -> np.ndarray:
     return np.ascontiguousarray(
         np.concatenate([np.asarray(weights[n], np.float32).reshape(-1)
-                        for n in layer_order(T, quadtree)]))
+                        for n in layer_order(T, quadtree, temporal)]))
 
 
 def _check(code: int, what: str):
@@ -195,18 +206,21 @@ class Codec:
 
     def __init__(self, T: int, C: int, weights: dict, precision: str = "bf16",
                  seg_log2: int = None, seg_log2_z: int = None, model_tag: int = 0,
-                 autotune: bool = False, quadtree: bool = None):
+                 autotune: bool = False, quadtree: bool = None, temporal: bool = None):
         """quadtree: four-step progressive means over the quadtree partition;
-        by default on exactly when the weights hold the mean-step layers."""
+        temporal: chunks coded with their stream's temporal context (through
+        Stream objects).  Each is on by default exactly when the weights hold
+        its layers (m1..m3; c1, c2, a1c, pc, d1c)."""
         self.T, self.C = T, C
         self.quadtree = ("m1" in weights) if quadtree is None else bool(quadtree)
+        self.temporal = ("c1" in weights) if temporal is None else bool(temporal)
         self.precision = precision
         seg_log2 = DEFAULT_SEG_LOG2 if seg_log2 is None else seg_log2
         seg_log2_z = DEFAULT_SEG_LOG2_Z if seg_log2_z is None else seg_log2_z
         self.seg_log2, self.seg_log2_z, self.model_tag = seg_log2, seg_log2_z, model_tag
-        flat = flatten_weights(weights, T, self.quadtree)
+        flat = flatten_weights(weights, T, self.quadtree, self.temporal)
         cfg = _Config(T, C, PRECISIONS[precision], seg_log2, seg_log2_z, model_tag & 0xFFFFFFFF,
-                      1 if autotune else 0, 1 if self.quadtree else 0)
+                      1 if autotune else 0, 1 if self.quadtree else 0, 1 if self.temporal else 0)
         h = ctypes.c_void_p()
         _check(lib.ufvc_create(ctypes.byref(cfg), flat.ctypes.data, flat.size, ctypes.byref(h)),
                "ufvc_create")
@@ -377,6 +391,66 @@ class Codec:
         elif which == BUF_AMAX:
             a = a.view(np.float32)
         return a
+
+
+class Stream:
+    """The temporal context of one video stream at one size, on one side
+    (encoder or decoder) of a temporal model: chunks go through it in stream
+    order.  Keep the codec alive while the stream is."""
+
+    def __init__(self, codec: "Codec", H: int, W: int):
+        self.codec, self.H, self.W = codec, H, W
+        h = ctypes.c_void_p()
+        _check(lib.ufvc_stream_create(codec._h, H, W, ctypes.byref(h)), "ufvc_stream_create")
+        self._h = h
+
+    def encode(self, frames, out=None, stream=None):
+        """Next chunk: cuda float32 (T, 3, H, W).  Returns (uint8 buffer, nbytes)."""
+        import torch
+        assert frames.is_cuda and frames.dtype == torch.float32 and frames.is_contiguous()
+        if out is None:
+            out = torch.empty(self.codec.max_bitstream_bytes(self.H, self.W), dtype=torch.uint8,
+                              device=frames.device)
+        n = ctypes.c_size_t(0)
+        _check(lib.ufvc_encode_next(self._h, _ptr(frames), _ptr(out), out.numel(), ctypes.byref(n),
+                                    _stream(stream)), "ufvc_encode_next")
+        return out, n.value
+
+    def decode(self, bitstream, nbytes: int, out=None, stream=None, check=True):
+        import torch
+        if out is None:
+            out = torch.empty((self.codec.T, 3, self.H, self.W), dtype=torch.float32,
+                              device=bitstream.device)
+        _check(lib.ufvc_decode_next(self._h, _ptr(bitstream), nbytes, _ptr(out), _stream(stream)),
+               "ufvc_decode_next")
+        if check:
+            self.codec.sync_status(stream)
+        return out
+
+    def context(self) -> np.ndarray:
+        """The next chunk's context, (h, w, C) float32."""
+        h, w, _, _ = self.codec.latent_size(self.H, self.W)
+        C = self.codec.C
+        act = np.float32 if self.codec.precision == "fp32" else np.uint16
+        a = np.zeros((h, w, C), act)
+        _check(lib.ufvc_stream_copy_context(self._h, a.ctypes.data, a.nbytes), "ufvc_stream_copy_context")
+        if a.dtype == np.uint16:
+            a = (a.astype(np.uint32) << 16).view(np.float32)
+        return a
+
+    def reset(self):
+        _check(lib.ufvc_stream_reset(self._h), "ufvc_stream_reset")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.ufvc_stream_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 DC_BLOCK_LAYERS = ("pw1", "dw", "pw2", "pw3", "pw4")

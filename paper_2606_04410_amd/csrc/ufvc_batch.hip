@@ -644,8 +644,8 @@ int ufvc_batch_create(ufvc_ctx* const* models, int n_models, ufvc_batch** out) {
     if (ci.C != c0.C || ci.precision != c0.precision || ci.seg_log2 != c0.seg_log2 ||
         ci.seg_log2_z != c0.seg_log2_z)
       return UFVC_E_INVAL;
-    // the batched pipeline has no quadtree mean steps
-    if (ci.quadtree) return UFVC_E_UNSUPPORTED;
+    // the batched pipeline has no quadtree mean steps and no stream contexts
+    if (ci.quadtree || ci.temporal) return UFVC_E_UNSUPPORTED;
   }
   ufvc_batch* b = new (std::nothrow) ufvc_batch();
   if (!b) return UFVC_E_NOMEM;

@@ -273,7 +273,7 @@ static hipError_t run_mean_steps(ufvc_ctx* c, const Geom& g, const float* y, int
 
 static void free_ws(ufvc_ctx* c) {
   Workspace& w = c->ws;
-  void* ptrs[] = {w.act0, w.act1, w.y, w.zsym, w.P, w.idx, w.sym, w.big0, w.big1};
+  void* ptrs[] = {w.act0, w.act1, w.y, w.zsym, w.P, w.idx, w.sym, w.big0, w.big1, w.side};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   c->ws = Workspace{};
@@ -297,6 +297,7 @@ static int ensure_ws(ufvc_ctx* c, int h, int w) {
   if (hipMalloc(&W.sym, npos * C + CODER_PAD) != hipSuccess) return UFVC_E_NOMEM;
   if (hipMalloc(&W.big0, npos * C * T * es) != hipSuccess) return UFVC_E_NOMEM;
   if (hipMalloc(&W.big1, npos * C * T * es) != hipSuccess) return UFVC_E_NOMEM;
+  if (c->cfg.temporal && hipMalloc(&W.side, npos * 2 * C * 4) != hipSuccess) return UFVC_E_NOMEM;
   W.h = h;
   W.w = w;
   return UFVC_OK;
@@ -343,10 +344,22 @@ static int ensure_pad(ufvc_ctx* c, size_t n) {
 }
 
 
+// Options of the synthesis pass for temporal models: d1 adds a conv of the
+// context; the context network turns the joint feature F into the next
+// context; the encoder runs the chunk decoder only.
+struct SynthOpts {
+  const float* d1_add = nullptr;   // float32 [pos][C], added to d1 before its ReLU
+  void* ctx_out = nullptr;         // next context [pos][C], activation type
+  bool heads = true;               // frame-specific decoders (false: F and the context only)
+  int prof_stage = -1;             // record the chunk decoder's convs under this stage
+  int ctxnet_stage = S_CTXNET_DEC; // ... and the context network's under this one
+};
+
 static hipError_t run_synthesis(ufvc_ctx* c, const Geom& g, const uint8_t* sym, const float* mu,
                                 long mu_pitch, const float* yhat, int H, int W, float* frames,
-                                hipStream_t s) {
+                                hipStream_t s, const SynthOpts& o = SynthOpts()) {
   const int C = c->cfg.C, T = c->cfg.T;
+  auto sid = [&](int id) { return o.prof_stage >= 0 ? o.prof_stage : id; };
   const int cp = conv_prec(c->cfg.precision);
   const int sp = synth_prec(c->cfg.precision);
   const int act_st = cp == P_BF16 ? ST_BF16 : ST_F32;
@@ -375,17 +388,31 @@ static hipError_t run_synthesis(ufvc_ctx* c, const Geom& g, const uint8_t* sym, 
   a.out = c->ws.act0;
   a.out_pitch = C;
   a.relu = 1;
+  a.add = o.d1_add;
+  a.add_pitch = C;
   chain(a, 0);
-  e = stage(c, S_D1, s, [&] { return tuned_conv(c, S_D1, cp, ld, act_st, a, 1, s); });
+  e = stage(c, sid(S_D1), s, [&] { return tuned_conv(c, S_D1, cp, ld, act_st, a, 1, s); });
   if (e != hipSuccess) return e;
   a = conv_args(g.h, g.w, g.h, g.w, c->d2);
   a.in = c->ws.act0; a.in_pitch = C; a.out = c->ws.act1; a.out_pitch = C; a.relu = 1;
   chain(a, 1);
-  if ((e = stage(c, S_D2, s, [&] { return tuned_conv(c, S_D2, sp, sld, act_st, a, 1, s); })) != hipSuccess) return e;
+  if ((e = stage(c, sid(S_D2), s, [&] { return tuned_conv(c, S_D2, sp, sld, act_st, a, 1, s); })) != hipSuccess) return e;
   a = conv_args(g.h, g.w, g.h, g.w, c->d3);
   a.in = c->ws.act1; a.in_pitch = C; a.out = c->ws.act0; a.out_pitch = C; a.relu = 1;
   chain(a, 2);
-  if ((e = stage(c, S_D3, s, [&] { return tuned_conv(c, S_D3, sp, sld, act_st, a, 1, s); })) != hipSuccess) return e;
+  if ((e = stage(c, sid(S_D3), s, [&] { return tuned_conv(c, S_D3, sp, sld, act_st, a, 1, s); })) != hipSuccess) return e;
+  // temporal models: the next context from F (act0), through act1
+  if (o.ctx_out) {
+    a = conv_args(g.h, g.w, g.h, g.w, c->c1);
+    a.in = c->ws.act0; a.in_pitch = C; a.out = c->ws.act1; a.out_pitch = C; a.relu = 1;
+    if ((e = stage(c, o.ctxnet_stage, s, [&] { return tuned_conv(c, T_C1, cp, LD_NHWC, act_st, a, 1, s); })) != hipSuccess)
+      return e;
+    a = conv_args(g.h, g.w, g.h, g.w, c->c2);
+    a.in = c->ws.act1; a.in_pitch = C; a.out = o.ctx_out; a.out_pitch = C; a.relu = 1;
+    if ((e = stage(c, o.ctxnet_stage, s, [&] { return tuned_conv(c, T_C2, cp, LD_NHWC, act_st, a, 1, s); })) != hipSuccess)
+      return e;
+  }
+  if (!o.heads) return hipSuccess;
   // k1 of all heads as one GEMM with T*C outputs
   a = conv_args(g.h, g.w, g.h, g.w, c->k1);
   a.in = c->ws.act0; a.in_pitch = C; a.out = c->ws.big0; a.out_pitch = (long)T * C; a.relu = 1;
@@ -405,6 +432,24 @@ static hipError_t run_synthesis(ufvc_ctx* c, const Geom& g, const uint8_t* sym, 
   return stage(c, S_K3, s, [&] { return tuned_conv(c, S_K3, sp, sld, ST_SHUFFLE, a, T, s); });
 }
 
+// Temporal models: out (float32 [pos][pitch]) = conv(context, L), the
+// context's part of a concatenated input.  The entropy-parameter part keeps
+// that conv's float32 arithmetic: in the bf16 modes the context is bf16
+// (exact) and the weights are three bf16 parts, so the repeating loader
+// feeds each context channel to its three weight blocks.
+static hipError_t context_conv(ufvc_ctx* c, const Geom& g, const Layer& L, int tune_id,
+                               const void* ctx, float* out, long out_pitch, hipStream_t s) {
+  ConvArgs a = conv_args(g.h, g.w, g.h, g.w, L);
+  a.in = ctx;
+  a.in_pitch = c->cfg.C;
+  a.out = out;
+  a.out_pitch = out_pitch;
+  a.relu = 0;
+  const int cp = conv_prec(c->cfg.precision);
+  const int ld = (tune_id == T_PC && cp == P_BF16) ? LD_REP : LD_NHWC;
+  return tuned_conv(c, tune_id, cp, ld, ST_F32, a, 1, s);
+}
+
 extern "C" {
 
 size_t ufvc_weight_count(int T, int C) {
@@ -421,8 +466,10 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
   if (cfg->precision != UFVC_FP32 && cfg->precision != UFVC_BF16 && cfg->precision != UFVC_BF16_FP8)
     return UFVC_E_UNSUPPORTED;
   if (cfg->quadtree != 0 && cfg->quadtree != 1) return UFVC_E_INVAL;
+  if (cfg->temporal != 0 && cfg->temporal != 1) return UFVC_E_INVAL;
   const size_t n_mean = cfg->quadtree ? (size_t)27 * cfg->C * cfg->C : 0;
-  if (n_weights != weight_count_tc(cfg->T, cfg->C) + n_mean) return UFVC_E_INVAL;
+  const size_t n_temporal = cfg->temporal ? (size_t)54 * cfg->C * cfg->C : 0;
+  if (n_weights != weight_count_tc(cfg->T, cfg->C) + n_mean + n_temporal) return UFVC_E_INVAL;
   ufvc_ctx* c = new (std::nothrow) ufvc_ctx();
   if (!c) return UFVC_E_NOMEM;
   c->cfg = *cfg;
@@ -467,6 +514,21 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
   if (!rc) rc = upload_layer(c->k2, k2s, C, C, sp);
   if (!rc) rc = upload_layer(c->k3, k3s, 192, C, sp);
   if (!rc && cfg->quadtree) rc = upload_mean_layers(c, p, C);
+  if (cfg->quadtree) p += (size_t)27 * C * C;
+  if (!rc && cfg->temporal) {
+    const size_t cc9 = (size_t)C * C * 9;
+    const float* wc1 = p;
+    const float* wc2 = wc1 + cc9;
+    const float* wa1c = wc2 + cc9;
+    const float* wpc = wa1c + cc9;
+    const float* wd1c = wpc + 2 * cc9;
+    if (!rc) rc = upload_layer(c->c1, {wc1}, C, C, cp);
+    if (!rc) rc = upload_layer(c->c2, {wc2}, C, C, cp);
+    if (!rc) rc = upload_layer(c->a1c, {wa1c}, C, C, cp);
+    if (!rc) rc = cp == P_BF16 ? upload_split_layer(c->pc, wpc, 2 * C, C)
+                               : upload_layer(c->pc, {wpc}, 2 * C, C, P_F32);
+    if (!rc) rc = upload_layer(c->d1c, {wd1c}, C, C, cp);
+  }
   if (!rc) {
     Tables& t = c->tab;
     if (hipMalloc(&t.fc, 4 * NSCALES * NSYM) || hipMalloc(&t.magic, 4 * NSCALES * NSYM) ||
@@ -491,7 +553,8 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
 void ufvc_destroy(ufvc_ctx* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
-  Layer* ls[] = {&c->a1, &c->a2, &c->a3, &c->h, &c->p, &c->d1, &c->d2, &c->d3, &c->k1, &c->k2, &c->k3};
+  Layer* ls[] = {&c->a1, &c->a2, &c->a3, &c->h,  &c->p,   &c->d1, &c->d2, &c->d3, &c->k1,
+                 &c->k2, &c->k3, &c->c1, &c->c2, &c->a1c, &c->pc, &c->d1c};
   for (Layer* l : ls) {
     if (l->w) (void)hipFree(l->w);
     if (l->wscale) (void)hipFree(l->wscale);
@@ -516,12 +579,16 @@ size_t ufvc_max_bitstream_bytes(const ufvc_ctx* c, int H, int W) {
          2 * (size_t)(g.ny + g.nz);
 }
 
-int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uint8_t* bs,
-                      size_t capacity, size_t* out_len, void* stream) {
-  if (!c || !frames || !bs || !out_len) return UFVC_E_INVAL;
+}  // extern "C"
+
+// Encodes one chunk; for a temporal model ctx_in is the stream's context and
+// ctx_out receives the next one (formed from the chunk decoder run on this
+// chunk's y_hat, as the decoder will).
+static int encode_impl(ufvc_ctx* c, const float* frames, int T, int H, int W, uint8_t* bs,
+                       size_t capacity, size_t* out_len, hipStream_t s, const void* ctx_in,
+                       void* ctx_out) {
   Geom g;
   if (T != c->cfg.T || !geom(c, H, W, g)) return UFVC_E_INVAL;
-  hipStream_t s = (hipStream_t)stream;
   int rc = ensure_ws(c, g.h, g.w);
   if (rc) return rc;
   const size_t sbz = slot_bytes(c->cfg.seg_log2_z), sby = slot_bytes(c->cfg.seg_log2);
@@ -531,10 +598,14 @@ int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uin
   const int cp = conv_prec(c->cfg.precision);
   const int act_st = cp == P_BF16 ? ST_BF16 : ST_F32;
   Workspace& ws = c->ws;
+  // temporal: a1 sees concat(X, C_i): its context part first
+  if (ctx_in)
+    CK(stage(c, S_CTXIN_ENC, s, [&] { return context_conv(c, g, c->a1c, T_A1C, ctx_in, ws.side, C, s); }));
   // analysis: patchify fused into a1's loader
   ConvArgs a = conv_args(g.h, g.w, g.h, g.w, c->a1);
   a.in = frames; a.T = T; a.H = H; a.W = W;
   a.out = ws.act0; a.out_pitch = C; a.relu = 1;
+  a.add = ctx_in ? ws.side : nullptr; a.add_pitch = C;
   CK(stage(c, S_A1, s, [&] { return tuned_conv(c, S_A1, cp, LD_UNSHUFFLE, act_st, a, 1, s); }));
   a = conv_args(g.h, g.w, g.h, g.w, c->a2);
   a.in = ws.act0; a.in_pitch = C; a.out = ws.act1; a.out_pitch = C; a.relu = 1;
@@ -546,9 +617,13 @@ int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uin
   a = conv_args(g.h, g.w, g.hz, g.wz, c->h);
   a.in = ws.y; a.in_pitch = C; a.out = ws.zsym; a.out_pitch = ZC;
   CK(stage(c, S_HYPER, s, [&] { return tuned_conv(c, S_HYPER, P_F32, LD_NHWC, ST_ZSYM, a, 1, s, 2); }));
-  // entropy parameters in one pass from up2(z_hat)
+  // entropy parameters in one pass from up2(z_hat) (temporal: the prior is
+  // concat(up2(z_hat), C_i), its context part first)
+  if (ctx_in)
+    CK(stage(c, S_CTXIN_ENC, s, [&] { return context_conv(c, g, c->pc, T_PC, ctx_in, ws.side, 2 * C, s); }));
   a = conv_args(g.h, g.w, g.h, g.w, c->p);
   a.in = ws.zsym; a.in_pitch = ZC; a.out = ws.P; a.out_pitch = 2 * C;
+  a.add = ctx_in ? ws.side : nullptr; a.add_pitch = 2 * C;
   // (tuned under one key for the encoder and the decoder; every configuration
   // gives the same results in any case)
   CK(stage(c, S_PARAMS_ENC, s, [&] { return tuned_conv(c, S_PARAMS_ENC, P_BF16, LD_UP2, ST_F32, a, 1, s); }));
@@ -564,6 +639,18 @@ int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uin
   CK(stage(c, S_COMPACT, s, [&] { return launch_compact(c->rw.scratch, sbz, sby, c->rw.info, g.nseg_z, g.nseg_y, 1, hf, bs, capacity,
                     c->result, c->rw.seg_off, s); }));
   CK(hipMemcpyAsync(c->result_host, c->result, 8, hipMemcpyDeviceToHost, s));
+  // temporal: the decoder's chunk decoder on this chunk's y_hat, then the
+  // context network, so the next context is the decoder's
+  if (ctx_in) {
+    CK(stage(c, S_CTXIN_ENC, s, [&] { return context_conv(c, g, c->d1c, T_D1C, ctx_in, ws.side, C, s); }));
+    SynthOpts o;
+    o.d1_add = ws.side;
+    o.ctx_out = ctx_out;
+    o.heads = false;
+    o.prof_stage = S_CHUNKDEC_ENC;
+    o.ctxnet_stage = S_CTXNET_ENC;
+    CK(run_synthesis(c, g, ws.sym, ws.P, 2 * C, nullptr, H, W, nullptr, s, o));
+  }
   CK(hipStreamSynchronize(s));
   c->last_stream = s;
   c->last_h = g.h;
@@ -572,13 +659,13 @@ int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uin
   return *out_len > capacity ? UFVC_E_NOSPC : UFVC_OK;
 }
 
-int ufvc_decode_chunk(ufvc_ctx* c, const uint8_t* bs, size_t len, int T, int H, int W,
-                      float* frames, void* stream) {
-  if (!c || !bs || !frames) return UFVC_E_INVAL;
+// Decodes one chunk; temporal models take the stream's context and write
+// the next one.
+static int decode_impl(ufvc_ctx* c, const uint8_t* bs, size_t len, int T, int H, int W,
+                       float* frames, hipStream_t s, const void* ctx_in, void* ctx_out) {
   Geom g;
   if (T != c->cfg.T || !geom(c, H, W, g)) return UFVC_E_INVAL;
   if (len > 0xFFFFFFF0ull || len < 28) return UFVC_E_INVAL;
-  hipStream_t s = (hipStream_t)stream;
   int rc = ensure_ws(c, g.h, g.w);
   if (rc) return rc;
   rc = ensure_rans(c, 0, g.nseg_z + g.nseg_y);
@@ -590,8 +677,11 @@ int ufvc_decode_chunk(ufvc_ctx* c, const uint8_t* bs, size_t len, int T, int H, 
   CK(stage(c, S_PARSE, s, [&] { return launch_parse(bs, len, 1, ex, g.nseg_z, g.nseg_y, c->rw.seg_off, c->rw.seg_len, c->status, s); }));
   DecStream dz{nullptr, K_Z, g.nz, c->cfg.seg_log2_z, g.nseg_z, 0, ws.zsym, len};
   CK(stage(c, S_RANS_DEC_Z, s, [&] { return launch_rans_decode(c->tab, bs, c->rw.seg_off, c->rw.seg_len, dz, c->status, s); }));
+  if (ctx_in)
+    CK(stage(c, S_CTXIN_DEC, s, [&] { return context_conv(c, g, c->pc, T_PC, ctx_in, ws.side, 2 * C, s); }));
   ConvArgs a = conv_args(g.h, g.w, g.h, g.w, c->p);
   a.in = ws.zsym; a.in_pitch = ZC; a.out = ws.P; a.out_pitch = 2 * C;
+  a.add = ctx_in ? ws.side : nullptr; a.add_pitch = 2 * C;
   CK(stage(c, S_PARAMS_DEC, s, [&] { return tuned_conv(c, S_PARAMS_ENC, P_BF16, LD_UP2, ST_F32, a, 1, s); }));
   CK(stage(c, S_EPI_DEC, s, [&] { return launch_params_epilogue(ws.P, nullptr, c->tab.thresholds, ws.idx, nullptr, (long)g.h * g.w, C, s); }));
   // all of r_hat in one launch: its tables depend on sigma only
@@ -599,12 +689,109 @@ int ufvc_decode_chunk(ufvc_ctx* c, const uint8_t* bs, size_t len, int T, int H, 
   CK(stage(c, S_RANS_DEC_Y, s, [&] { return launch_rans_decode(c->tab, bs, c->rw.seg_off, c->rw.seg_len, dy, c->status, s); }));
   // quadtree: the means of partitions 1..3 from the decoded residuals
   if (c->cfg.quadtree) CK(run_mean_steps(c, g, nullptr, S_MEANS_DEC, s));
-  CK(run_synthesis(c, g, ws.sym, ws.P, 2 * C, nullptr, H, W, frames, s));
+  SynthOpts o;
+  if (ctx_in) {
+    CK(stage(c, S_CTXIN_DEC, s, [&] { return context_conv(c, g, c->d1c, T_D1C, ctx_in, ws.side, C, s); }));
+    o.d1_add = ws.side;
+    o.ctx_out = ctx_out;
+  }
+  CK(run_synthesis(c, g, ws.sym, ws.P, 2 * C, nullptr, H, W, frames, s, o));
   c->last_stream = s;
   c->last_h = g.h;
   c->last_w = g.w;
   return UFVC_OK;
 }
+
+struct ufvc_stream {
+  ufvc_ctx* ctx = nullptr;
+  int H = 0, W = 0;
+  size_t bytes = 0;          // one context, [h][w][C] activation type
+  void* cur = nullptr;       // the next chunk's context
+  void* nxt = nullptr;       // written by a call, swapped in on success
+  hipStream_t last = nullptr;
+};
+
+extern "C" {
+
+int ufvc_encode_chunk(ufvc_ctx* c, const float* frames, int T, int H, int W, uint8_t* bs,
+                      size_t capacity, size_t* out_len, void* stream) {
+  if (!c || !frames || !bs || !out_len) return UFVC_E_INVAL;
+  if (c->cfg.temporal) return UFVC_E_UNSUPPORTED;
+  return encode_impl(c, frames, T, H, W, bs, capacity, out_len, (hipStream_t)stream, nullptr, nullptr);
+}
+
+int ufvc_decode_chunk(ufvc_ctx* c, const uint8_t* bs, size_t len, int T, int H, int W,
+                      float* frames, void* stream) {
+  if (!c || !bs || !frames) return UFVC_E_INVAL;
+  if (c->cfg.temporal) return UFVC_E_UNSUPPORTED;
+  return decode_impl(c, bs, len, T, H, W, frames, (hipStream_t)stream, nullptr, nullptr);
+}
+
+int ufvc_stream_create(ufvc_ctx* c, int H, int W, ufvc_stream** out) {
+  if (!c || !out) return UFVC_E_INVAL;
+  *out = nullptr;
+  Geom g;
+  if (!c->cfg.temporal || !geom(c, H, W, g)) return UFVC_E_INVAL;
+  ufvc_stream* st = new (std::nothrow) ufvc_stream();
+  if (!st) return UFVC_E_NOMEM;
+  st->ctx = c;
+  st->H = H;
+  st->W = W;
+  st->bytes = (size_t)g.h * g.w * c->cfg.C * act_elem_size(c->cfg.precision);
+  if (hipMalloc(&st->cur, st->bytes) != hipSuccess || hipMalloc(&st->nxt, st->bytes) != hipSuccess) {
+    ufvc_stream_destroy(st);
+    return UFVC_E_NOMEM;
+  }
+  if (hipMemset(st->cur, 0, st->bytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    ufvc_stream_destroy(st);
+    return UFVC_E_DEVICE;
+  }
+  *out = st;
+  return UFVC_OK;
+}
+
+void ufvc_stream_destroy(ufvc_stream* st) {
+  if (!st) return;
+  (void)hipDeviceSynchronize();
+  if (st->cur) (void)hipFree(st->cur);
+  if (st->nxt) (void)hipFree(st->nxt);
+  delete st;
+}
+
+int ufvc_stream_reset(ufvc_stream* st) {
+  if (!st) return UFVC_E_INVAL;
+  if (st->last) CK(hipStreamSynchronize(st->last));
+  CK(hipMemset(st->cur, 0, st->bytes));
+  CK(hipDeviceSynchronize());
+  return UFVC_OK;
+}
+
+int ufvc_stream_copy_context(ufvc_stream* st, void* dst, size_t bytes) {
+  if (!st || !dst || bytes != st->bytes) return UFVC_E_INVAL;
+  if (st->last) CK(hipStreamSynchronize(st->last));
+  CK(hipMemcpy(dst, st->cur, bytes, hipMemcpyDeviceToHost));
+  return UFVC_OK;
+}
+
+int ufvc_encode_next(ufvc_stream* st, const float* frames, uint8_t* bs, size_t capacity,
+                     size_t* out_len, void* stream) {
+  if (!st || !frames || !bs || !out_len) return UFVC_E_INVAL;
+  const int rc = encode_impl(st->ctx, frames, st->ctx->cfg.T, st->H, st->W, bs, capacity, out_len,
+                             (hipStream_t)stream, st->cur, st->nxt);
+  st->last = (hipStream_t)stream;
+  if (rc == UFVC_OK) std::swap(st->cur, st->nxt);
+  return rc;
+}
+
+int ufvc_decode_next(ufvc_stream* st, const uint8_t* bs, size_t len, float* frames, void* stream) {
+  if (!st || !bs || !frames) return UFVC_E_INVAL;
+  const int rc = decode_impl(st->ctx, bs, len, st->ctx->cfg.T, st->H, st->W, frames,
+                             (hipStream_t)stream, st->cur, st->nxt);
+  st->last = (hipStream_t)stream;
+  if (rc == UFVC_OK) std::swap(st->cur, st->nxt);
+  return rc;
+}
+
 
 int ufvc_sync_status(ufvc_ctx* c, void* stream) {
   if (!c) return UFVC_E_INVAL;

@@ -66,7 +66,9 @@ enum Loader {
   LD_UP2 = 3,        // nearest x2 upsampling of uint8 z symbols (value sym - 32), bf16;
                      // input channel c is symbol channel c mod in_pitch
   LD_F32 = 4,        // float32 tensor, channels innermost, feeding a bf16 conv
-  LD_Q8 = 5          // bf16 tensor quantised to FP8 E4M3 with the producer's amax scale
+  LD_Q8 = 5,         // bf16 tensor quantised to FP8 E4M3 with the producer's amax scale
+  LD_REP = 6         // bf16 tensor, channels innermost; input channel c is tensor channel
+                     // c mod in_pitch (the split-weight convs over a bf16 input)
 };
 enum Store {
   ST_BF16 = 0,     // bf16 [pos][pitch], optional ReLU
@@ -94,6 +96,11 @@ struct ConvArgs {
   long out_pitch;
   long out_goff;
   int relu;
+  // optional float32 term added to every output before the activation
+  // (bf16 and float32 stores of single-group layers): add[pos * add_pitch + n].
+  // Must not alias out: the autotuner runs a conv more than once.
+  const float* add;
+  long add_pitch;
   // FP8: per-output-channel weight scales [group][cout]; the amax (float
   // bits) of this layer's input and, for a producer, of its own output
   const float* wscale;
@@ -187,6 +194,7 @@ struct HeaderFields {
   uint8_t flags;   // model structure bits (HDR_FLAG_*), header byte 15
 };
 constexpr uint8_t HDR_FLAG_QUADTREE = 1;   // four-step progressive means
+constexpr uint8_t HDR_FLAG_TEMPORAL = 2;   // coded with the stream's temporal context
 // seg_off: n_seg_z + n_seg_y words of scratch for the segments' offsets.
 hipError_t launch_compact(const uint8_t* scratch, size_t slot_bytes_z, size_t slot_bytes_y,
                           const SegInfo* info, int n_seg_z, int n_seg_y, int with_header,

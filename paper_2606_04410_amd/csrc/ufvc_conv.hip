@@ -146,6 +146,10 @@ __device__ __forceinline__ Raw fetch_raw(const ConvArgs& a, const unsigned char*
       r.c.x = ldg(reinterpret_cast<const uint32_t*>(sp));
       r.a = __builtin_bit_cast(v4u, ldg(reinterpret_cast<const v4f*>(mp)));
     }
+  } else if constexpr (LD == LD_REP) {
+    static_assert(PREC == P_BF16, "the repeating loader feeds bf16 split-weight convs");
+    const int c0 = (slice * E + ch * (E / 2)) % (int)a.in_pitch;
+    r.a = ld16(inb + (pos * a.in_pitch + c0) * ESZ);
   } else {  // LD_UP2: input channel c reads symbol channel c mod in_pitch
     static_assert(PREC == P_BF16, "up2 loader feeds the bf16 split-weight conv");
     const int c0 = (slice * E + ch * (E / 2)) % (int)a.in_pitch;
@@ -160,7 +164,7 @@ __device__ __forceinline__ Raw fetch_raw(const ConvArgs& a, const unsigned char*
 template <int PREC, int LD>
 __device__ __forceinline__ v4u convert_raw(const Raw& r, float qinv) {
   v4u o;
-  if constexpr (LD == LD_NHWC) {
+  if constexpr (LD == LD_NHWC || LD == LD_REP) {
     o = r.a;
   } else if constexpr (LD == LD_Q8) {
     // 16 bf16 channels -> 16 FP8 E4M3 values of x * qinv (qinv = 448 / amax)
@@ -232,6 +236,9 @@ __device__ __forceinline__ v4u convert_raw(const Raw& r, float qinv) {
 template <int ST>
 __device__ __forceinline__ void store_out(const ConvArgs& a, int grp, int oy, int ox, int n, float v) {
   const long pos = (long)oy * a.Wout + ox;
+  if constexpr (ST == ST_BF16 || ST == ST_F32) {
+    if (a.add) v += ldg(a.add + pos * a.add_pitch + n);
+  }
   if constexpr (ST == ST_BF16) {
     if (a.relu) v = fmaxf(v, 0.f);
     stg(reinterpret_cast<__bf16*>(a.out) + pos * a.out_pitch + grp * a.out_goff + n, (__bf16)v);
@@ -884,6 +891,12 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
 #pragma unroll
         for (int k = 0; k < 8; ++k) o[k] = v[8 * h + k];
         if constexpr (ST == ST_BF16 || ST == ST_F32) {
+          if (a.add) {
+            const float* ad = a.add + pos * a.add_pitch + n;
+            const v4f a0 = ldg(reinterpret_cast<const v4f*>(ad)), a1 = ldg(reinterpret_cast<const v4f*>(ad + 4));
+            o[0] += a0.x; o[1] += a0.y; o[2] += a0.z; o[3] += a0.w;
+            o[4] += a1.x; o[5] += a1.y; o[6] += a1.z; o[7] += a1.w;
+          }
           if (a.relu) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) o[k] = fmaxf(o[k], 0.f);
@@ -1137,6 +1150,7 @@ static hipError_t dispatch(int prec, int loader, int store, int stride, int cfg,
   UFVC_CONV(P_BF16, LD_F32, ST_BF16, 1)
   // entropy parameters: float32 weights as three bf16 parts (exact products)
   UFVC_CONV(P_BF16, LD_UP2, ST_F32, 1)
+  UFVC_CONV(P_BF16, LD_REP, ST_F32, 1)
   // fp8 synthesis
   UFVC_CONV(P_FP8, LD_Q8, ST_BF16, 1)
   UFVC_CONV(P_FP8, LD_Q8, ST_SHUFFLE, 1)

@@ -29,6 +29,7 @@ struct Workspace {
   uint8_t* sym = nullptr;         // [h][w][C]
   void* big0 = nullptr;           // [h][w][T C]
   void* big1 = nullptr;
+  float* side = nullptr;          // temporal models: [h][w][2C], a conv of the context
 };
 
 struct RansWs {
@@ -57,6 +58,10 @@ struct ufvc_ctx {
   // quadtree progressive means: steps 1..3, each [tap][C / 4][C][4] float32
   float* mw = nullptr;
   size_t mw_kstride = 0;
+  // temporal context: context network c1, c2 and the context inputs of a1,
+  // of the entropy parameters (split into three bf16 parts in the bf16
+  // modes) and of d1
+  Layer c1, c2, a1c, pc, d1c;
   Workspace ws;
   RansWs rw;
   unsigned long long* result = nullptr;      // device
@@ -86,13 +91,17 @@ struct ufvc_ctx {
 enum Stage {
   S_A1, S_A2, S_A3, S_HYPER, S_PARAMS_ENC, S_EPI_ENC, S_RANS_ENC, S_COMPACT, S_PARSE,
   S_RANS_DEC_Z, S_PARAMS_DEC, S_EPI_DEC, S_RANS_DEC_Y, S_D1, S_D2, S_D3, S_K1, S_K2, S_K3,
-  S_MEANS_ENC, S_MEANS_DEC, S_COUNT
+  S_MEANS_ENC, S_MEANS_DEC, S_CTXIN_ENC, S_CTXIN_DEC, S_CHUNKDEC_ENC, S_CTXNET_ENC, S_CTXNET_DEC,
+  S_COUNT
 };
+// autotuner keys of the context layers (distinct from the stage ids above)
+enum TuneId { T_A1C = 64, T_PC, T_D1C, T_C1, T_C2 };
 static const char* kStageNames[S_COUNT] = {
     "a1_conv", "a2_conv", "a3_conv", "hyper_conv", "params_conv_enc", "params_epilogue_enc",
     "rans_encode", "compact", "parse", "rans_decode_z", "params_conv_dec", "params_epilogue_dec",
     "rans_decode_y", "d1_conv", "d2_conv", "d3_conv", "k1_conv", "k2_conv", "k3_conv",
-    "mean_steps_enc", "mean_steps_dec"};
+    "mean_steps_enc", "mean_steps_dec", "context_inputs_enc", "context_inputs_dec",
+    "chunk_decoder_enc", "context_net_enc", "context_net_dec"};
 
 
 namespace ufvc {
@@ -140,7 +149,9 @@ inline bool geom(const ufvc_ctx* c, int H, int W, Geom& g) {
 }
 
 // Header flag bits of the model structure a stream needs.
-inline uint8_t header_flags(const ufvc_ctx* c) { return c->cfg.quadtree ? HDR_FLAG_QUADTREE : 0; }
+inline uint8_t header_flags(const ufvc_ctx* c) {
+  return (uint8_t)((c->cfg.quadtree ? HDR_FLAG_QUADTREE : 0) | (c->cfg.temporal ? HDR_FLAG_TEMPORAL : 0));
+}
 
 inline ConvArgs conv_args(int Hin, int Win, int Hout, int Wout, const Layer& L) {
   ConvArgs a{};
