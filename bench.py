@@ -260,20 +260,35 @@ def run_batch_c3(torch, ufvc, steps, seg_log2, seg_log2_z):
     if code != 0:
         raise RuntimeError(f"batch decode status {st}")
     torch.cuda.synchronize()
-    te = td = 0.0
-    for _ in range(steps):
-        t0 = time.perf_counter()
-        lens = batch.encode(enc_items)
-        t1 = time.perf_counter()
-        batch.decode(dec_items, graph=True, check=False)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        te += t1 - t0
-        td += t2 - t1
-    st, code = batch.sync_status()
-    if code != 0:
-        raise RuntimeError(f"batch decode status {st}")
     frames_total = sum(T for T, _, _ in spec)
+    per_policy = {}
+    for policy in (0, 1):
+        batch.set_policy(policy)
+        batch.encode(enc_items)                          # plans for this policy
+        batch.decode(dec_items, graph=True)
+        torch.cuda.synchronize()
+        te = td = 0.0
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            lens = batch.encode(enc_items)
+            t1 = time.perf_counter()
+            batch.decode(dec_items, graph=True, check=False)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            te += t1 - t0
+            td += t2 - t1
+        st, code = batch.sync_status()
+        if code != 0:
+            raise RuntimeError(f"batch decode status {st}")
+        bst = batch.stats()
+        per_policy[policy] = {"value": round(frames_total * steps / (te + td), 2),
+                              "enc_ms_per_batch": round(1e3 * te / steps, 3),
+                              "dec_ms_per_batch": round(1e3 * td / steps, 3),
+                              "conv_stages": int(bst["conv_stages"]),
+                              "conv_launches": int(bst["conv_launches"])}
+    best = max(per_policy, key=lambda k: per_policy[k]["value"])
+    te = per_policy[best]["enc_ms_per_batch"] * steps / 1e3
+    td = per_policy[best]["dec_ms_per_batch"] * steps / 1e3
     tuning = {f"{W}x{H}": {f"T{T}": models[T].tuning(H, W)["k1"] for T in (4, 8)}
               for _, W, H in C3_MIX}
     res = {"chunks": len(spec), "frames_per_batch": frames_total,
@@ -281,6 +296,9 @@ def run_batch_c3(torch, ufvc, steps, seg_log2, seg_log2_z):
            "enc_ms_per_batch": round(1e3 * te / steps, 3),
            "dec_ms_per_batch": round(1e3 * td / steps, 3), "steps": steps,
            "decode": "hipGraph replay", "k1_tile_per_bucket": tuning,
+           "launch_policy": {"chosen": "one launch per stage" if best == 1 else
+                             "one launch per tile configuration",
+                             "per_tile_configuration": per_policy[0], "one_per_stage": per_policy[1]},
            "mix": "16x832x480, 16x1280x720, 12x1920x1088, 4x3840x2160; T from {4,8} (seed 2)"}
     batch.close()
     for m in models.values():
@@ -322,6 +340,28 @@ def run_quadtree(torch, ufvc, chunks, H, W, steps, warmup, seg_log2, seg_log2_z,
                            "flop_per_side": fl}
     out["note"] = ("bf16 convs; partitions 1-3 refined by 3 float32 MFMA mean steps per side "
                    "(Sec. 3.4 quadtree means); same 1080p T=8 chunks and step as the headline")
+    return out
+
+
+def run_seg_sweep(torch, ufvc, weights, chunks, H, W, steps, warmup, lanes, sizes=(11, 12, 13, 14)):
+    """y segment size (symbols per rANS segment = 2^seg_log2) against speed
+    and stream size on the headline workload: per size, the y decode and
+    encode kernel times (HIP events, one chunk at a time), the stream bytes,
+    and the enc+dec rates one chunk at a time and with `lanes` in flight."""
+    out = {}
+    for sl in sizes:
+        r = run_codec(torch, ufvc, weights, "bf16", chunks, H, W, steps, warmup, sl, 10,
+                      profile=True, autotune=True)
+        rp = run_pipelined(torch, ufvc, weights, "bf16", chunks, H, W, steps, warmup, sl, 10,
+                           lanes=lanes)
+        T = chunks[0].shape[0]
+        st = r["stages"]
+        out[str(sl)] = {"y_segments": -(-((H + 15) // 16 * 2) * ((W + 15) // 16 * 2) * 128 // (1 << sl)),
+                        "rans_decode_y_us": round(1e3 * st["rans_decode_y"][0] / steps, 1),
+                        "rans_encode_us": round(1e3 * st["rans_encode"][0] / steps, 1),
+                        "bytes": r["bytes"],
+                        "sequential_fps": round(T * steps / r["seconds"], 1),
+                        "pipelined_fps": round(T * rp["steps"] / rp["seconds"], 1)}
     return out
 
 
@@ -485,13 +525,15 @@ def run_dc_block(torch, ufvc, h, w, C=128, reps=50):
                     "bf16 in and out; intensity 2 (6C + 9) / 4 FLOP per byte"}
 
 
-def run_fp8_c4(torch, ufvc, steps, seg_log2, seg_log2_z, n_chunks=16):
+def run_fp8_c4(torch, ufvc, steps, seg_log2, seg_log2_z, n_chunks=16, n_oracle=2):
     """16 chunks of 1920x1088, T = 8: analysis convs BF16, synthesis convs FP8
     E4M3 (per-output-channel weight scales), entropy params FP32, tables FP64
     on the GPU; encoded and decoded as one batch.  Reports throughput, the
-    bit-stream size against the FP32 path and PSNR against the source next to
-    the FP32 and BF16 paths (errors against the FP64 oracle are measured by
-    the full-size tests)."""
+    bit-stream size against the FP32 path, PSNR against the source next to
+    the FP32 and BF16 paths, and for the first n_oracle chunks the max abs
+    and PSNR of the FP8 and BF16 frames against the float64 oracle's
+    synthesis of the same y_hat (a bounded sample: about 5 s of host work per
+    chunk and precision)."""
     from synthetic import stand_in_weights, video_chunk
     T, H, W, C = 8, 1088, 1920, 128
     w = stand_in_weights(T, C)
@@ -502,11 +544,24 @@ def run_fp8_c4(torch, ufvc, steps, seg_log2, seg_log2_z, n_chunks=16):
               for p in ("bf16_fp8", "bf16", "fp32")}
     per = {p: [] for p in codecs}
     sizes = {p: [] for p in codecs}
+    vs_oracle = {p: [] for p in ("bf16_fp8", "bf16")}
+    from oracle import nets
     for p, c in codecs.items():
-        for fr in frames:
+        for k, fr in enumerate(frames):
             bs, n = c.encode(fr)
             sizes[p].append(n)
-            per[p].append(psnr_t(torch, fr, c.decode(bs, n, H, W)))
+            rec = c.decode(bs, n, H, W)
+            per[p].append(psnr_t(torch, fr, rec))
+            if p in vs_oracle and k < n_oracle:
+                # the float64 oracle's synthesis of this chunk's own y_hat
+                sym = c.buffer(ufvc.BUF_SYM, H, W).astype(np.float64)
+                mu = c.buffer(ufvc.BUF_PARAMS, H, W)[..., :C].astype(np.float64)
+                ref = nets.synthesis(np.transpose(sym - 32 + mu, (2, 0, 1)), w, T, H, W)
+                err = np.abs(rec.cpu().numpy().astype(np.float64) - ref)
+                mse = float(np.mean(err ** 2))
+                vs_oracle[p].append({"chunk": k, "max_abs": round(float(err.max()), 5),
+                                     "mean_abs": round(float(err.mean()), 6),
+                                     "psnr_db": round(10 * np.log10(1 / mse), 3)})
     batch = ufvc.Batch([codecs["bf16_fp8"]])
     outs = [torch.empty(codecs["bf16_fp8"].max_bitstream_bytes(H, W), dtype=torch.uint8,
                         device="cuda") for _ in frames]
@@ -557,6 +612,7 @@ def run_fp8_c4(torch, ufvc, steps, seg_log2, seg_log2_z, n_chunks=16):
            "bitstream_size_delta_vs_fp32": {"min": round(float(dsize.min()), 6),
                                             "max": round(float(dsize.max()), 6)},
            "per_chunk_psnr_db": {p: [round(x, 3) for x in v] for p, v in per.items()},
+           "vs_fp64_oracle": {"sample": f"chunks 0-{n_oracle - 1} of {len(frames)}", **vs_oracle},
            "one_chunk_synthesis_ms": one_chunk,
            "precision": "analysis bf16, synthesis fp8 e4m3 (d1 bf16), params fp32, tables fp64"}
     batch.close()
@@ -569,11 +625,14 @@ C5_MIX = [(21, 832, 480), (21, 1280, 720), (16, 1920, 1088), (6, 3840, 2160)]
 
 
 def run_serving(torch, ufvc, prec, mix, seconds, rate, seg_log2, seg_log2_z, seed=5,
-                lanes=2, max_batch=8):
+                lanes=2, max_batch=8, small_pixels=1920 * 1088):
     """Open-loop serving: 64 streams (resolution mix), Poisson arrivals of
     `rate` chunk requests/s for `seconds`, 70% decode / 30% encode, T = 8,
     C = 128.  Inputs and bit-streams are resident in HBM before the clock
-    starts; the server admits requests within a 64 GiB footprint."""
+    starts; the server admits requests within a 64 GiB footprint; lane 0
+    prefers requests of at most 1920x1088.  Its frames/s is bound by the
+    arrival rate; `capacity` is a closed-loop run of the same request mix
+    (all submitted at once) that measures what the server sustains."""
     import threading
     from synthetic import stand_in_weights, video_chunk
     T, C = 8, 128
@@ -590,7 +649,8 @@ def run_serving(torch, ufvc, prec, mix, seconds, rate, seg_log2, seg_log2_z, see
     enc_out = [torch.empty(codec.max_bitstream_bytes(H, W), dtype=torch.uint8, device="cuda")
                for (W, H) in streams]
     dec_out = [torch.empty((T, 3, H, W), dtype=torch.float32, device="cuda") for (W, H) in streams]
-    srv = ufvc.Server([codec], hbm_budget=64 << 30, lanes=lanes, max_batch=max_batch, graph=True)
+    srv = ufvc.Server([codec], hbm_budget=64 << 30, lanes=lanes, max_batch=max_batch, graph=True,
+                      small_pixels=small_pixels)
 
     def submit(i, kind):
         W, H = streams[i]
@@ -616,6 +676,7 @@ def run_serving(torch, ufvc, prec, mix, seconds, rate, seg_log2, seg_log2_z, see
             comps.extend(srv.poll(256, 200))
 
     th = threading.Thread(target=poller)
+    st0 = srv.stats()
     th.start()
     t0 = time.perf_counter()
     for k in range(n_req):
@@ -625,6 +686,16 @@ def run_serving(torch, ufvc, prec, mix, seconds, rate, seg_log2, seg_log2_z, see
         submit(int(who[k]), kinds[k])
     th.join()
     st = srv.stats()
+    # closed loop: the same number of requests, all queued at once
+    n_cap = min(n_req, 600)
+    t_c = time.perf_counter()
+    for k in range(n_cap):
+        submit(int(who[k]), kinds[k])
+    got = 0
+    while got < n_cap:
+        got += len(srv.poll(256, 200))
+    cap_s = time.perf_counter() - t_c
+    st_cap = srv.stats()
     srv.close()
     codec.close()
     bad = sum(1 for c in comps if c["status"] != 0)
@@ -635,11 +706,27 @@ def run_serving(torch, ufvc, prec, mix, seconds, rate, seg_log2, seg_log2_z, see
     last = max(c["t_done_us"] for c in comps)
     pix = {i: streams[i][0] * streams[i][1] for i in range(len(streams))}
     frames = T * n_req
+    by_res = {}
+    for (W, H) in res:
+        lr = np.array([(c["t_done_us"] - c["t_submit_us"]) / 1e3 for c in comps
+                       if streams[int(c["tag"])] == (W, H)])
+        if lr.size:
+            by_res[f"{W}x{H}"] = {"requests": int(lr.size), "p50": round(float(np.percentile(lr, 50)), 3),
+                                  "p99": round(float(np.percentile(lr, 99)), 3),
+                                  "max": round(float(lr.max()), 3)}
     return {"precision": prec, "requests": n_req, "seconds": seconds, "rate_req_s": rate,
             "value": round(frames / ((last - first) / 1e6), 2), "unit": "frames/s",
+            "value_note": "arrival-bound: the open-loop rate times T, not the server's capacity",
+            "capacity": {"value": round(T * n_cap / cap_s, 2), "unit": "frames/s",
+                         "requests": n_cap, "mean_batch": round(
+                             (st_cap["completed"] - st["completed"]) /
+                             max(1, st_cap["batches"] - st["batches"]), 2)},
             "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                            "p99": round(float(np.percentile(lat, 99)), 3),
                            "max": round(float(lat.max()), 3)},
+            "latency_ms_by_resolution": by_res,
+            "plan_builds_in_timed_window": int(st["plans_built"] - st0["plans_built"]),
+            "small_first_lane_pixels": small_pixels,
             "decode_share": round(float(np.mean(kinds == "dec")), 3),
             "mean_batch": round(float(np.mean([c["batch_size"] for c in comps])), 2),
             "batches": int(st["batches"]), "lanes": lanes, "max_batch": max_batch,
@@ -669,7 +756,62 @@ def psnr_t(torch, a, b):
     return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
 
 
-def cpu_baseline(T, H, W, C, n_chunks=3):
+def precision_report(torch, ufvc, weights, chunk_np, H, W, seg_log2, seg_log2_z):
+    """Every precision's error against the float64 oracle on chunk 0 of the
+    headline workload (T=8, 1080p, C=128), each stage on the GPU's own input:
+    y against the oracle's analysis of the frames; scale indices and symbols
+    against the oracle's entropy model of the GPU's z_hat and y, and against
+    the FP32 GPU path; frames against the oracle synthesis of the GPU's own
+    y_hat (what the decoder decodes), as max abs and PSNR; and the BF16 / FP8
+    reconstruction against the FP32 one directly.  About 20 s of host float64
+    work."""
+    from oracle import entropy, nets
+    T, C = chunk_np.shape[0], 128
+    o_y = np.transpose(nets.analysis(chunk_np, weights), (1, 2, 0))
+    h, w = o_y.shape[0], o_y.shape[1]
+    res, gpu = {}, {}
+    frames = torch.from_numpy(chunk_np).cuda()
+    for p in ("fp32", "bf16", "bf16_fp8"):
+        c = ufvc.Codec(T, C, weights, precision=p, seg_log2=seg_log2, seg_log2_z=seg_log2_z,
+                       model_tag=0x0800_1080, autotune=True)
+        bs, n = c.encode(frames)
+        g_y = c.buffer(ufvc.BUF_Y, H, W).astype(np.float64)
+        g_z = c.buffer(ufvc.BUF_ZSYM, H, W).astype(np.float64) - 32
+        g_P = c.buffer(ufvc.BUF_PARAMS, H, W).astype(np.float64)
+        g_idx = c.buffer(ufvc.BUF_IDX, H, W)
+        g_sym = c.buffer(ufvc.BUF_SYM, H, W)
+        rec = c.decode(bs, n, H, W).cpu().numpy().astype(np.float64)
+        c.close()
+        mu, sigma = nets.params(np.transpose(g_z, (2, 0, 1)), weights, h, w)
+        o_idx = np.transpose(entropy.scale_index(sigma), (1, 2, 0))
+        o_sym = np.clip(np.rint(g_y - np.transpose(mu, (1, 2, 0))), -32, 32) + 32
+        y_hat = np.transpose(g_sym.astype(np.float64) - 32 + g_P[..., :C], (2, 0, 1))
+        ref = nets.synthesis(y_hat, weights, T, H, W)
+        err = np.abs(rec - ref)
+        mse = float(np.mean(err ** 2))
+        gpu[p] = (g_idx, g_sym, rec, n)
+        res[p] = {"y_max_abs_vs_oracle": float(np.abs(g_y - o_y).max()),
+                  "y_max_abs_over_max_y": float(np.abs(g_y - o_y).max() / np.abs(o_y).max()),
+                  "idx_agree_oracle": float(np.mean(g_idx == o_idx)),
+                  "sym_agree_oracle": float(np.mean(g_sym == o_sym)),
+                  "frames_vs_oracle_synthesis": {"max_abs": float(err.max()),
+                                                 "psnr_db": round(10 * np.log10(1 / mse), 3)
+                                                 if mse > 0 else None},
+                  "bytes": int(n)}
+    for p in ("bf16", "bf16_fp8"):
+        i32, s32, r32, n32 = gpu["fp32"]
+        ip, sp_, rp, npb = gpu[p]
+        mse = float(np.mean((rp - r32) ** 2))
+        res[p]["idx_agree_fp32"] = float(np.mean(ip == i32))
+        res[p]["sym_agree_fp32"] = float(np.mean(sp_ == s32))
+        res[p]["recon_psnr_vs_fp32_db"] = round(10 * np.log10(1 / mse), 3) if mse > 0 else None
+        res[p]["bytes_vs_fp32"] = round(npb / n32 - 1, 6)
+    res["note"] = ("chunk 0 of the 1080p T=8 workload; every stage on the GPU's own input; "
+                   "frames against the float64 oracle's synthesis of the GPU's own y_hat")
+    return res
+
+
+def cpu_baseline(T, H, W, C, n_chunks=3, seg_log2=13, seg_log2_z=10):
     """The oracle, untouched, on `n_chunks` full chunks of the same workload
     (about 10-30 s of host work)."""
     from oracle import codec as ocodec
@@ -683,12 +825,14 @@ def cpu_baseline(T, H, W, C, n_chunks=3):
     frames = [video_chunk(T, H, W, 16, seed=1, chunk_id=k) for k in range(n_chunks)]
     t0 = time.perf_counter()
     for fr in frames:
-        bs, _ = ocodec.encode_chunk(fr, w, seg_log2=15, seg_log2_z=11, model_tag=0x0800_1080)
+        bs, _ = ocodec.encode_chunk(fr, w, seg_log2=seg_log2, seg_log2_z=seg_log2_z,
+                                    model_tag=0x0800_1080)
         ocodec.decode_chunk(bs, w)
     dt = time.perf_counter() - t0
     return {"value": T * n_chunks / dt, "unit": "frames/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n_chunks} {W}x{H} T={T} chunks (generator chunks 0-{n_chunks - 1}): "
-                      f"float64 oracle encode + decode, {dt:.1f} s; BLAS threads {threads}, "
+                      f"float64 oracle encode + decode at segment sizes 2^{seg_log2} / "
+                      f"2^{seg_log2_z} (the GPU line's), {dt:.1f} s; BLAS threads {threads}, "
                       f"rANS loop single-threaded, host cpus {len(os.sched_getaffinity(0))}"}
 
 
@@ -712,6 +856,10 @@ def main():
     ap.add_argument("--no-color", action="store_true", help="skip the format-conversion leg")
     ap.add_argument("--no-dcblock", action="store_true", help="skip the DC-block leg")
     ap.add_argument("--no-temporal", action="store_true", help="skip the temporal-context leg")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the per-precision errors against the oracle (about 20 s of host work)")
+    ap.add_argument("--seg-sweep", action="store_true",
+                    help="add the y segment-size sweep (2^11 .. 2^14) to the line")
     ap.add_argument("--lanes", type=int, default=2, help="chunks in flight for the headline run")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="finish with three plain device copies of this many MB (counter scaling)")
@@ -859,6 +1007,14 @@ def main():
     if not args.no_color:
         log("bench: format conversions (BT.709 RGB, 4:2:0)")
         result["color"] = run_color(torch, ufvc, chunks, H, W, 20, args.seg_log2, args.seg_log2_z)
+    if not args.no_precision:
+        log("bench: per-precision errors against the oracle (chunk 0)")
+        result["precision_vs_oracle"] = precision_report(torch, ufvc, weights, chunks_np[0], H, W,
+                                                         args.seg_log2, args.seg_log2_z)
+    if args.seg_sweep:
+        log("bench: segment-size sweep")
+        result["seg_sweep"] = run_seg_sweep(torch, ufvc, weights, chunks, H, W, args.steps,
+                                            args.warmup, args.lanes)
     if not args.no_temporal:
         log("bench: temporal context")
         result["temporal"] = run_temporal(torch, ufvc, chunks, H, W, args.steps, args.warmup,
@@ -884,7 +1040,8 @@ def main():
         result["serving"] = serving
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        result["cpu_baseline"] = cpu_baseline(T, H, W, C)
+        result["cpu_baseline"] = cpu_baseline(T, H, W, C, seg_log2=args.seg_log2,
+                                              seg_log2_z=args.seg_log2_z)
     if args.calib_copy_mb:
         # plain copies of a known size, for scaling hardware byte counters
         n = args.calib_copy_mb * (1 << 20) // 4

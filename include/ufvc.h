@@ -339,6 +339,19 @@ int ufvc_encode_batch(ufvc_batch* b, ufvc_chunk* chunks, int n, void* stream);
 int ufvc_decode_batch(ufvc_batch* b, ufvc_chunk* chunks, int n, int use_graph, void* stream);
 /* Synchronises `stream` and sets each chunk's decode status. */
 int ufvc_batch_sync_status(ufvc_batch* b, ufvc_chunk* chunks, int n, void* stream);
+/* Launch policy of the batch's conv stages.  0: each chunk keeps its size
+ * bucket's tuned tile configuration, one launch per configuration present
+ * in a stage.  1 (default): one launch per stage, every chunk of the batch on
+ * the configuration of the chunk with the most work in that stage (when all
+ * chunks support it; else as 0).  Results are bitwise identical either way
+ * (configurations never change them).  Drops the cached plans (after a
+ * device sync).  INVAL for other values. */
+int ufvc_batch_set_policy(ufvc_batch* b, int policy);
+/* stats[0] plans built, [1] plans evicted (the cache keeps the 32 most
+ * recently used compositions), [2] plans cached, [3] conv stages and [4]
+ * conv launches of the most recently used plan (encode and decode stages
+ * together), [5] the launch policy.  n >= 6. */
+int ufvc_batch_stats(ufvc_batch* b, uint64_t* stats, int n);
 
 /* ---- Request server: continuous batching over the batch executor ----
  * Requests (encode or decode of one chunk) arrive from any thread at any
@@ -363,10 +376,16 @@ int ufvc_batch_sync_status(ufvc_batch* b, ufvc_chunk* chunks, int n, void* strea
  * had finished. */
 typedef struct ufvc_server ufvc_server;
 typedef struct {
-  size_t hbm_budget;    /* bytes; 0 selects 64 GiB */
+  size_t hbm_budget;    /* bytes; 0 selects 64 GiB.  Each lane's working arena
+                           (hbm_budget / lanes) is allocated at creation, so
+                           nothing grows on the request path */
   int lanes;            /* 1..8 concurrent batches */
   int max_batch;        /* 1..64 chunks per batch */
   int use_graph;        /* decode batches replay a captured hipGraph */
+  int small_pixels;     /* 0: batches formed by arrival only.  > 0 (with two or
+                           more lanes): lane 0 prefers requests of at most this
+                           many pixels per frame (the oldest such, batched only
+                           with such), so a large request cannot hold every lane */
 } ufvc_server_config;
 enum { UFVC_REQ_ENCODE = 0, UFVC_REQ_DECODE = 1 };
 typedef struct {
@@ -399,7 +418,9 @@ int ufvc_server_submit(ufvc_server* s, const ufvc_request* req, uint64_t* ticket
  * first; returns their number (or a negative status). */
 int ufvc_server_poll(ufvc_server* s, ufvc_completion* out, int max, int timeout_ms);
 /* stats[0] requests queued, [1] in flight, [2] completed, [3] batches run,
- * [4] peak admitted footprint (bytes), [5] HBM budget (bytes). */
+ * [4] peak admitted footprint (bytes), [5] HBM budget (bytes), [6] batch
+ * plans built so far (all lanes; a plan is built for each new batch
+ * composition, cached up to 32 per lane), [7] lane arena bytes allocated. */
 int ufvc_server_stats(ufvc_server* s, uint64_t* stats, int n);
 /* Finishes every queued and in-flight request, then frees the server
  * (unpolled completions are dropped). */

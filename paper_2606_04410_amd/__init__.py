@@ -52,7 +52,8 @@ class _Chunk(ctypes.Structure):
 
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("lanes", ctypes.c_int),
-                ("max_batch", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("max_batch", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("small_pixels", ctypes.c_int)]
 
 
 class _Request(ctypes.Structure):
@@ -111,6 +112,8 @@ def _load():
         "ufvc_encode_batch": (I, [P, P, I, P]),
         "ufvc_decode_batch": (I, [P, P, I, I, P]),
         "ufvc_batch_sync_status": (I, [P, P, I, P]),
+        "ufvc_batch_set_policy": (I, [P, I]),
+        "ufvc_batch_stats": (I, [P, P, I]),
         "ufvc_server_create": (I, [P, I, ctypes.POINTER(_ServerConfig), ctypes.POINTER(P)]),
         "ufvc_server_submit": (I, [P, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]),
         "ufvc_server_poll": (I, [P, P, I, I]),
@@ -138,6 +141,7 @@ EXPORTS = ("ufvc_weight_count", "ufvc_create", "ufvc_destroy", "ufvc_max_bitstre
            "ufvc_force_tile_config", "ufvc_convert_frames", "ufvc_dcblock_create",
            "ufvc_dcblock_destroy", "ufvc_dcblock_run", "ufvc_batch_create",
            "ufvc_batch_destroy", "ufvc_encode_batch", "ufvc_decode_batch", "ufvc_batch_sync_status",
+           "ufvc_batch_set_policy", "ufvc_batch_stats",
            "ufvc_server_create", "ufvc_server_submit", "ufvc_server_poll", "ufvc_server_stats",
            "ufvc_server_destroy")
 REQ_ENCODE, REQ_DECODE = 0, 1
@@ -538,6 +542,17 @@ class Batch:
             return self.sync_status(stream)
         return None
 
+    def set_policy(self, policy: int):
+        """0: one launch per tile configuration in a stage; 1: one launch per
+        stage (drops cached plans)."""
+        _check(lib.ufvc_batch_set_policy(self._h, int(policy)), "ufvc_batch_set_policy")
+
+    def stats(self):
+        v = (ctypes.c_uint64 * 6)()
+        _check(lib.ufvc_batch_stats(self._h, v, 6), "ufvc_batch_stats")
+        return dict(plans_built=v[0], plans_evicted=v[1], plans_cached=v[2], conv_stages=v[3],
+                    conv_launches=v[4], policy=v[5])
+
     def sync_status(self, stream=None):
         arr = self._last
         code = lib.ufvc_batch_sync_status(self._h, arr, len(arr), _stream(stream))
@@ -550,10 +565,10 @@ class Server:
     caller keeps alive until their completion is polled."""
 
     def __init__(self, codecs, hbm_budget: int = 0, lanes: int = 2, max_batch: int = 8,
-                 graph: bool = True):
+                 graph: bool = True, small_pixels: int = 0):
         self.codecs = list(codecs)
         arr = (ctypes.c_void_p * len(self.codecs))(*[c._h.value for c in self.codecs])
-        cfg = _ServerConfig(hbm_budget, lanes, max_batch, 1 if graph else 0)
+        cfg = _ServerConfig(hbm_budget, lanes, max_batch, 1 if graph else 0, small_pixels)
         h = ctypes.c_void_p()
         _check(lib.ufvc_server_create(arr, len(self.codecs), ctypes.byref(cfg), ctypes.byref(h)),
                "ufvc_server_create")
@@ -592,10 +607,10 @@ class Server:
         return out
 
     def stats(self):
-        v = (ctypes.c_uint64 * 6)()
-        _check(lib.ufvc_server_stats(self._h, v, 6), "ufvc_server_stats")
+        v = (ctypes.c_uint64 * 8)()
+        _check(lib.ufvc_server_stats(self._h, v, 8), "ufvc_server_stats")
         return dict(queued=v[0], in_flight=v[1], completed=v[2], batches=v[3],
-                    peak_footprint=v[4], budget=v[5])
+                    peak_footprint=v[4], budget=v[5], plans_built=v[6], arena_bytes=v[7])
 
     def close(self):
         if getattr(self, "_h", None):

@@ -234,20 +234,32 @@ static int upload_hyper_layer(Layer& L, const float* W, int cout, int cin) {
   return UFVC_OK;
 }
 
-// Mean-step weights for mean_step_kernel: three OIHW float32 C x C layers
-// to [step][tap][C / 4][C][4] (four consecutive input channels per 16 bytes).
+// Mean-step weights for mean_step_kernel: three OIHW float32 C x C layers,
+// each weight split exactly into three bf16 parts h + m + l (as for the
+// entropy-parameter conv), to [step][tap][part][C / 8][C][8] bf16 (eight
+// consecutive input channels of one output channel per 16 bytes).
 static int upload_mean_layers(ufvc_ctx* c, const float* W, int C) {
-  const size_t per = (size_t)9 * C * C;
-  std::vector<float> pk(3 * per);
+  const size_t per_in = (size_t)9 * C * C;           // float32 weights per step
+  const size_t per = 3 * per_in;                     // bf16 values per step (3 parts)
+  std::vector<__bf16> pk(3 * per);
   for (int k = 0; k < 3; ++k)
-    for (int tap = 0; tap < 9; ++tap)
+    for (int n = 0; n < C; ++n)
       for (int ci = 0; ci < C; ++ci)
-        for (int n = 0; n < C; ++n)
-          pk[k * per + (((size_t)tap * (C / 4) + ci / 4) * C + n) * 4 + ci % 4] =
-              W[k * per + ((size_t)n * C + ci) * 9 + tap];
-  if (hipMalloc(&c->mw, pk.size() * 4) != hipSuccess) return UFVC_E_NOMEM;
-  CK(hipMemcpy(c->mw, pk.data(), pk.size() * 4, hipMemcpyHostToDevice));
-  c->mw_kstride = per * 4;
+        for (int tap = 0; tap < 9; ++tap) {
+          const float w = W[k * per_in + ((size_t)n * C + ci) * 9 + tap];
+          const float h = (float)(__bf16)w;
+          const float r1 = w - h;
+          const float m = (float)(__bf16)r1;
+          const float r2 = r1 - m;
+          const float l = (float)(__bf16)r2;
+          if (l != r2 || (double)h + (double)m + (double)l != (double)w) return UFVC_E_UNSUPPORTED;
+          const float v[3] = {h, m, l};
+          for (int p = 0; p < 3; ++p)
+            pk[k * per + ((((size_t)tap * 3 + p) * (C / 8) + ci / 8) * C + n) * 8 + ci % 8] = (__bf16)v[p];
+        }
+  if (hipMalloc(&c->mw, pk.size() * sizeof(__bf16)) != hipSuccess) return UFVC_E_NOMEM;
+  CK(hipMemcpy(c->mw, pk.data(), pk.size() * sizeof(__bf16), hipMemcpyHostToDevice));
+  c->mw_kstride = per * sizeof(__bf16);
   return UFVC_OK;
 }
 

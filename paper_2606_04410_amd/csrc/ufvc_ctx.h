@@ -55,8 +55,8 @@ struct ufvc_ctx {
   int device = 0;
   Tables tab{};
   Layer a1, a2, a3, h, p, d1, d2, d3, k1, k2, k3;
-  // quadtree progressive means: steps 1..3, each [tap][C / 4][C][4] float32
-  float* mw = nullptr;
+  // quadtree progressive means: steps 1..3, each [tap][part][C / 8][C][8] bf16
+  __bf16* mw = nullptr;
   size_t mw_kstride = 0;
   // temporal context: context network c1, c2 and the context inputs of a1,
   // of the entropy parameters (split into three bf16 parts in the bf16
@@ -175,3 +175,8 @@ inline ConvArgs conv_args(int Hin, int Win, int Hout, int Wout, const Layer& L) 
 int batch_set_arena_cap(ufvc_batch* b, size_t cap);
 // Arena bytes one chunk of model `c` at H x W takes in a batch (0: invalid size).
 size_t batch_chunk_footprint(ufvc_ctx* c, int H, int W);
+// Shared-arena mode: allocates the whole capped arena now, so it never grows
+// (or drops plans) on a request path.
+int batch_reserve_arena(ufvc_batch* b);
+// Plans built so far by a batch object.
+uint64_t batch_plans_built(const ufvc_batch* b);

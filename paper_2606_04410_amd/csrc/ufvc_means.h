@@ -13,9 +13,9 @@ struct MeanArgs {
   float* P;             // [h][w][2C]: mu in the first C channels, refined in place on partition k
   const float* y;       // encoder: y [h][w][C] (partition k is quantised); decoder: null
   uint8_t* sym_out;     // encoder: symbol output (may alias sym: different partitions)
-  const float* wpk;     // step weights [step 1..3][tap][C / 4][C][4] float32
+  const __bf16* wpk;    // step weights [step 1..3][tap][part h, m, l][C / 8][C][8] bf16
   size_t w_kstride;     // bytes per step
-  const float* wk;      // this step's weights (set by the launcher)
+  const __bf16* wk;     // this step's weights (set by the launcher)
 };
 
 // Step k (1..3) of the progressive means: reads the symbols of partitions

@@ -20,15 +20,19 @@
 // channels, against 9 C / 16 for the full conv.
 //
 // One wave per unit of 16 output positions of one phase row x 16 output
-// channels on v_mfma_f32_16x16x4f32, as in the hyper conv: lane l holds
-// position l % 16 (A row) and output channel l % 16 (B column); lane group
-// gq = l / 16 holds input channels 4gq..4gq+3 of each 16-channel chunk, and
-// MFMA j of a chunk takes channel 4gq + j.  K order: tap, active group
-// (ascending partition), chunk, j, then the MFMA's own sum: fixed, so the
-// encoder and the decoder compute the same float32 means bit for bit.
-// Residuals are small integers (exact in float32); operands are read
+// channels on v_mfma_f32_16x16x32_bf16: lane l holds position l % 16 (A row)
+// and output channel l % 16 (B column); lane group gq = l / 16 holds input
+// channels 8gq..8gq+7 of each 32-channel chunk.  The residuals (-32..32) are
+// exact in bf16, and every float32 weight is the exact sum of three bf16
+// parts (h + m + l, checked when the model is created), so each chunk runs
+// three MFMAs on the same residuals, one per part: every product is exact
+// and the sums are float32, as in a float32 conv.  K order: tap, chunk
+// (ascending partition at C = 128), part, then the MFMA's own sum: fixed,
+// so the encoder and the decoder compute the same means bit for bit.  Chunks
+// of later partitions only are not visited; in a chunk that straddles two
+// groups (C = 64) the lanes of a later group feed zeros.  Operands are read
 // straight from device memory (the symbols are 4 MB at 1080p, L2-resident),
-// nine K steps ahead of the multiplications.
+// six K steps ahead of the multiplications.
 #include "ufvc_common.h"
 #include "ufvc_means.h"
 
@@ -38,30 +42,42 @@ typedef float mv4f __attribute__((ext_vector_type(4)));
 
 __constant__ int kPhaseRank[4] = {0, 2, 3, 1};
 
-template <int K, int NCG>
+typedef __bf16 mbf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int mv4u __attribute__((ext_vector_type(4)));
+typedef unsigned int mv2u __attribute__((ext_vector_type(2)));
+
+// NC: 32-channel chunks of C.  Returns the 16 x 16 block: acc[r] is position
+// 4 gq + r of the unit, output channel n.  At C = 128 a chunk is one channel
+// group, so only the K groups of earlier partitions are visited (9 K steps);
+// at C = 64 a chunk holds two groups, every chunk is visited and lanes of a
+// later group feed zeros.
+template <int K, int NC>
 __device__ __forceinline__ mv4f mean_mac(const MeanArgs& a, int qy, int qx, int vo, int uo, int gq,
-                                         const float* __restrict__ wl) {
-  // NCG: 16-channel chunks per channel group (C / 64); loads run D K steps
-  // ahead of the multiplications
-  constexpr int NS = 9 * K * NCG, D = 9;
+                                         const __bf16* __restrict__ wl) {
+  constexpr bool ONE_GROUP = NC == 4;                    // C = 128: 32 channels per group
+  constexpr int NS = ONE_GROUP ? 9 * K : 9 * NC, D = 6;
   const int C = a.C;
   const int cg = C / 4;
-  mv4f vb[NS];
-  uint32_t va[NS];
-  bool ok[NS];
+  mv2u va[NS];
+  mv4u vb[NS][3];
+  bool ok[NS], act[NS];
   auto load = [&](int s) {
-    const int tap = s / (K * NCG);
-    const int m = (s / NCG) % K;       // m-th active group: partition m of this tap's input phase
-    const int cc = s % NCG;
+    const int tap = ONE_GROUP ? s / K : s / NC;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
     const int iy = 2 * vo + qy + dy, ix = 2 * uo + qx + dx;
     const int rank = kPhaseRank[2 * ((qy + dy) & 1) + ((qx + dx) & 1)];
-    const int grp = (m - rank) & 3;
-    const int c0 = grp * cg + cc * 16 + 4 * gq;
-    ok[s] = uo < a.wo && iy >= 0 && ix >= 0 && iy < a.h && ix < a.w;
+    // ONE_GROUP: the (s % K)-th earlier partition's group is chunk (m - rank) & 3
+    const int ch = ONE_GROUP ? (((s % K) - rank) & 3) : s % NC;
+    const int c0 = ch * 32 + 8 * gq;                    // this lane's 8 input channels
+    const int part = (rank + c0 / cg) & 3;              // their partition at this tap
+    ok[s] = uo < a.wo && iy >= 0 && ix >= 0 && iy < a.h && ix < a.w && part < K;
+    const int p_first = (rank + (ch * 32) / cg) & 3, p_last = (rank + (ch * 32 + 31) / cg) & 3;
+    act[s] = ONE_GROUP || p_first < K || p_last < K;
     const int cy = min(max(iy, 0), a.h - 1), cx = min(max(ix, 0), a.w - 1);
-    va[s] = ldg(reinterpret_cast<const uint32_t*>(a.sym + ((long)cy * a.w + cx) * C + c0));
-    vb[s] = ldg(reinterpret_cast<const mv4f*>(wl + ((long)tap * (C / 4) + c0 / 4) * C * 4));
+    va[s] = ldg(reinterpret_cast<const mv2u*>(a.sym + ((long)cy * a.w + cx) * C + c0));
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      vb[s][p] = ldg(reinterpret_cast<const mv4u*>(wl + (((long)(tap * 3 + p) * (C / 8) + c0 / 8) * C) * 8));
   };
 #pragma unroll
   for (int s = 0; s < D && s < NS; ++s) load(s);
@@ -71,18 +87,22 @@ __device__ __forceinline__ mv4f mean_mac(const MeanArgs& a, int qy, int qx, int 
     if (s + D < NS) load(s + D);
     // keep the prefetch ahead of this step's multiplications
     __builtin_amdgcn_sched_barrier(0);
-    const uint32_t r = ok[s] ? va[s] : 0x20202020u;   // symbol 32 = residual 0
-    const float r0 = (float)(int)(r & 0xFFu) - 32.f, r1 = (float)(int)((r >> 8) & 0xFFu) - 32.f;
-    const float r2 = (float)(int)((r >> 16) & 0xFFu) - 32.f, r3 = (float)(int)(r >> 24) - 32.f;
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(r0, vb[s].x, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(r1, vb[s].y, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(r2, vb[s].z, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(r3, vb[s].w, acc, 0, 0, 0);
+    if (!act[s]) continue;
+    mbf16x8 r;
+    const mv2u v = ok[s] ? va[s] : mv2u{0x20202020u, 0x20202020u};   // symbol 32 = residual 0
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      r[j] = (__bf16)((float)(int)((v.x >> (8 * j)) & 0xFFu) - 32.f);
+      r[4 + j] = (__bf16)((float)(int)((v.y >> (8 * j)) & 0xFFu) - 32.f);
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r, __builtin_bit_cast(mbf16x8, vb[s][p]), acc, 0, 0, 0);
   }
   return acc;
 }
 
-template <int K, int NCG>
+template <int K, int NC>
 __global__ void __launch_bounds__(64) mean_step_kernel(MeanArgs a) {
   // grid: x = XCD-banded unit of (phase, phase row, 16 columns), y = 16-channel tile
   const int units_x = (a.wo + 15) / 16;
@@ -100,8 +120,8 @@ __global__ void __launch_bounds__(64) mean_step_kernel(MeanArgs a) {
   const int cg = a.C / 4;
   const int gout = (K - kPhaseRank[q]) & 3;
   const int n = gout * cg + blockIdx.y * 16 + (lane & 15);
-  const float* __restrict__ wl = a.wk + (long)n * 4;
-  const mv4f acc = mean_mac<K, NCG>(a, qy, qx, vo, uo0 + (lane & 15), gq, wl);
+  const __bf16* __restrict__ wl = a.wk + (long)n * 8;
+  const mv4f acc = mean_mac<K, NC>(a, qy, qx, vo, uo0 + (lane & 15), gq, wl);
   // acc[r]: position 4 gq + r of the unit, output channel n
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -124,9 +144,9 @@ static hipError_t launch_step(const MeanArgs& a, hipStream_t s) {
   const int units = 4 * a.ho * ((a.wo + 15) / 16);
   const dim3 grid(((units + 7) / 8) * 8, a.C / 64, 1);
   if (a.C == 128)
-    hipLaunchKernelGGL((mean_step_kernel<K, 2>), grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL((mean_step_kernel<K, 4>), grid, dim3(64), 0, s, a);
   else
-    hipLaunchKernelGGL((mean_step_kernel<K, 1>), grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL((mean_step_kernel<K, 2>), grid, dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
@@ -136,8 +156,8 @@ hipError_t launch_mean_step(int k, const MeanArgs& a0, hipStream_t s) {
   MeanArgs a = a0;
   a.ho = a.h / 2;
   a.wo = a.w / 2;
-  a.wk = reinterpret_cast<const float*>(reinterpret_cast<const unsigned char*>(a0.wpk) +
-                                       (size_t)(k - 1) * a0.w_kstride);
+  a.wk = reinterpret_cast<const __bf16*>(reinterpret_cast<const unsigned char*>(a0.wpk) +
+                                        (size_t)(k - 1) * a0.w_kstride);
   switch (k) {
     case 1: return launch_step<1>(a, s);
     case 2: return launch_step<2>(a, s);

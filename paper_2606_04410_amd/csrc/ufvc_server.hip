@@ -58,15 +58,30 @@ namespace {
 
 constexpr size_t kDefaultBudget = 64ull << 30;
 
-// Forms the next batch for one lane (called with the lock held); empty when
-// nothing can be admitted now.
-std::vector<ufvc_server::Req> take_batch(ufvc_server* S) {
+// Forms the next batch for lane `li` (called with the lock held); empty when
+// nothing can be admitted now.  With small_pixels set (and two or more
+// lanes), lane 0 prefers small requests: it starts from the oldest request
+// of at most small_pixels per frame and batches only such requests, so a
+// large request at the head of the queue cannot hold every lane; when no
+// small request is queued it takes the oldest as the other lanes do.
+std::vector<ufvc_server::Req> take_batch(ufvc_server* S, int li) {
   std::vector<ufvc_server::Req> out;
   if (S->queue.empty()) return out;
-  const int kind = S->queue.front().r.kind;
+  const long small = S->cfg.small_pixels;
+  auto is_small = [&](const ufvc_server::Req& q) { return (long)q.r.H * q.r.W <= small; };
+  bool small_only = false;
+  auto head = S->queue.begin();
+  if (small > 0 && li == 0 && S->lanes.size() >= 2) {
+    auto f = std::find_if(S->queue.begin(), S->queue.end(), is_small);
+    if (f != S->queue.end()) {
+      head = f;
+      small_only = true;
+    }
+  }
+  const int kind = head->r.kind;
   size_t arena = 0, foot = 0;
-  for (auto it = S->queue.begin(); it != S->queue.end() && (int)out.size() < S->cfg.max_batch;) {
-    if (it->r.kind != kind) {
+  for (auto it = head; it != S->queue.end() && (int)out.size() < S->cfg.max_batch;) {
+    if (it->r.kind != kind || (small_only && !is_small(*it))) {
       ++it;
       continue;
     }
@@ -148,7 +163,7 @@ void lane_main(ufvc_server* S, int li) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
       for (;;) {
-        reqs = take_batch(S);
+        reqs = take_batch(S, li);
         if (!reqs.empty()) break;
         if (S->stopping && S->queue.empty()) return;
         S->cv_work.wait(lk);
@@ -178,7 +193,9 @@ int ufvc_server_create(ufvc_ctx* const* models, int n_models, const ufvc_server_
                        ufvc_server** out) {
   if (!models || n_models < 1 || !cfg || !out) return UFVC_E_INVAL;
   *out = nullptr;
-  if (cfg->lanes < 1 || cfg->lanes > 8 || cfg->max_batch < 1 || cfg->max_batch > 64) return UFVC_E_INVAL;
+  if (cfg->lanes < 1 || cfg->lanes > 8 || cfg->max_batch < 1 || cfg->max_batch > 64 ||
+      cfg->small_pixels < 0)
+    return UFVC_E_INVAL;
   ufvc_server* S = new (std::nothrow) ufvc_server();
   if (!S) return UFVC_E_NOMEM;
   S->models.assign(models, models + n_models);
@@ -196,6 +213,9 @@ int ufvc_server_create(ufvc_ctx* const* models, int n_models, const ufvc_server_
     }
     if ((rc = ufvc_batch_create(models, n_models, &L.batch)) != UFVC_OK) break;
     if ((rc = batch_set_arena_cap(L.batch, S->lane_cap)) != UFVC_OK) break;
+    // the lane's whole share now: no arena growth (nor plan loss) on the
+    // request path
+    if ((rc = batch_reserve_arena(L.batch)) != UFVC_OK) break;
   }
   if (rc != UFVC_OK) {
     for (auto& L : S->lanes) {
@@ -260,9 +280,11 @@ int ufvc_server_poll(ufvc_server* S, ufvc_completion* out, int max, int timeout_
 int ufvc_server_stats(ufvc_server* S, uint64_t* stats, int n) {
   if (!S || !stats || n < 1) return UFVC_E_INVAL;
   std::lock_guard<std::mutex> lk(S->mu);
-  const uint64_t v[6] = {S->queue.size(), S->n_in_flight, S->n_completed, S->n_batches,
-                         S->peak_bytes, S->cfg.hbm_budget};
-  for (int i = 0; i < n && i < 6; ++i) stats[i] = v[i];
+  uint64_t built = 0;
+  for (const auto& L : S->lanes) built += batch_plans_built(L.batch);
+  const uint64_t v[8] = {S->queue.size(), S->n_in_flight, S->n_completed, S->n_batches,
+                         S->peak_bytes, S->cfg.hbm_budget, built, S->lane_cap * S->lanes.size()};
+  for (int i = 0; i < n && i < 8; ++i) stats[i] = v[i];
   return UFVC_OK;
 }
 

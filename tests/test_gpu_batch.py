@@ -96,28 +96,64 @@ def test_batch_c3_buckets_at_c128(prec):
         ref_fr.append(models[m].decode(bs, n, H, W).clone())
     torch.cuda.synchronize()
     batch = u.Batch(models)
-    outs = [torch.zeros(models[m].max_bitstream_bytes(H, W), dtype=torch.uint8, device="cuda")
-            for (m, H, W) in shapes]
-    lens = batch.encode([(m, fr, o) for (m, _, _), fr, o in zip(shapes, frames, outs)])
-    for i in range(len(shapes)):
-        assert lens[i] == ref_bs[i].numel() and torch.equal(outs[i][:lens[i]], ref_bs[i]), i
-    rec = [torch.full((models[m].T, 3, H, W), -1.0, device="cuda") for (m, H, W) in shapes]
-    items = [(m, o, n, H, W, r) for (m, H, W), o, n, r in zip(shapes, outs, lens, rec)]
-    st, code = batch.decode(items, graph=False)
-    assert code == 0 and all(x == 0 for x in st)
-    for i in range(len(shapes)):
-        assert torch.equal(rec[i], ref_fr[i]), i
-    for rep in range(3):
-        for r in rec:
-            r.fill_(-1.0)
-        st, code = batch.decode(items, graph=True)
-        assert code == 0 and all(x == 0 for x in st), (rep, st)
+    launches = {}
+    # both launch policies: one launch per tile configuration, one per stage
+    for policy in (0, 1):
+        batch.set_policy(policy)
+        outs = [torch.zeros(models[m].max_bitstream_bytes(H, W), dtype=torch.uint8, device="cuda")
+                for (m, H, W) in shapes]
+        lens = batch.encode([(m, fr, o) for (m, _, _), fr, o in zip(shapes, frames, outs)])
         for i in range(len(shapes)):
-            assert torch.equal(rec[i], ref_fr[i]), (rep, i)
-        models[1].encode(frames[1])
-        torch.cuda.synchronize()
-    say(f"  {len(shapes)} chunks: batch == single, graph x3 == eager; "
+            assert lens[i] == ref_bs[i].numel() and torch.equal(outs[i][:lens[i]], ref_bs[i]), i
+        rec = [torch.full((models[m].T, 3, H, W), -1.0, device="cuda") for (m, H, W) in shapes]
+        items = [(m, o, n, H, W, r) for (m, H, W), o, n, r in zip(shapes, outs, lens, rec)]
+        st, code = batch.decode(items, graph=False)
+        assert code == 0 and all(x == 0 for x in st)
+        for i in range(len(shapes)):
+            assert torch.equal(rec[i], ref_fr[i]), i
+        for rep in range(3):
+            for r in rec:
+                r.fill_(-1.0)
+            st, code = batch.decode(items, graph=True)
+            assert code == 0 and all(x == 0 for x in st), (rep, st)
+            for i in range(len(shapes)):
+                assert torch.equal(rec[i], ref_fr[i]), (rep, i)
+            models[1].encode(frames[1])
+            torch.cuda.synchronize()
+        stt = batch.stats()
+        launches[policy] = (stt["conv_launches"], stt["conv_stages"])
+    assert launches[1][0] == launches[1][1]          # one launch per conv stage
+    assert launches[1][0] <= launches[0][0]
+    say(f"  {len(shapes)} chunks: batch == single, graph x3 == eager, both policies; "
+        f"conv launches / stages {launches}; "
         f"k1 tiles {[models[m].tuning(H, W)['k1'] for m, H, W in shapes]}")
     batch.close()
     for m in models:
         m.close()
+
+
+def test_batch_plan_cache_is_bounded():
+    """More compositions than the plan cache holds: the least recently used
+    plans are evicted, and an evicted composition is rebuilt with the same
+    results."""
+    import paper_2606_04410_amd as u
+    C = 64
+    m = u.Codec(1, C, stand_in_weights(1, C), precision="bf16", seg_log2=10, seg_log2_z=8,
+                model_tag=7, autotune=False)
+    widths = [16 + 8 * k for k in range(34)]
+    frames = {W: torch.from_numpy(video_chunk(1, 16, W, 3, seed=2, chunk_id=W)).cuda() for W in widths}
+    ref = {}
+    for W in widths:
+        bs, n = m.encode(frames[W])
+        ref[W] = bs[:n].cpu().numpy().tobytes()
+    batch = u.Batch([m])
+    for W in widths + widths[:2]:
+        out = torch.zeros(m.max_bitstream_bytes(16, W), dtype=torch.uint8, device="cuda")
+        (n,) = batch.encode([(0, frames[W], out)])
+        assert out[:n].cpu().numpy().tobytes() == ref[W], W
+    st = batch.stats()
+    say(f"  plan cache: {st}")
+    assert st["plans_cached"] <= 32 and st["plans_evicted"] >= 2 and st["plans_built"] == 36
+    assert st["policy"] == 1                          # one launch per stage by default
+    batch.close()
+    m.close()

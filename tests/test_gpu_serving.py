@@ -154,8 +154,8 @@ def test_server_c128_two_resolutions():
         ref_bs.append(bs[:n].clone())
         ref_fr.append(codec.decode(bs, n, H, W).clone())
     torch.cuda.synchronize()
-    say(f"server C=128: {len(sizes)} encodes + {len(sizes)} decodes, {sizes}")
-    srv = u.Server([codec], lanes=2, max_batch=4, graph=True)
+    say(f"server C=128: {len(sizes)} encodes + {len(sizes)} decodes, {sizes}, lane 0 small-first")
+    srv = u.Server([codec], lanes=2, max_batch=4, graph=True, small_pixels=832 * 480)
     enc_out = [torch.zeros(codec.max_bitstream_bytes(H, W), dtype=torch.uint8, device="cuda")
                for (H, W) in sizes]
     dec_out = [torch.full((T, 3, H, W), -1.0, device="cuda") for (H, W) in sizes]
@@ -180,6 +180,8 @@ def test_server_c128_two_resolutions():
             o.zero_()
         tickets = {}
     st = srv.stats()
+    say(f"  stats {st}")
     assert st["peak_footprint"] <= st["budget"]
+    assert st["arena_bytes"] == st["budget"]       # both lane arenas reserved up front
     srv.close()
     codec.close()
