@@ -24,9 +24,12 @@ BUF_Y, BUF_ZSYM, BUF_PARAMS, BUF_IDX, BUF_SYM, BUF_D2, BUF_F, BUF_K1, BUF_K2, BU
 Z_CHANNELS = 32
 # Segment sizes (log2 symbols per rANS segment) used unless a codec names its
 # own: the 1080p benchmark configuration.  Each segment carries 32 final lane
-# states (128 bytes), so smaller segments buy decoder parallelism (512 y
-# segments at 1080p) for about 2.5% of stream size against 0.9% at 2^15.
-DEFAULT_SEG_LOG2 = 13
+# states (128 bytes) and is one chain of 2^seg_log2 / 32 serial decode steps,
+# so smaller segments buy decoder parallelism for stream size.  Measured at
+# 1080p T=8 (bench.py --seg-sweep): 2^12 decodes y in 67 us against 120 us
+# at 2^13 for 1.6% more bytes; 2^11 is no faster (two decoder blocks per CU
+# already run every segment pair of 2^12 at once) and costs 4.8%.
+DEFAULT_SEG_LOG2 = 12
 DEFAULT_SEG_LOG2_Z = 10
 
 
