@@ -686,7 +686,12 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
 //     slices of MFMA work to land in;
 //   * the global address of every 16-byte chunk a lane fetches is computed
 //     once per tile; a slice only adds its offset.
-template <int ST, int TH, int TW, int WM, int WN, int FM, int FN, int NH>
+// Stages of one ring configuration.  A stage holds one slice of the halo
+// (HCH 16-byte chunks) or of the weights (WCH chunks), written by whole
+// 1 KB direct-to-LDS loads: IH (IW) loads per stage, load i issued by wave
+// i % NWAVES, so a wave issues at most NIH (NIW) of them; the tail of the
+// last load reads the zero chunk into the stage's padding.
+template <int TH, int TW, int WM, int WN, int FM, int FN, int NH, int NW>
 struct Ring {
   static constexpr int NWAVES = WM * WN;
   static constexpr int BN = WN * FN * 32;
@@ -694,76 +699,133 @@ struct Ring {
   static constexpr int HP = (TH + 2) * HW;
   static constexpr int HCH = HP * 2;           // 16-byte chunks of a halo slice
   static constexpr int WCH = 9 * BN * 2;       // 16-byte chunks of a weight slice
-  static constexpr int NIH = ((HCH + 63) / 64 + NWAVES - 1) / NWAVES;  // loads per wave
-  static constexpr int NIW = ((WCH + 63) / 64 + NWAVES - 1) / NWAVES;
-  static constexpr int HSTAGE = NIH * NWAVES * 1024;
-  static constexpr int WSTAGE = NIW * NWAVES * 1024;
-  static constexpr int LDS = NH * HSTAGE + 2 * WSTAGE;
-  static_assert(NH >= 3, "the wait count assumes the halo runs at least two slices ahead");
+  static constexpr int IH = (HCH + 63) / 64, IW = (WCH + 63) / 64;
+  static constexpr int NIH = (IH + NWAVES - 1) / NWAVES;
+  static constexpr int NIW = (IW + NWAVES - 1) / NWAVES;
+  static constexpr int HSTAGE = IH * 1024;
+  static constexpr int WSTAGE = IW * 1024;
+  static constexpr int LDS = NH * HSTAGE + NW * WSTAGE;
+  static_assert(NH >= 2 && NH <= 3 && NW >= 2 && NW <= 3, "one or two slices of lookahead per stream");
+  static_assert(NIH + NIW < 64, "vmcnt range");
 };
 
-template <int ST, int TH, int TW, int WM, int WN, int FM, int FN, int NH>
+// s_waitcnt vmcnt(n) for a wave-uniform n <= K (an immediate is needed, so
+// count down; waiting for fewer outstanding loads than allowed is safe).
+template <int K>
+__device__ __forceinline__ void wait_vmcnt_le(int n) {
+  if constexpr (K == 0) {
+    wait_vmcnt<0>();
+  } else {
+    if (n >= K) wait_vmcnt<K>();
+    else wait_vmcnt_le<K - 1>(n);
+  }
+}
+
+// Work items of the ring kernel are (tile, channel block, group).  A plain
+// launch gives each workgroup one item from its grid position.  The
+// persistent form launches as many workgroups as fit on the chip; each walks
+// its own list of items and keeps the slice pipeline running across item
+// boundaries: the first halo and weight slices of its next item are in
+// flight while it finishes (and stores) the current one.  Items are numbered
+// group-major, then tile, then channel block; each XCD takes a contiguous
+// band of them (workgroups are dispatched round-robin over the 8 XCDs), so
+// the workgroups resident on one XCD share input halos and weights in its L2.
+template <int ST, int TH, int TW, int WM, int WN, int FM, int FN, int NH, int NW, bool PERSIST>
 __global__ void __launch_bounds__(WM * WN * 64)
 conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __restrict__ work,
                     int nwork) {
-  using R = Ring<ST, TH, TW, WM, WN, FM, FN, NH>;
+  using R = Ring<TH, TW, WM, WN, FM, FN, NH, NW>;
   constexpr int BN = R::BN, HW = R::HW, HCH = R::HCH, WCH = R::WCH;
   constexpr int NIH = R::NIH, NIW = R::NIW, NWAVES = R::NWAVES;
+  constexpr int LH = NH - 1, LW = NW - 1;      // slices of lookahead: halo, weights
   static_assert(TH * TW == WM * FM * 32, "tile positions must match the wave grid");
   extern __shared__ __attribute__((aligned(16))) unsigned char sh[];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN;
   const int wn = wave - wm * WN;
+  // this wave's loads per stage: load j * NWAVES + wave exists for j < cH (cW)
+  const int cH = (R::IH - wave + NWAVES - 1) / NWAVES;
+  const int cW = (R::IW - wave + NWAVES - 1) / NWAVES;
+
   ConvArgs a;
-  int tile, n0, grp;
+  int first = 0, step = 1, count = 1;          // items first + k * step, k < count
+  int tile0 = 0, n00 = 0, grp0 = 0, nt = 1, ncb = 1;
   if (descs) {
     const int per = (nwork + 7) >> 3;
     const int wi = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (wi >= nwork) return;
     const int4 w = work[wi];
     a = descs[w.x];
-    tile = w.y;
-    n0 = w.z;
-    grp = w.w;
+    tile0 = w.y;
+    n00 = w.z;
+    grp0 = w.w;
   } else {
     a = a0;
-    const int nt = ((a.Hout + TH - 1) / TH) * ((a.Wout + TW - 1) / TW);
-    const int per = (nt + 7) >> 3;
-    tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (tile >= nt) return;
-    n0 = blockIdx.y * BN;
-    grp = blockIdx.z;
-  }
-  const int tiles_x = (a.Wout + TW - 1) / TW;
-  const int oy0 = (tile / tiles_x) * TH;
-  const int ox0 = (tile % tiles_x) * TW;
-  const int nslices = a.cin / 16;
-  const unsigned char* wbase = reinterpret_cast<const unsigned char*>(a.wpk) + grp * a.w_gstride;
-  const unsigned char* inb = reinterpret_cast<const unsigned char*>(a.in) + grp * a.in_goff * 2;
-
-  // Source of each chunk this lane fetches.  LDS chunk q of a stage holds
-  // row q / 2, half (q & 1) ^ swizzle(row), the layout the fragment reads
-  // expect; halo rows outside the input read the zero chunk (no slice step).
-  const unsigned char* hsrc[NIH];
-  int hstep[NIH];
-#pragma unroll
-  for (int j = 0; j < NIH; ++j) {
-    const int q = (j * NWAVES + wave) * 64 + lane;
-    hsrc[j] = kZeroChunk;
-    hstep[j] = 0;
-    if (q < HCH) {
-      const int row = q >> 1;
-      const int c = (q & 1) ^ ((row >> 3) & 1);
-      const int iy = oy0 - 1 + row / HW, ix = ox0 - 1 + row % HW;
-      if (iy >= 0 && ix >= 0 && iy < a.Hin && ix < a.Win) {
-        hsrc[j] = inb + (((long)iy * a.Win + ix) * a.in_pitch + c * 8) * 2;
-        hstep[j] = 32;
-      }
+    nt = ((a.Hout + TH - 1) / TH) * ((a.Wout + TW - 1) / TW);
+    if constexpr (PERSIST) {
+      // nwork carries the group count
+      ncb = a.cout / BN;
+      const int n = nt * ncb * nwork;
+      const int per = (n + 7) >> 3, p8 = gridDim.x >> 3;
+      const int lo = (blockIdx.x & 7) * per + (blockIdx.x >> 3), hi = min(n, ((blockIdx.x & 7) + 1) * per);
+      if (lo >= hi) return;
+      first = lo;
+      step = p8;
+      count = (hi - lo + p8 - 1) / p8;
+    } else {
+      const int per = (nt + 7) >> 3;
+      tile0 = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+      if (tile0 >= nt) return;
+      n00 = blockIdx.y * BN;
+      grp0 = blockIdx.z;
     }
   }
+  auto item = [&](int k, int& tile, int& n0, int& grp) {
+    if (PERSIST && !descs) {
+      const int L = first + k * step;
+      const int t = L / ncb;
+      n0 = (L - t * ncb) * BN;
+      tile = t % nt;
+      grp = t / nt;
+    } else {
+      tile = tile0;
+      n0 = n00;
+      grp = grp0;
+    }
+  };
+  const int tiles_x = (a.Wout + TW - 1) / TW;
+  const int ns = a.cin / 16;
+  const int total = count * ns;                // slices over all items
+
+  // Halo sources of the item the halo loads are on.  LDS chunk q of a stage
+  // holds row q / 2, half (q & 1) ^ swizzle(row), the layout the fragment
+  // reads expect; rows outside the input read the zero chunk (no slice step).
+  const unsigned char* hsrc[NIH];
+  int hstep[NIH];
+  auto set_halo = [&](int tile, int grp) {
+    const int oy0 = (tile / tiles_x) * TH, ox0 = (tile % tiles_x) * TW;
+    const unsigned char* inb = reinterpret_cast<const unsigned char*>(a.in) + grp * a.in_goff * 2;
+#pragma unroll
+    for (int j = 0; j < NIH; ++j) {
+      const int q = (j * NWAVES + wave) * 64 + lane;
+      hsrc[j] = kZeroChunk;
+      hstep[j] = 0;
+      if (q < HCH) {
+        const int row = q >> 1;
+        const int c = (q & 1) ^ ((row >> 3) & 1);
+        const int iy = oy0 - 1 + row / HW, ix = ox0 - 1 + row % HW;
+        if (iy >= 0 && ix >= 0 && iy < a.Hin && ix < a.Win) {
+          hsrc[j] = inb + (((long)iy * a.Win + ix) * a.in_pitch + c * 8) * 2;
+          hstep[j] = 32;
+        }
+      }
+    }
+  };
+  // Weight chunk offsets within a slice for channel block 0 (an item adds
+  // n0 * 32); -1 past the slice.
   int woff[NIW];
 #pragma unroll
   for (int j = 0; j < NIW; ++j) {
@@ -773,29 +835,58 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
       const int row = q >> 1;
       const int c = (q & 1) ^ ((row >> 3) & 1);
       const int tap = row / BN, n = row - (row / BN) * BN;
-      woff[j] = ((tap * a.cout + n0 + n) * 32 + c * 16);
+      woff[j] = ((tap * a.cout + n) * 32 + c * 16);
     }
   }
   const long wslice = 9L * a.cout * 32;
+  auto wbase_of = [&](int n0, int grp) {
+    return reinterpret_cast<const unsigned char*>(a.wpk) + grp * a.w_gstride + (long)n0 * 32;
+  };
   unsigned char* const hring = sh;
   unsigned char* const wring = sh + NH * R::HSTAGE;
-  auto issue_h = [&](int s, int stage) {
+
+  // the halo and weight load cursors: item, slice
+  int hk = 0, hs = 0, wk = 0, ws = 0;
+  const unsigned char* wsrc;
+  {
+    int t, n0, g;
+    item(0, t, n0, g);
+    set_halo(t, g);
+    wsrc = wbase_of(n0, g);
+  }
+  auto next_h = [&](int stage) {
+    if (hs == ns) {
+      hs = 0;
+      int t, n0, g;
+      item(++hk, t, n0, g);
+      set_halo(t, g);
+    }
 #pragma unroll
     for (int j = 0; j < NIH; ++j)
-      __builtin_amdgcn_global_load_lds(
-          (const UFVC_GLOBAL void*)(hsrc[j] + s * hstep[j]),
-          (__attribute__((address_space(3))) void*)(hring + stage * R::HSTAGE + (j * NWAVES + wave) * 1024),
-          16, 0, 0);
+      if (j < cH)
+        __builtin_amdgcn_global_load_lds(
+            (const UFVC_GLOBAL void*)(hsrc[j] + hs * hstep[j]),
+            (__attribute__((address_space(3))) void*)(hring + stage * R::HSTAGE + (j * NWAVES + wave) * 1024),
+            16, 0, 0);
+    ++hs;
   };
-  auto issue_w = [&](int s, int stage) {
-#pragma unroll
-    for (int j = 0; j < NIW; ++j) {
-      const unsigned char* src = woff[j] >= 0 ? wbase + s * wslice + woff[j] : kZeroChunk;
-      __builtin_amdgcn_global_load_lds(
-          (const UFVC_GLOBAL void*)src,
-          (__attribute__((address_space(3))) void*)(wring + stage * R::WSTAGE + (j * NWAVES + wave) * 1024),
-          16, 0, 0);
+  auto next_w = [&](int stage) {
+    if (ws == ns) {
+      ws = 0;
+      int t, n0, g;
+      item(++wk, t, n0, g);
+      wsrc = wbase_of(n0, g);
     }
+#pragma unroll
+    for (int j = 0; j < NIW; ++j)
+      if (j < cW) {
+        const unsigned char* src = woff[j] >= 0 ? wsrc + ws * wslice + woff[j] : kZeroChunk;
+        __builtin_amdgcn_global_load_lds(
+            (const UFVC_GLOBAL void*)src,
+            (__attribute__((address_space(3))) void*)(wring + stage * R::WSTAGE + (j * NWAVES + wave) * 1024),
+            16, 0, 0);
+      }
+    ++ws;
   };
 
   // positions (MFMA columns) of this lane in each of the wave's FM blocks
@@ -807,12 +898,15 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
   }
   const int khalf = lane >> 5;
   f32x16 acc[FN][FM];
+  auto zero_acc = [&]() {
 #pragma unroll
-  for (int fn = 0; fn < FN; ++fn)
+    for (int fn = 0; fn < FN; ++fn)
 #pragma unroll
-    for (int fm = 0; fm < FM; ++fm)
+      for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[fn][fm][r] = 0.f;
+        for (int r = 0; r < 16; ++r) acc[fn][fm][r] = 0.f;
+  };
+  zero_acc();
 
   auto compute_slice = [&](const unsigned char* lh, const unsigned char* lw) {
     v4u xf[2][FM], wf[2][FN];
@@ -840,102 +934,140 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
     }
   };
 
-  // Ring schedule: halos 0 .. NH-2 and weights 0 before the loop; iteration s
-  // issues weights s + 1, then halo s + NH - 1.  At the top of iteration s
-  // everything up to and including weights s has landed once only the last
-  // halo group may still be in flight (NH >= 3 puts halo s before weights s).
-#pragma unroll
-  for (int k = 0; k < NH - 1; ++k)
-    if (k < nslices) issue_h(k, k);
-  issue_w(0, 0);
-  for (int s = 0; s < nslices; ++s) {
-    if (s > 0 && s + NH - 2 < nslices) wait_vmcnt<NIH>();
-    else wait_vmcnt<0>();
-    // every wave's chunks of slice s are in LDS, and every wave is done with
-    // slice s - 1, whose stages the next loads overwrite
-    asm volatile("s_barrier" ::: "memory");
-    if (s + 1 < nslices) issue_w(s + 1, (s + 1) & 1);
-    if (s + NH - 1 < nslices) issue_h(s + NH - 1, (s + NH - 1) % NH);
-    compute_slice(hring + (s % NH) * R::HSTAGE, wring + (s & 1) * R::WSTAGE);
-  }
-  wait_vmcnt<0>();
-
   // Lane l holds, per block, position (l & 31) and channels
   // 8 (r / 4) + 4 (l / 32) + r % 4.  Swapping registers r and r + 4 (r % 8
   // < 4) between the lane halves leaves lane l < 32 with channels 0-7 and
   // 16-23 in registers 0-7 and 8-15, lane l + 32 with 8-15 and 24-31.
-  const int cofs = (lane >> 5) * 8;
   float vmax = 0.f;
+  auto epilogue = [&](int tile, int n0b, int grp) {
+    const int oy0 = (tile / tiles_x) * TH, ox0 = (tile % tiles_x) * TW;
+    const int cofs = (lane >> 5) * 8;
 #pragma unroll
-  for (int fn = 0; fn < FN; ++fn)
+    for (int fn = 0; fn < FN; ++fn)
 #pragma unroll
-    for (int fm = 0; fm < FM; ++fm) {
-      f32x16 v = acc[fn][fm];
+      for (int fm = 0; fm < FM; ++fm) {
+        f32x16 v = acc[fn][fm];
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[8 * h + r]),
-                                                          __float_as_uint(v[8 * h + r + 4]), false, false);
-          v[8 * h + r] = __uint_as_float(p[0]);
-          v[8 * h + r + 4] = __uint_as_float(p[1]);
-        }
-      const int M = blk_pos<1, TW>(wm * FM + fm, lane & 31);
-      const int oy = oy0 + M / TW, ox = ox0 + M % TW;
-      if (oy >= a.Hout || ox >= a.Wout) continue;
-      const long pos = (long)oy * a.Wout + ox;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int n = n0 + (wn * FN + fn) * 32 + h * 16 + cofs;   // first of 8 channels
-        float o[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) o[k] = v[8 * h + k];
-        if constexpr (ST == ST_BF16 || ST == ST_F32) {
-          if (a.add) {
-            const float* ad = a.add + pos * a.add_pitch + n;
-            const v4f a0 = ldg(reinterpret_cast<const v4f*>(ad)), a1 = ldg(reinterpret_cast<const v4f*>(ad + 4));
-            o[0] += a0.x; o[1] += a0.y; o[2] += a0.z; o[3] += a0.w;
-            o[4] += a1.x; o[5] += a1.y; o[6] += a1.z; o[7] += a1.w;
+          for (int r = 0; r < 4; ++r) {
+            const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[8 * h + r]),
+                                                            __float_as_uint(v[8 * h + r + 4]), false, false);
+            v[8 * h + r] = __uint_as_float(p[0]);
+            v[8 * h + r + 4] = __uint_as_float(p[1]);
           }
-          if (a.relu) {
+        const int M = blk_pos<1, TW>(wm * FM + fm, lane & 31);
+        const int oy = oy0 + M / TW, ox = ox0 + M % TW;
+        if (oy >= a.Hout || ox >= a.Wout) continue;
+        const long pos = (long)oy * a.Wout + ox;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) o[k] = fmaxf(o[k], 0.f);
+        for (int h = 0; h < 2; ++h) {
+          const int n = n0b + (wn * FN + fn) * 32 + h * 16 + cofs;   // first of 8 channels
+          float o[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) o[k] = v[8 * h + k];
+          if constexpr (ST == ST_BF16 || ST == ST_F32) {
+            if (a.add) {
+              const float* ad = a.add + pos * a.add_pitch + n;
+              const v4f a0 = ldg(reinterpret_cast<const v4f*>(ad)), a1 = ldg(reinterpret_cast<const v4f*>(ad + 4));
+              o[0] += a0.x; o[1] += a0.y; o[2] += a0.z; o[3] += a0.w;
+              o[4] += a1.x; o[5] += a1.y; o[6] += a1.z; o[7] += a1.w;
+            }
+            if (a.relu) {
+#pragma unroll
+              for (int k = 0; k < 8; ++k) o[k] = fmaxf(o[k], 0.f);
+            }
           }
-        }
-        if constexpr (ST == ST_BF16) {
-          bf16x8 b;
+          if constexpr (ST == ST_BF16) {
+            bf16x8 b;
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            b[k] = (__bf16)o[k];
-            vmax = fmaxf(vmax, fabsf(o[k]));
-          }
-          stg(reinterpret_cast<v4u*>(reinterpret_cast<__bf16*>(a.out) + pos * a.out_pitch + grp * a.out_goff + n),
-              __builtin_bit_cast(v4u, b));
-        } else if constexpr (ST == ST_F32) {
-          float* dst = reinterpret_cast<float*>(a.out) + pos * a.out_pitch + grp * a.out_goff + n;
-          stg(reinterpret_cast<v4f*>(dst), v4f{o[0], o[1], o[2], o[3]});
-          stg(reinterpret_cast<v4f*>(dst + 4), v4f{o[4], o[5], o[6], o[7]});
-        } else {
-          static_assert(ST == ST_SHUFFLE, "ring kernel stores bf16, float32 or shuffled frames");
-          // channels n .. n + 7 = c*64 + i*8 + (0..7): pixels (8 oy + i, 8 ox + 0..7)
-          const int c = n >> 6, i = (n >> 3) & 7;
-          const int py = 8 * oy + i, px = 8 * ox;
-          if (py < a.H) {
+            for (int k = 0; k < 8; ++k) {
+              b[k] = (__bf16)o[k];
+              vmax = fmaxf(vmax, fabsf(o[k]));
+            }
+            stg(reinterpret_cast<v4u*>(reinterpret_cast<__bf16*>(a.out) + pos * a.out_pitch + grp * a.out_goff + n),
+                __builtin_bit_cast(v4u, b));
+          } else if constexpr (ST == ST_F32) {
+            float* dst = reinterpret_cast<float*>(a.out) + pos * a.out_pitch + grp * a.out_goff + n;
+            stg(reinterpret_cast<v4f*>(dst), v4f{o[0], o[1], o[2], o[3]});
+            stg(reinterpret_cast<v4f*>(dst + 4), v4f{o[4], o[5], o[6], o[7]});
+          } else {
+            static_assert(ST == ST_SHUFFLE, "ring kernel stores bf16, float32 or shuffled frames");
+            // channels n .. n + 7 = c*64 + i*8 + (0..7): pixels (8 oy + i, 8 ox + 0..7)
+            const int c = n >> 6, i = (n >> 3) & 7;
+            const int py = 8 * oy + i, px = 8 * ox;
+            if (py < a.H) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) o[k] = fminf(fmaxf(o[k], 0.f), 1.f);
-            float* dst = reinterpret_cast<float*>(a.out) + (((long)grp * 3 + c) * a.H + py) * a.W + px;
-            if ((a.W & 3) == 0 && (reinterpret_cast<uintptr_t>(a.out) & 15) == 0 && px + 8 <= a.W) {
-              stg(reinterpret_cast<v4f*>(dst), v4f{o[0], o[1], o[2], o[3]});
-              stg(reinterpret_cast<v4f*>(dst + 4), v4f{o[4], o[5], o[6], o[7]});
-            } else {
+              for (int k = 0; k < 8; ++k) o[k] = fminf(fmaxf(o[k], 0.f), 1.f);
+              float* dst = reinterpret_cast<float*>(a.out) + (((long)grp * 3 + c) * a.H + py) * a.W + px;
+              if ((a.W & 3) == 0 && (reinterpret_cast<uintptr_t>(a.out) & 15) == 0 && px + 8 <= a.W) {
+                stg(reinterpret_cast<v4f*>(dst), v4f{o[0], o[1], o[2], o[3]});
+                stg(reinterpret_cast<v4f*>(dst + 4), v4f{o[4], o[5], o[6], o[7]});
+              } else {
 #pragma unroll
-              for (int k = 0; k < 8; ++k)
-                if (px + k < a.W) stg(dst + k, o[k]);
+                for (int k = 0; k < 8; ++k)
+                  if (px + k < a.W) stg(dst + k, o[k]);
+              }
             }
           }
         }
       }
+  };
+
+  // Ring schedule over the slices g = 0 .. total - 1 of all items: halos
+  // 0 .. LH - 1 and weights 0 .. LW - 1 before the loop; iteration g issues
+  // the stream with the shorter lookahead first, then the other (halo g + LH,
+  // weights g + LW).  Loads complete in issue order, so at the top of
+  // iteration g halo g and weights g have landed once no more than the loads
+  // issued after the later of them are outstanding: those of iteration g - 1
+  // that are not needed yet.  (Stores of a finished item, issued after them,
+  // only make that wait stricter.)
+#pragma unroll
+  for (int g = 0; g < LH; ++g)
+    if (g < total) next_h(g);
+#pragma unroll
+  for (int g = 0; g < LW; ++g)
+    if (g < total) next_w(g);
+  [[maybe_unused]] int ck = 0, cs = 0;
+  int c_tile, c_n0, c_grp;
+  item(0, c_tile, c_n0, c_grp);
+  for (int g = 0; g < total; ++g) {
+    if (g == 0) {
+      wait_vmcnt<0>();
+    } else {
+      int after = 0;
+      if (g + 1 < total) {
+        if constexpr (LH == 2 && LW == 2) after = cH + cW;
+        else if constexpr (LH == 1 && LW == 2) after = cW;
+        else if constexpr (LH == 2 && LW == 1) after = cH;
+      }
+      wait_vmcnt_le<NIH + NIW>(after);
     }
+    // every wave's chunks of slice g are in LDS, and every wave is done with
+    // slice g - 1, whose stages the next loads overwrite
+    asm volatile("s_barrier" ::: "memory");
+    if constexpr (LH <= LW) {
+      if (g + LH < total) next_h((g + LH) % NH);
+      if (g + LW < total) next_w((g + LW) % NW);
+    } else {
+      if (g + LW < total) next_w((g + LW) % NW);
+      if (g + LH < total) next_h((g + LH) % NH);
+    }
+    compute_slice(hring + (g % NH) * R::HSTAGE, wring + (g % NW) * R::WSTAGE);
+    if constexpr (PERSIST) {
+      if (++cs == ns) {
+        epilogue(c_tile, c_n0, c_grp);
+        zero_acc();
+        cs = 0;
+        if (++ck < count) item(ck, c_tile, c_n0, c_grp);
+      }
+    }
+  }
+  // no load may still be writing LDS when the block ends
+  wait_vmcnt<0>();
+  // one item per workgroup: its epilogue after the loop, where the loop's
+  // registers are free
+  if constexpr (!PERSIST) epilogue(c_tile, c_n0, c_grp);
   if constexpr (ST == ST_BF16) {
     if (a.amax_out) {
       vmax = fmaxf(vmax, 0.f);
@@ -974,6 +1106,15 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
 //     23 = 4x16 tile,  32 channels, 2x1 waves of 32x32
 //   hyper_conv_kernel (the stride-2 hyper conv, float32, and nothing else):
 //     24 = 1x16 tile,  16 channels, one wave of 16x16
+//   ring kernel with the weights two slices ahead (tile, waves as listed),
+//   persistent (P) or one item per workgroup:
+//     25 = 16x16 tile, 64 channels, 4x1 waves of 64x64; halo 1 ahead; P
+//     26 = 8x16 tile,  64 channels, 4x1 waves of 32x64; halo 2 ahead; P
+//     27 = 16x16 tile, 64 channels, 4x1 waves of 64x64; halo 1 ahead
+//     28 = 8x16 tile,  64 channels, 4x1 waves of 32x64; halo 2 ahead
+//   persistent ring kernel with the weights one slice ahead:
+//     29 = 16x16 tile, 64 channels, 4x1 waves of 64x64; halo 2 ahead; P
+//     30 = 8x16 tile,  64 channels, 4x1 waves of 32x64; halo 2 ahead; P
 static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 16, 128},
                                 {8, 16, 64},  {16, 16, 128}, {16, 16, 192}, {16, 16, 64},
                                 {16, 16, 128}, {16, 16, 64},
@@ -981,8 +1122,10 @@ static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 1
                                 {16, 16, 128}, {16, 16, 192}, {8, 16, 192}, {8, 16, 32},
                                 {16, 16, 64}, {8, 16, 64},
                                 {8, 16, 64}, {16, 16, 64}, {2, 16, 32}, {4, 16, 32},
-                                {1, 16, 16}};
-constexpr int kFirstRing = 10, kLastRing = 19;
+                                {1, 16, 16},
+                                {16, 16, 64}, {8, 16, 64}, {16, 16, 64}, {8, 16, 64},
+                                {16, 16, 64}, {8, 16, 64}};
+constexpr int kFirstRing = 10, kLastRing = 19, kFirstRing2 = 25, kLastRing2 = 30;
 int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int cfg) {
   // stride 2 (the hyper conv) has the one configuration, so its results
@@ -990,7 +1133,7 @@ bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int
   if (stride == 2 || cfg == kHyperCfg)
     return cfg == kHyperCfg && stride == 2 && prec == P_F32 && loader == LD_NHWC &&
            (cin == 64 || cin == 128) && cout % 16 == 0;
-  if (cfg >= kFirstRing && cfg <= kLastRing)
+  if ((cfg >= kFirstRing && cfg <= kLastRing) || (cfg >= kFirstRing2 && cfg <= kLastRing2))
     return prec == P_BF16 && loader == LD_NHWC && stride == 1 && cin % 16 == 0;
   if (cfg >= conv_num_cfgs()) return false;
   return cfg >= 0 && !(prec == P_FP8 && (cfg == 5 || cfg == 6 || cfg == 8));
@@ -1046,24 +1189,50 @@ static hipError_t run_conv(const ConvArgs& a, int groups, const ConvArgs* descs,
   return hipGetLastError();
 }
 
-template <int ST, int TH, int TW, int WM, int WN, int FM, int FN, int NH>
+// Workgroups of kern resident on the whole chip at once (per device, cached).
+static int chip_slots(std::atomic<int>* cache, const void* kern, int threads, int lds) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 32) return 0;
+  int v = cache[dev].load(std::memory_order_acquire);
+  if (v > 0) return v;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  v = per_cu * cus;
+  if (v > 0) cache[dev].store(v, std::memory_order_release);
+  return v;
+}
+
+template <int ST, int TH, int TW, int WM, int WN, int FM, int FN, int NH, int NW, bool PERSIST>
 static hipError_t run_ring(const ConvArgs& a, int groups, const ConvArgs* descs, const int4* work,
                            int nwork, hipStream_t s) {
-  using R = Ring<ST, TH, TW, WM, WN, FM, FN, NH>;
-  auto kern = conv3x3_ring_kernel<ST, TH, TW, WM, WN, FM, FN, NH>;
+  using R = Ring<TH, TW, WM, WN, FM, FN, NH, NW>;
+  auto kern = conv3x3_ring_kernel<ST, TH, TW, WM, WN, FM, FN, NH, NW, PERSIST>;
   static std::atomic<uint32_t> attr_done{0};
   if (const hipError_t e = set_lds_limit_once(attr_done, reinterpret_cast<const void*>(kern), R::LDS))
     return e;
   dim3 grid;
+  int arg = nwork;
   if (descs) {
     if (nwork <= 0) return hipSuccess;
     grid = dim3(((nwork + 7) / 8) * 8, 1, 1);
   } else {
     if (a.cout % R::BN || a.cin % 16) return hipErrorInvalidValue;
     const int tiles = ((a.Hout + TH - 1) / TH) * ((a.Wout + TW - 1) / TW);
-    grid = dim3(((tiles + 7) / 8) * 8, a.cout / R::BN, groups);
+    if constexpr (PERSIST) {
+      static std::atomic<int> slots[32];
+      const int sl = chip_slots(slots, reinterpret_cast<const void*>(kern), WM * WN * 64, R::LDS);
+      if (sl <= 0) return hipErrorLaunchFailure;
+      const long items = (long)tiles * (a.cout / R::BN) * groups;
+      const long p = std::min<long>(items, sl);
+      grid = dim3((unsigned)(((p + 7) / 8) * 8), 1, 1);
+      arg = groups;
+    } else {
+      grid = dim3(((tiles + 7) / 8) * 8, a.cout / R::BN, groups);
+    }
   }
-  hipLaunchKernelGGL(kern, grid, dim3(WM * WN * 64), R::LDS, s, a, descs, work, nwork);
+  hipLaunchKernelGGL(kern, grid, dim3(WM * WN * 64), R::LDS, s, a, descs, work, arg);
   return hipGetLastError();
 }
 
@@ -1118,16 +1287,22 @@ static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs
   }
   if constexpr (PREC == P_BF16 && LD == LD_NHWC && STRIDE == 1 && ST != ST_ZSYM) {
     switch (cfg) {
-      case 10: return run_ring<ST, 16, 16, 2, 2, 4, 2, 3>(a, groups, d, w, nw, s);
-      case 11: return run_ring<ST, 8, 16, 2, 2, 2, 2, 3>(a, groups, d, w, nw, s);
-      case 12: return run_ring<ST, 8, 16, 2, 2, 2, 1, 3>(a, groups, d, w, nw, s);
-      case 13: return run_ring<ST, 16, 16, 2, 2, 4, 1, 3>(a, groups, d, w, nw, s);
-      case 14: return run_ring<ST, 16, 16, 4, 2, 2, 2, 3>(a, groups, d, w, nw, s);
-      case 15: return run_ring<ST, 16, 16, 2, 2, 4, 3, 3>(a, groups, d, w, nw, s);
-      case 16: return run_ring<ST, 8, 16, 2, 2, 2, 3, 3>(a, groups, d, w, nw, s);
-      case 17: return run_ring<ST, 8, 16, 4, 1, 1, 1, 3>(a, groups, d, w, nw, s);
-      case 18: return run_ring<ST, 16, 16, 4, 1, 2, 2, 3>(a, groups, d, w, nw, s);
-      case 19: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3>(a, groups, d, w, nw, s);
+      case 10: return run_ring<ST, 16, 16, 2, 2, 4, 2, 3, 2, false>(a, groups, d, w, nw, s);
+      case 11: return run_ring<ST, 8, 16, 2, 2, 2, 2, 3, 2, false>(a, groups, d, w, nw, s);
+      case 12: return run_ring<ST, 8, 16, 2, 2, 2, 1, 3, 2, false>(a, groups, d, w, nw, s);
+      case 13: return run_ring<ST, 16, 16, 2, 2, 4, 1, 3, 2, false>(a, groups, d, w, nw, s);
+      case 14: return run_ring<ST, 16, 16, 4, 2, 2, 2, 3, 2, false>(a, groups, d, w, nw, s);
+      case 15: return run_ring<ST, 16, 16, 2, 2, 4, 3, 3, 2, false>(a, groups, d, w, nw, s);
+      case 16: return run_ring<ST, 8, 16, 2, 2, 2, 3, 3, 2, false>(a, groups, d, w, nw, s);
+      case 17: return run_ring<ST, 8, 16, 4, 1, 1, 1, 3, 2, false>(a, groups, d, w, nw, s);
+      case 18: return run_ring<ST, 16, 16, 4, 1, 2, 2, 3, 2, false>(a, groups, d, w, nw, s);
+      case 19: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 2, false>(a, groups, d, w, nw, s);
+      case 25: return run_ring<ST, 16, 16, 4, 1, 2, 2, 2, 3, true>(a, groups, d, w, nw, s);
+      case 26: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 3, true>(a, groups, d, w, nw, s);
+      case 27: return run_ring<ST, 16, 16, 4, 1, 2, 2, 2, 3, false>(a, groups, d, w, nw, s);
+      case 28: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 3, false>(a, groups, d, w, nw, s);
+      case 29: return run_ring<ST, 16, 16, 4, 1, 2, 2, 3, 2, true>(a, groups, d, w, nw, s);
+      case 30: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 2, true>(a, groups, d, w, nw, s);
       default: break;
     }
   }
