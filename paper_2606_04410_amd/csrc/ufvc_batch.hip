@@ -124,7 +124,7 @@ int pick_cfg(ufvc_ctx* c, int stage_id, int prec, int ld, int stride, const Conv
     return c->force_cfg;
   auto it = c->tune.find(tune_key(stage_id, a.Hout, a.Wout));
   if (it != c->tune.end()) return it->second;
-  return default_cfg(a.cout, (long)a.Hout * a.Wout, stride);
+  return default_cfg(a.cout, (long)a.Hout * a.Wout, stride, ld);
 }
 
 // Builds the work list entries of one conv stage: per chunk one problem

@@ -83,7 +83,7 @@ static hipError_t tuned_conv(ufvc_ctx* c, int id, int prec, int ld, int st, cons
   auto it = c->tune.find(key);
   if (it != c->tune.end()) return launch_conv(prec, ld, st, stride, it->second, a, groups, s);
   if (!c->cfg.autotune)
-    return launch_conv(prec, ld, st, stride, default_cfg(a.cout, (long)a.Hout * a.Wout, stride), a, groups, s);
+    return launch_conv(prec, ld, st, stride, default_cfg(a.cout, (long)a.Hout * a.Wout, stride, ld), a, groups, s);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hipErrorOutOfMemory;
   int best = -1;

@@ -288,8 +288,9 @@ __device__ __forceinline__ int blk_pos(int b, int j) {
 // belongs at its position, XOR swizzle included), through two slice
 // buffers: loads run one slice ahead, nothing is staged in registers and the
 // block syncs once per slice.  Loaders that convert (unshuffle, dequantise,
-// up-sample, quantise) stage through registers into a single buffer.
-template <int PREC, int LD, int STRIDE, int TH, int TW, int WM, int WN, int FN>
+// up-sample, quantise) stage through registers into a single buffer, one per
+// K group (KS = 2: two wave groups take alternate slices).
+template <int PREC, int LD, int STRIDE, int TH, int TW, int WM, int WN, int FN, int KS = 1>
 struct Pipe {
   static constexpr int ROWB = PT<PREC>::ROWB, CH = PT<PREC>::CH;
   static constexpr int NWAVES = WM * WN;
@@ -299,8 +300,9 @@ struct Pipe {
   static constexpr int NIW = ((NCH + 63) / 64 + NWAVES - 1) / NWAVES;  // loads per wave and slice
   static constexpr int STAGE = NIW * NWAVES * 64 * 16;            // bytes, padded to whole loads
   static constexpr bool DIRECT =
-      LD == LD_NHWC && (PREC == P_BF16 || PREC == P_F32) && 2 * STAGE <= 160 * 1024;
-  static constexpr int LDS = DIRECT ? 2 * STAGE : (HP + 9 * BN) * ROWB;
+      KS == 1 && LD == LD_NHWC && (PREC == P_BF16 || PREC == P_F32) && 2 * STAGE <= 160 * 1024;
+  static constexpr int GROUP_LDS = (HP + 9 * BN) * ROWB;      // one K group's staging buffer
+  static constexpr int LDS = DIRECT ? 2 * STAGE : KS * GROUP_LDS;
 };
 
 // Hyper-prior conv (Sec. 3.4): stride 2, pad 1, float32 operands on the
@@ -396,11 +398,18 @@ hyper_conv_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* _
 __device__ __attribute__((aligned(64))) unsigned char kZeroChunk[64];
 
 
-template <int PREC, int LD, int ST, int STRIDE, int TH, int TW, int WM, int WN, int FM, int FN>
-__global__ void __launch_bounds__(WM * WN * 64)
+// KS = 2 (split K): the workgroup holds two groups of WM x WN waves; group g
+// stages and multiplies slices g, g + 2, g + 4, ... into its own
+// accumulators, and group 1 adds its sums into group 0's through LDS at the
+// end, so each output is (sum over even slices) + (sum over odd slices).
+// Halving the output tile per K group is what lets 64 x 64 wave blocks (one
+// LDS fragment read per MFMA instead of 1.5) fill the chip on a layer with
+// few output tiles.
+template <int PREC, int LD, int ST, int STRIDE, int TH, int TW, int WM, int WN, int FM, int FN, int KS = 1>
+__global__ void __launch_bounds__(WM * WN * 64 * KS, KS == 2 ? 2 : 1)   // split K: two waves per SIMD
 conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __restrict__ work,
                int nwork) {
-  constexpr int NT = WM * WN * 64;
+  constexpr int NT = WM * WN * 64;   // threads of one K group
   constexpr int BM = TH * TW;
   static_assert(BM == WM * FM * 32, "tile rows must match the wave grid");
   constexpr int BN = WN * FN * 32;
@@ -416,12 +425,15 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
   constexpr int E = PT<PREC>::E;
   constexpr int ESZ = PT<PREC>::ESZ;
 
-  using PP = Pipe<PREC, LD, STRIDE, TH, TW, WM, WN, FN>;
+  using PP = Pipe<PREC, LD, STRIDE, TH, TW, WM, WN, FN, KS>;
+  static_assert(KS == 1 || (KS == 2 && !PP::DIRECT), "split K uses the register-staged pipeline");
+  static_assert(KS == 1 || WM * WN * FM * FN * 4096 <= PP::LDS, "the K groups' sums pass through LDS");
   extern __shared__ __attribute__((aligned(16))) unsigned char sh[];
-  unsigned char* lds_h = sh;
-  unsigned char* lds_w = sh + HP * ROWB;
+  const int kg = KS == 1 ? 0 : (int)(threadIdx.x >= NT);   // K group
+  unsigned char* lds_h = sh + kg * PP::GROUP_LDS;
+  unsigned char* lds_w = lds_h + HP * ROWB;
 
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x - kg * NT;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave / WN;
@@ -628,14 +640,42 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
     // no load may still be writing LDS when the block ends
     wait_vmcnt<0>();
   } else {
-    UFVC_GLOAD(0);
-    for (int s = 0; s < nslices; ++s) {
+    UFVC_GLOAD(kg);
+    for (int s = 0; s < nslices; s += KS) {
       UFVC_LSTORE();
       __syncthreads();
-      UFVC_GLOAD(min(s + 1, nslices - 1));
+      UFVC_GLOAD(min(s + KS, nslices - KS) + kg);
       compute_slice();
       __syncthreads();
     }
+  }
+  if constexpr (KS == 2) {
+    // group 1's sums to group 0 (the staging buffers are free after the last
+    // barrier): 16-byte runs of 4 accumulator registers, lane-contiguous
+    v4f* red = reinterpret_cast<v4f*>(sh);
+    const int wave_ = tid >> 6;
+    if (kg == 1) {
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            red[(((wave_ * FM + fm) * FN + fn) * 4 + q) * 64 + lane] =
+                v4f{acc[fm][fn][4 * q], acc[fm][fn][4 * q + 1], acc[fm][fn][4 * q + 2], acc[fm][fn][4 * q + 3]};
+    }
+    __syncthreads();
+    if (kg == 1) return;
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const v4f t = red[(((wave_ * FM + fm) * FN + fn) * 4 + q) * 64 + lane];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[fm][fn][4 * q + i] += t[i];
+        }
   }
 #undef UFVC_GLOAD
 #undef UFVC_LSTORE
@@ -1115,6 +1155,10 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
 //   persistent ring kernel with the weights one slice ahead:
 //     29 = 16x16 tile, 64 channels, 4x1 waves of 64x64; halo 2 ahead; P
 //     30 = 8x16 tile,  64 channels, 4x1 waves of 32x64; halo 2 ahead; P
+//   first family split over K between two wave groups (the patchify loader
+//   takes these and only these, so its results never depend on the choice):
+//     31 = 8x16 tile,  64 channels, 2 groups of 2x1 waves of 64x64
+//     32 = 8x16 tile, 128 channels, 2 groups of 2x2 waves of 64x64
 static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 16, 128},
                                 {8, 16, 64},  {16, 16, 128}, {16, 16, 192}, {16, 16, 64},
                                 {16, 16, 128}, {16, 16, 64},
@@ -1124,8 +1168,10 @@ static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 1
                                 {8, 16, 64}, {16, 16, 64}, {2, 16, 32}, {4, 16, 32},
                                 {1, 16, 16},
                                 {16, 16, 64}, {8, 16, 64}, {16, 16, 64}, {8, 16, 64},
-                                {16, 16, 64}, {8, 16, 64}};
+                                {16, 16, 64}, {8, 16, 64},
+                                {8, 16, 64}, {8, 16, 128}};
 constexpr int kFirstRing = 10, kLastRing = 19, kFirstRing2 = 25, kLastRing2 = 30;
+constexpr int kFirstSplitK = 31, kLastSplitK = 32;
 int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int cfg) {
   // stride 2 (the hyper conv) has the one configuration, so its results
@@ -1133,6 +1179,10 @@ bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int
   if (stride == 2 || cfg == kHyperCfg)
     return cfg == kHyperCfg && stride == 2 && prec == P_F32 && loader == LD_NHWC &&
            (cin == 64 || cin == 128) && cout % 16 == 0;
+  if (cfg >= kFirstSplitK && cfg <= kLastSplitK)
+    return loader == LD_UNSHUFFLE && (prec == P_BF16 || prec == P_F32) && stride == 1 &&
+           cin % (prec == P_BF16 ? 32 : 16) == 0;
+  if (loader == LD_UNSHUFFLE) return false;
   if ((cfg >= kFirstRing && cfg <= kLastRing) || (cfg >= kFirstRing2 && cfg <= kLastRing2))
     return prec == P_BF16 && loader == LD_NHWC && stride == 1 && cin % 16 == 0;
   if (cfg >= conv_num_cfgs()) return false;
@@ -1167,12 +1217,12 @@ TileCfg conv_cfg(int c) { return kCfgs[c]; }
 
 // descs == nullptr: one problem `a` over a (tiles, cout / BN, groups) grid.
 // Otherwise: nwork items of the work list over the problems in descs.
-template <int PREC, int LD, int ST, int STRIDE, int TH, int TW, int WM, int WN, int FM, int FN>
+template <int PREC, int LD, int ST, int STRIDE, int TH, int TW, int WM, int WN, int FM, int FN, int KS = 1>
 static hipError_t run_conv(const ConvArgs& a, int groups, const ConvArgs* descs, const int4* work,
                            int nwork, hipStream_t s) {
   constexpr int BN = WN * FN * 32;
-  constexpr int lds = Pipe<PREC, LD, STRIDE, TH, TW, WM, WN, FN>::LDS;
-  auto kern = conv3x3_kernel<PREC, LD, ST, STRIDE, TH, TW, WM, WN, FM, FN>;
+  constexpr int lds = Pipe<PREC, LD, STRIDE, TH, TW, WM, WN, FN, KS>::LDS;
+  auto kern = conv3x3_kernel<PREC, LD, ST, STRIDE, TH, TW, WM, WN, FM, FN, KS>;
   static std::atomic<uint32_t> attr_done{0};
   if (const hipError_t e = set_lds_limit_once(attr_done, reinterpret_cast<const void*>(kern), lds))
     return e;
@@ -1181,11 +1231,11 @@ static hipError_t run_conv(const ConvArgs& a, int groups, const ConvArgs* descs,
     if (nwork <= 0) return hipSuccess;
     grid = dim3(((nwork + 7) / 8) * 8, 1, 1);
   } else {
-    if (a.cout % BN || a.cin % PT<PREC>::E) return hipErrorInvalidValue;
+    if (a.cout % BN || a.cin % (PT<PREC>::E * KS)) return hipErrorInvalidValue;
     const int tiles = ((a.Hout + TH - 1) / TH) * ((a.Wout + TW - 1) / TW);
     grid = dim3(((tiles + 7) / 8) * 8, a.cout / BN, groups);
   }
-  hipLaunchKernelGGL(kern, grid, dim3(WM * WN * 64), lds, s, a, descs, work, nwork);
+  hipLaunchKernelGGL(kern, grid, dim3(WM * WN * 64 * KS), lds, s, a, descs, work, nwork);
   return hipGetLastError();
 }
 
@@ -1284,6 +1334,13 @@ static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs
     case 22: return run_conv<PREC, LD, ST, STRIDE, 2, 16, 1, 1, 1, 1>(a, groups, d, w, nw, s);
     case 23: return run_conv<PREC, LD, ST, STRIDE, 4, 16, 2, 1, 1, 1>(a, groups, d, w, nw, s);
     default: break;
+  }
+  if constexpr (LD == LD_UNSHUFFLE && STRIDE == 1 && (PREC == P_BF16 || PREC == P_F32)) {
+    switch (cfg) {
+      case 31: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 1, 2, 2, 2>(a, groups, d, w, nw, s);
+      case 32: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 2, 2>(a, groups, d, w, nw, s);
+      default: break;
+    }
   }
   if constexpr (PREC == P_BF16 && LD == LD_NHWC && STRIDE == 1 && ST != ST_ZSYM) {
     switch (cfg) {

@@ -105,8 +105,10 @@ static const char* kStageNames[S_COUNT] = {
 
 
 namespace ufvc {
-inline int default_cfg(int cout, long npos, int stride = 1) {
+inline int default_cfg(int cout, long npos, int stride = 1, int loader = -1) {
   if (stride == 2) return kHyperCfg;
+  // the patchify loader runs split over K (its only configurations)
+  if (loader == LD_UNSHUFFLE) return 31;
   if (cout % 128 == 0) return npos >= 16384 ? 5 : 0;
   if (cout % 192 == 0) return 2;
   if (cout % 64 == 0) return 4;
