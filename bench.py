@@ -32,23 +32,30 @@ sys.path.insert(0, ROOT)
 METRIC = "1080p frames/s enc+dec, BF16 vs FP32 at <=0.05 dB PSNR delta; p99 latency"
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
 
-# HBM bytes per launch of the analysis conv a1 (1080p, T = 8, C = 128) from
-# rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this script, each scaled by the
-# same counter's reading for plain 256 MiB device copies in the same run
-# (profiles/a1_conv_1080p_t8_hbm_counters.md), per tile configuration
-# (rows, cols, channels).  They hold only for the conv sources they were
-# taken with: bench reports them while the SHA-256 of ufvc_conv.hip followed
-# by ufvc_common.h still matches, and null otherwise.
-A1_TRAFFIC_SHA256 = "fb64b8c27e340b571356893c06262a2e1457f959b70d8620e287b9bbb18dd619"
-A1_TRAFFIC = {  # (rows, cols, channels): (read bytes, write bytes)
-    (8, 16, 64): (250.96e6, 8.36e6),     # both 8x16/64 configurations measure the same
-    (4, 16, 128): (256.84e6, 8.38e6),
-    (8, 16, 128): (251.11e6, 8.36e6),
-    (16, 16, 128): (254.06e6, 8.36e6),   # two configurations within 0.1%
-    (16, 16, 64): (296.47e6, 8.36e6),    # mean of three configurations within 0.1%
-    (8, 16, 32): (751.61e6, 8.48e6),
-    (4, 16, 32): (801.70e6, 8.60e6),
-    (2, 16, 32): (947.65e6, 8.39e6),
+# HBM bytes per launch of the two largest convs at 1080p, T = 8, C = 128 (a1,
+# the patchify-fused analysis conv, and k3, the frame heads with the
+# pixel-shuffle store), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
+# script, each scaled by the same counter's reading for plain 256 MiB device
+# copies in the same run, per tile configuration index.  They hold only for
+# the conv sources they were taken with: bench reports them while the SHA-256
+# of ufvc_conv.hip followed by ufvc_common.h still matches, and null otherwise.
+TRAFFIC_SHA256 = "a5c266fce642629ff90ac29d53693549443cc36ccea46e4a586bda1afd1f5719"
+TRAFFIC = {  # (stage, tile configuration): (read bytes, write bytes)
+    ("a1_conv", 31): (251.13e6, 8.36e6),
+    ("a1_conv", 32): (251.1e6, 8.36e6),
+    ("k3_conv", 12): (103.43e6, 199.08e6),
+    ("k3_conv", 13): (114.96e6, 199.07e6),
+    ("k3_conv", 15): (116.09e6, 199.07e6),
+    ("k3_conv", 16): (102.59e6, 199.07e6),
+    ("k3_conv", 17): (102.38e6, 199.07e6),
+    ("k3_conv", 18): (115.42e6, 199.07e6),
+    ("k3_conv", 19): (103.71e6, 199.07e6),
+    ("k3_conv", 25): (83.74e6, 199.09e6),
+    ("k3_conv", 26): (74.15e6, 199.07e6),
+    ("k3_conv", 27): (115.72e6, 199.07e6),
+    ("k3_conv", 28): (103.21e6, 199.07e6),
+    ("k3_conv", 29): (85.27e6, 199.07e6),
+    ("k3_conv", 30): (73.09e6, 199.07e6),
 }
 
 
@@ -92,6 +99,12 @@ def a1_algorithmic_bytes(T, C, H, W, h, w):
     """Bytes a1 must move once: the float32 frames and its bf16 weights read,
     its bf16 activation written."""
     return T * 3 * H * W * 4 + 9 * (T * 192) * C * 2 + h * w * C * 2
+
+
+def k3_algorithmic_bytes(T, C, H, W, h, w):
+    """Bytes the frame heads' last conv must move once: k2's bf16 activation
+    and the bf16 weights read, the float32 frames written."""
+    return h * w * T * C * 2 + 9 * C * 192 * T * 2 + T * 3 * H * W * 4
 
 
 def stage_bytes(h, w, C, r):
@@ -913,11 +926,13 @@ def main():
         achieved = flops[dom] / (avg_ms * 1e-3) / 1e12
         traffic = None
         tile = r16["tuning"].get(dom.replace("_conv", ""))
-        if dom == "a1_conv" and tile and conv_sources_sha256() == A1_TRAFFIC_SHA256:
-            rw = A1_TRAFFIC.get(tuple(tile[1:]))
+        if tile and conv_sources_sha256() == TRAFFIC_SHA256:
+            rw = TRAFFIC.get((dom, tile[0]))
             if rw:
+                alg = (a1_algorithmic_bytes(T, C, H, W, h, w) if dom == "a1_conv"
+                       else k3_algorithmic_bytes(T, C, H, W, h, w))
                 traffic = {"read_bytes": rw[0], "write_bytes": rw[1], "bytes": rw[0] + rw[1],
-                           "algorithmic_bytes": a1_algorithmic_bytes(T, C, H, W, h, w),
+                           "algorithmic_bytes": alg, "tile_config": tile[0],
                            "source": "rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated"}
         roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2),
                 "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
