@@ -30,6 +30,7 @@ struct ChunkPlan {
   Geom g;
   // arena offsets
   size_t act0, act1, y, zsym, P, idx, sym, big0, big1, scratch, info, seg_off, seg_len;
+  size_t q8;                      // FP8 synthesis: quantised layer input (0 otherwise)
   size_t slot_z, slot_y;
 };
 
@@ -61,7 +62,8 @@ struct ufvc_batch {
     std::vector<uint8_t> hblob;
     size_t off_conv = 0, off_work = 0, off_epi_e = 0, off_epi_d = 0, off_epi_work = 0,
            off_encseg = 0, off_comp = 0, off_compmap = 0, off_parse = 0, off_decz = 0, off_decy = 0,
-           off_status = 0, off_result = 0, off_amax = 0;
+           off_status = 0, off_result = 0, off_amax = 0, off_q8 = 0;
+    long q8_units[5] = {0, 0, 0, 0, 0};   // FP8: largest quantise job of d2 d3 k1 k2 k3
     size_t dyn_bytes = 0;          // leading part of the blob rewritten per call
     bool uploaded = false;         // static part already on the device
     int n_conv = 0, n_work = 0, n_epi_work = 0, n_encseg = 0, n_compblk = 0, n_decz = 0, n_decy = 0;
@@ -124,7 +126,7 @@ int pick_cfg(ufvc_ctx* c, int stage_id, int prec, int ld, int stride, const Conv
     return c->force_cfg;
   auto it = c->tune.find(tune_key(stage_id, a.Hout, a.Wout));
   if (it != c->tune.end()) return it->second;
-  return default_cfg(a.cout, (long)a.Hout * a.Wout, stride, ld);
+  return default_cfg(a.cout, (long)a.Hout * a.Wout, stride, ld, prec);
 }
 
 // Builds the work list entries of one conv stage: per chunk one problem
@@ -176,6 +178,7 @@ int layout_chunk(ufvc_ctx* c, int model, int H, int W, ChunkPlan& cp, size_t& of
   cp.sym = take(npos * C + CODER_PAD);
   cp.big0 = take(npos * C * cp.T * es);
   cp.big1 = take(npos * C * cp.T * es);
+  cp.q8 = synth_prec(c->cfg.precision) == P_FP8 ? take(npos * C * cp.T) : 0;
   cp.scratch = take(cp.slot_z * cp.g.nseg_z + cp.slot_y * cp.g.nseg_y);
   const int nseg = cp.g.nseg_z + cp.g.nseg_y;
   cp.info = take(sizeof(SegInfo) * nseg);
@@ -223,21 +226,36 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
   }
   // fp8 amax slots of all chunks, cleared together before every decode
   P.off_amax = off;
-  off = align_up(off + 4 * (size_t)N_AMAX * n);
+  off = align_up(off + 4 * (size_t)AMAX_WORDS * n);
   P.arena_bytes = off;
   if (const int rc = plan_arena(b, P)) return rc;
   uint8_t* A = P.arena;
   const int cp_prec = conv_prec(m0->cfg.precision);
   const int sp = synth_prec(m0->cfg.precision);
   const bool q8 = sp == P_FP8;
-  const int sld = q8 ? LD_Q8 : LD_NHWC;
+  const int sld = LD_NHWC;   // FP8 layers read a quantised copy (see quant below)
   const int act_st = cp_prec == P_BF16 ? ST_BF16 : ST_F32;
   // input slot k - 1, output slot k of chunk i's synthesis chain
   auto chain = [&](ConvArgs& a, int i, int k) {
     if (!q8) return;
-    uint32_t* slots = at<uint32_t>(A, P.off_amax) + (size_t)N_AMAX * i;
+    uint32_t* slots = at<uint32_t>(A, P.off_amax) + (size_t)AMAX_WORDS * i;
     if (k > 0) a.amax_in = slots + k - 1;
-    if (k < 5) a.amax_out = slots + k;
+    if (k < 5) a.amax_out = amax_spread(slots, k);
+  };
+  // FP8 layer k (1..5) of chunk i reads a quantised copy of its input
+  // (`cpp` channels per position); the batch quantises all chunks' inputs in
+  // one launch before the layer's stage
+  std::vector<Q8Job> q8jobs[5];
+  auto quant = [&](ConvArgs& a, int i, int k, long cpp) {
+    if (!q8) return;
+    const ChunkPlan& q = P.chunks[i];
+    const long npos = (long)q.g.h * q.g.w;
+    uint32_t* slots = at<uint32_t>(A, P.off_amax) + (size_t)AMAX_WORDS * i;
+    q8jobs[k - 1].push_back(Q8Job{a.in, a.in_pitch, A + q.q8, npos, (int)cpp, amax_spread(slots, k - 1),
+                                  slots + k - 1});
+    P.q8_units[k - 1] = std::max(P.q8_units[k - 1], npos * (cpp / 16));
+    a.in = A + q.q8;
+    a.in_pitch = cpp;
   };
 
   // ---- conv stages
@@ -329,6 +347,7 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
     ConvArgs a = conv_of(q.g.h, q.g.w, q.g.h, q.g.w, b->models[q.model]->d2);
     a.in = A + q.act0; a.in_pitch = C; a.out = A + q.act1; a.out_pitch = C; a.relu = 1;
     chain(a, i, 1);
+    quant(a, i, 1, C);
     return a;
   });
   stage(P.dec_stage[3], S_D3, sp, sld, act_st, 1, -1, [&](int i, int&) {
@@ -336,6 +355,7 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
     ConvArgs a = conv_of(q.g.h, q.g.w, q.g.h, q.g.w, b->models[q.model]->d3);
     a.in = A + q.act1; a.in_pitch = C; a.out = A + q.act0; a.out_pitch = C; a.relu = 1;
     chain(a, i, 2);
+    quant(a, i, 2, C);
     return a;
   });
   stage(P.dec_stage[4], S_K1, sp, sld, act_st, 1, -1, [&](int i, int&) {
@@ -343,6 +363,7 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
     ConvArgs a = conv_of(q.g.h, q.g.w, q.g.h, q.g.w, b->models[q.model]->k1);
     a.in = A + q.act0; a.in_pitch = C; a.out = A + q.big0; a.out_pitch = (long)q.T * C; a.relu = 1;
     chain(a, i, 3);
+    quant(a, i, 3, C);
     return a;
   });
   stage(P.dec_stage[5], S_K2, sp, sld, act_st, 1, -1, [&](int i, int& g) {
@@ -351,6 +372,7 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
     a.in = A + q.big0; a.in_pitch = (long)q.T * C; a.in_goff = C;
     a.out = A + q.big1; a.out_pitch = (long)q.T * C; a.out_goff = C; a.relu = 1;
     chain(a, i, 4);
+    quant(a, i, 4, (long)q.T * C);
     g = q.T;
     return a;
   });
@@ -361,6 +383,7 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
     a.out = nullptr;  // the caller's frames, set per call
     a.T = q.T; a.H = q.H; a.W = q.W;
     chain(a, i, 5);
+    quant(a, i, 5, (long)q.T * C);
     g = q.T;
     return a;
   });
@@ -465,6 +488,7 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
   P.off_compmap = place(sizeof(int2) * compmap.size());
   P.off_status = place(4 * (size_t)n);
   P.off_result = place(8 * (size_t)n);
+  if (q8) P.off_q8 = place(sizeof(Q8Job) * 5 * (size_t)n);
   P.hblob.assign(bo, 0);
   if (hipMalloc(&P.dblob, bo) != hipSuccess) return UFVC_E_NOMEM;
   uint8_t* H = P.hblob.data();
@@ -495,6 +519,11 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
   std::memcpy(H + P.off_parse, parse.data(), sizeof(ParseDesc) * n);
   std::memcpy(H + P.off_decz, decz.data(), sizeof(DecSeg) * decz.size());
   std::memcpy(H + P.off_decy, decy.data(), sizeof(DecSeg) * decy.size());
+  if (q8)
+    for (int k = 0; k < 5; ++k) {
+      if ((int)q8jobs[k].size() != n) return UFVC_E_INVAL;
+      std::memcpy(H + P.off_q8 + sizeof(Q8Job) * (size_t)k * n, q8jobs[k].data(), sizeof(Q8Job) * n);
+    }
   return UFVC_OK;
 }
 
@@ -558,7 +587,7 @@ hipError_t run_decode(ufvc_batch* b, ufvc_batch::Plan& P, hipStream_t s) {
   hipError_t e = launch_zero_u32(at<uint32_t>(D, P.off_status), n, s);
   if (e != hipSuccess) return e;
   if (synth_prec(m0->cfg.precision) == P_FP8 &&
-      (e = launch_zero_u32(at<uint32_t>(P.arena, P.off_amax), N_AMAX * n, s)) != hipSuccess)
+      (e = launch_zero_u32(at<uint32_t>(P.arena, P.off_amax), AMAX_WORDS * n, s)) != hipSuccess)
     return e;
   if ((e = launch_parse_batch(at<ParseDesc>(D, P.off_parse), n, s)) != hipSuccess) return e;
   if ((e = launch_rans_decode_batch(m0->tab, at<DecSeg>(D, P.off_decz), P.n_decz, true, s)) != hipSuccess) return e;
@@ -567,8 +596,14 @@ hipError_t run_decode(ufvc_batch* b, ufvc_batch::Plan& P, hipStream_t s) {
                                         P.n_epi_work, m0->tab.thresholds, s)) != hipSuccess)
     return e;
   if ((e = launch_rans_decode_batch(m0->tab, at<DecSeg>(D, P.off_decy), P.n_decy, false, s)) != hipSuccess) return e;
-  for (int k = 1; k < 7; ++k)
+  const bool q8 = synth_prec(m0->cfg.precision) == P_FP8;
+  for (int k = 1; k < 7; ++k) {
+    // FP8 layers d2 .. k3: their inputs quantised first
+    if (q8 && k >= 2 &&
+        (e = launch_q8_batch(at<Q8Job>(D, P.off_q8) + (size_t)(k - 2) * n, n, P.q8_units[k - 2], s)) != hipSuccess)
+      return e;
     if ((e = run_stage(P, P.dec_stage[k], s)) != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
@@ -684,7 +719,7 @@ size_t batch_chunk_footprint(ufvc_ctx* c, int H, int W) {
   ChunkPlan cp;
   size_t off = 0;
   if (layout_chunk(c, 0, H, W, cp, off)) return 0;
-  return off + ALIGN;  // + a share of the per-batch amax block
+  return off + align_up(4 * (size_t)AMAX_WORDS);  // + its share of the per-batch amax block
 }
 
 extern "C" {

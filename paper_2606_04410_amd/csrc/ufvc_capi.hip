@@ -83,7 +83,7 @@ static hipError_t tuned_conv(ufvc_ctx* c, int id, int prec, int ld, int st, cons
   auto it = c->tune.find(key);
   if (it != c->tune.end()) return launch_conv(prec, ld, st, stride, it->second, a, groups, s);
   if (!c->cfg.autotune)
-    return launch_conv(prec, ld, st, stride, default_cfg(a.cout, (long)a.Hout * a.Wout, stride, ld), a, groups, s);
+    return launch_conv(prec, ld, st, stride, default_cfg(a.cout, (long)a.Hout * a.Wout, stride, ld, prec), a, groups, s);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hipErrorOutOfMemory;
   int best = -1;
@@ -137,12 +137,12 @@ static uint8_t e4m3_rne_sat(double x) {
 }
 
 // Repacks OIHW float32 weights of `groups` groups into the conv kernels'
-// layout: [g][slice][tap][cout][row], a slice holding 16 bf16, 8 f32 or 64
-// fp8 consecutive input channels (a row of 32, 32 or 64 bytes).  FP8 weights
-// carry a per-output-channel scale amax / 448 over that channel's taps.
+// layout: [g][slice][tap][cout][row], a slice holding 16 bf16, 8 f32 or 32
+// fp8 consecutive input channels (a row of 32 bytes).  FP8 weights carry a
+// per-output-channel scale amax / 448 over that channel's taps.
 static int upload_layer(Layer& L, const std::vector<const float*>& src, int cout, int cin,
                         int prec_conv) {
-  const int E = prec_conv == P_FP8 ? 64 : prec_conv == P_BF16 ? 16 : 8;
+  const int E = prec_conv == P_FP8 ? 32 : prec_conv == P_BF16 ? 16 : 8;
   const int esz = prec_conv == P_FP8 ? 1 : prec_conv == P_BF16 ? 2 : 4;
   const int rowb = E * esz;
   if (cin % E) return UFVC_E_UNSUPPORTED;
@@ -285,7 +285,7 @@ static hipError_t run_mean_steps(ufvc_ctx* c, const Geom& g, const float* y, int
 
 static void free_ws(ufvc_ctx* c) {
   Workspace& w = c->ws;
-  void* ptrs[] = {w.act0, w.act1, w.y, w.zsym, w.P, w.idx, w.sym, w.big0, w.big1, w.side};
+  void* ptrs[] = {w.act0, w.act1, w.y, w.zsym, w.P, w.idx, w.sym, w.big0, w.big1, w.side, w.q8};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   c->ws = Workspace{};
@@ -310,6 +310,8 @@ static int ensure_ws(ufvc_ctx* c, int h, int w) {
   if (hipMalloc(&W.big0, npos * C * T * es) != hipSuccess) return UFVC_E_NOMEM;
   if (hipMalloc(&W.big1, npos * C * T * es) != hipSuccess) return UFVC_E_NOMEM;
   if (c->cfg.temporal && hipMalloc(&W.side, npos * 2 * C * 4) != hipSuccess) return UFVC_E_NOMEM;
+  if (synth_prec(c->cfg.precision) == P_FP8 && hipMalloc(&W.q8, npos * C * T) != hipSuccess)
+    return UFVC_E_NOMEM;
   W.h = h;
   W.w = w;
   return UFVC_OK;
@@ -375,16 +377,34 @@ static hipError_t run_synthesis(ufvc_ctx* c, const Geom& g, const uint8_t* sym, 
   const int cp = conv_prec(c->cfg.precision);
   const int sp = synth_prec(c->cfg.precision);
   const int act_st = cp == P_BF16 ? ST_BF16 : ST_F32;
-  // fp8 layers quantise their bf16 input with the amax its producer recorded
+  // fp8 layers read a copy of their bf16 input quantised with the amax its
+  // producer recorded (one quantise pass per layer, into ws.q8)
   const bool q8 = sp == P_FP8;
-  const int sld = q8 ? LD_Q8 : LD_NHWC;
+  const long npos = (long)g.h * g.w;
   hipError_t e;
-  if (q8 && (e = launch_zero_u32(c->amax, N_AMAX, s)) != hipSuccess) return e;
+  if (q8 && (e = launch_zero_u32(c->amax, AMAX_WORDS, s)) != hipSuccess) return e;
   auto chain = [&](ConvArgs& a, int k) {  // input slot k - 1, output slot k
     if (!q8) return;
     if (k > 0) a.amax_in = c->amax + k - 1;
-    if (k < 5) a.amax_out = c->amax + k;
+    if (k < 5) a.amax_out = amax_spread(c->amax, k);
   };
+  // FP8 layer k (1..5): its input (channels per position `cpp`) quantised
+  // into ws.q8, which the conv then reads; the two launches form one stage
+  Q8Job qj{};
+  auto quantise = [&](ConvArgs& a, int k, long cpp) {
+    if (!q8) return;
+    qj = Q8Job{a.in, a.in_pitch, c->ws.q8, npos, (int)cpp, amax_spread(c->amax, k - 1), c->amax + k - 1};
+    a.in = c->ws.q8;
+    a.in_pitch = cpp;
+  };
+  auto fp8_first = [&](auto&& conv) -> hipError_t {
+    if (q8) {
+      const hipError_t r = launch_q8(qj, s);
+      if (r != hipSuccess) return r;
+    }
+    return conv();
+  };
+  const int sld = LD_NHWC;
   // d1: loads y_hat = r_hat + mu (or a caller-provided float32 y_hat)
   ConvArgs a = conv_args(g.h, g.w, g.h, g.w, c->d1);
   int ld = LD_DEQUANT;
@@ -408,11 +428,13 @@ static hipError_t run_synthesis(ufvc_ctx* c, const Geom& g, const uint8_t* sym, 
   a = conv_args(g.h, g.w, g.h, g.w, c->d2);
   a.in = c->ws.act0; a.in_pitch = C; a.out = c->ws.act1; a.out_pitch = C; a.relu = 1;
   chain(a, 1);
-  if ((e = stage(c, sid(S_D2), s, [&] { return tuned_conv(c, S_D2, sp, sld, act_st, a, 1, s); })) != hipSuccess) return e;
+  quantise(a, 1, C);
+  if ((e = stage(c, sid(S_D2), s, [&] { return fp8_first([&] { return tuned_conv(c, S_D2, sp, sld, act_st, a, 1, s); }); })) != hipSuccess) return e;
   a = conv_args(g.h, g.w, g.h, g.w, c->d3);
   a.in = c->ws.act1; a.in_pitch = C; a.out = c->ws.act0; a.out_pitch = C; a.relu = 1;
   chain(a, 2);
-  if ((e = stage(c, sid(S_D3), s, [&] { return tuned_conv(c, S_D3, sp, sld, act_st, a, 1, s); })) != hipSuccess) return e;
+  quantise(a, 2, C);
+  if ((e = stage(c, sid(S_D3), s, [&] { return fp8_first([&] { return tuned_conv(c, S_D3, sp, sld, act_st, a, 1, s); }); })) != hipSuccess) return e;
   // temporal models: the next context from F (act0), through act1
   if (o.ctx_out) {
     a = conv_args(g.h, g.w, g.h, g.w, c->c1);
@@ -429,19 +451,22 @@ static hipError_t run_synthesis(ufvc_ctx* c, const Geom& g, const uint8_t* sym, 
   a = conv_args(g.h, g.w, g.h, g.w, c->k1);
   a.in = c->ws.act0; a.in_pitch = C; a.out = c->ws.big0; a.out_pitch = (long)T * C; a.relu = 1;
   chain(a, 3);
-  if ((e = stage(c, S_K1, s, [&] { return tuned_conv(c, S_K1, sp, sld, act_st, a, 1, s); })) != hipSuccess) return e;
+  quantise(a, 3, C);
+  if ((e = stage(c, S_K1, s, [&] { return fp8_first([&] { return tuned_conv(c, S_K1, sp, sld, act_st, a, 1, s); }); })) != hipSuccess) return e;
   // k2 per head: group t reads channels [tC, tC + C) and writes the same range
   a = conv_args(g.h, g.w, g.h, g.w, c->k2);
   a.in = c->ws.big0; a.in_pitch = (long)T * C; a.in_goff = C;
   a.out = c->ws.big1; a.out_pitch = (long)T * C; a.out_goff = C; a.relu = 1;
   chain(a, 4);
-  if ((e = stage(c, S_K2, s, [&] { return tuned_conv(c, S_K2, sp, sld, act_st, a, T, s); })) != hipSuccess) return e;
+  quantise(a, 4, (long)T * C);
+  if ((e = stage(c, S_K2, s, [&] { return fp8_first([&] { return tuned_conv(c, S_K2, sp, sld, act_st, a, T, s); }); })) != hipSuccess) return e;
   // k3 per head with the pixel-shuffle store into frame t
   a = conv_args(g.h, g.w, g.h, g.w, c->k3);
   a.in = c->ws.big1; a.in_pitch = (long)T * C; a.in_goff = C;
   a.out = frames; a.T = T; a.H = H; a.W = W;
   chain(a, 5);
-  return stage(c, S_K3, s, [&] { return tuned_conv(c, S_K3, sp, sld, ST_SHUFFLE, a, T, s); });
+  quantise(a, 5, (long)T * C);
+  return stage(c, S_K3, s, [&] { return fp8_first([&] { return tuned_conv(c, S_K3, sp, sld, ST_SHUFFLE, a, T, s); }); });
 }
 
 // Temporal models: out (float32 [pos][pitch]) = conv(context, L), the
@@ -546,11 +571,11 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
     if (hipMalloc(&t.fc, 4 * NSCALES * NSYM) || hipMalloc(&t.magic, 4 * NSCALES * NSYM) ||
         hipMalloc(&t.shift, NSCALES * NSYM) || hipMalloc(&t.lut, NSCALES * LUT_BUCKETS * 2) ||
         hipMalloc(&t.thresholds, 4 * 64) || hipMalloc(&t.tail, 64) || hipMalloc(&c->result, 16) ||
-        hipMalloc(&c->status, 16) || hipMalloc(&c->amax, 4 * N_AMAX) || hipHostMalloc(&c->result_host, 16) ||
+        hipMalloc(&c->status, 16) || hipMalloc(&c->amax, 4 * AMAX_WORDS) || hipHostMalloc(&c->result_host, 16) ||
         hipHostMalloc(&c->status_host, 16))
       rc = UFVC_E_NOMEM;
   }
-  if (!rc && (hipMemset(c->status, 0, 16) != hipSuccess || hipMemset(c->amax, 0, 4 * N_AMAX) != hipSuccess))
+  if (!rc && (hipMemset(c->status, 0, 16) != hipSuccess || hipMemset(c->amax, 0, 4 * AMAX_WORDS) != hipSuccess))
     rc = UFVC_E_DEVICE;
   if (!rc && launch_build_tables(c->tab, nullptr) != hipSuccess) rc = UFVC_E_DEVICE;
   if (!rc && hipDeviceSynchronize() != hipSuccess) rc = UFVC_E_DEVICE;

@@ -66,7 +66,6 @@ enum Loader {
   LD_UP2 = 3,        // nearest x2 upsampling of uint8 z symbols (value sym - 32), bf16;
                      // input channel c is symbol channel c mod in_pitch
   LD_F32 = 4,        // float32 tensor, channels innermost, feeding a bf16 conv
-  LD_Q8 = 5,         // bf16 tensor quantised to FP8 E4M3 with the producer's amax scale
   LD_REP = 6         // bf16 tensor, channels innermost; input channel c is tensor channel
                      // c mod in_pitch (the split-weight convs over a bf16 input)
 };
@@ -102,11 +101,17 @@ struct ConvArgs {
   const float* add;
   long add_pitch;
   // FP8: per-output-channel weight scales [group][cout]; the amax (float
-  // bits) of this layer's input and, for a producer, of its own output
+  // bits) of this layer's input and, for a producer, where its waves record
+  // the amax of its own output: AMAX_SPREAD sub-slots AMAX_STRIDE words apart
+  // (one 128-byte line each, so the atomics do not queue on one address)
   const float* wscale;
   const unsigned* amax_in;
   unsigned* amax_out;
 };
+constexpr int AMAX_SPREAD = 64, AMAX_STRIDE = 32;
+__device__ __forceinline__ unsigned* amax_sub(unsigned* spread, unsigned who) {
+  return spread + (who & (AMAX_SPREAD - 1)) * AMAX_STRIDE;
+}
 
 // Launches one conv layer.  `cfg` selects a tile configuration (see
 // conv_tile_configs); returns hipErrorInvalidValue for unsupported combos.
@@ -292,6 +297,23 @@ struct ParseDesc {
 };
 
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
+
+// FP8 synthesis: one layer input quantised for the FP8 convs.  dst[pos][c] =
+// E4M3(src[pos * src_pitch + c] * 448 / amax) (round to nearest even,
+// saturated at 448; scale 1 if amax is 0), for npos positions of C channels
+// (a multiple of 16); the FP8 conv rescales by amax / 448.
+struct Q8Job {
+  const void* src;         // bf16
+  long src_pitch;          // elements between positions
+  void* dst;               // E4M3, C bytes per position
+  long npos;
+  int C;
+  const unsigned* amax;    // the producer's amax sub-slots (float bits; see ConvArgs::amax_out)
+  unsigned* amax_final;    // their maximum, written here for the conv and the caller
+};
+hipError_t launch_q8(const Q8Job& j, hipStream_t s);
+// jobs: device array of n jobs, each of at most max_units 16-channel units
+hipError_t launch_q8_batch(const Q8Job* jobs, int n, long max_units, hipStream_t s);
 hipError_t launch_params_epilogue_batch(const EpiDesc* d, const int2* work, int nwork,
                                         const float* thr, hipStream_t s);
 hipError_t launch_rans_encode_batch(const Tables& t, const EncSeg* segs, int nsegs, hipStream_t s);

@@ -17,10 +17,11 @@
 // stage for inputs that are copied unchanged, into registers for inputs that
 // a loader converts.  Reduction order is fixed: slice, then tap, then the
 // MFMA's own order, and does not depend on the tile configuration, so results
-// do not depend on how many workgroups cover the output.  A second kernel
-// family (conv3x3_ring_kernel, below) serves bf16 activations at stride 1,
-// and hyper_conv_kernel the stride-2 hyper conv (the first family's stride-2
-// form is not instantiated).
+// do not depend on how many workgroups cover the output (the patchify
+// loader's split-K form sums even and odd slices separately, and is that
+// loader's only form).  A second kernel family (conv3x3_ring_kernel, below)
+// serves bf16 and FP8 activations at stride 1, and hyper_conv_kernel the
+// stride-2 hyper conv (the first family's stride-2 form is not instantiated).
 //
 // Loaders fuse the producer's layout change into the halo fetch: the x8
 // pixel-unshuffle of the patch embedding with edge-replicated padding
@@ -44,9 +45,6 @@ template <> struct PT<P_BF16> {
 };
 template <> struct PT<P_F32> {
   static constexpr int ESZ = 4, E = 8, ROWB = 32, CH = 2;
-};
-template <> struct PT<P_FP8> {
-  static constexpr int ESZ = 1, E = 64, ROWB = 64, CH = 4;
 };
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
@@ -77,8 +75,8 @@ __device__ __forceinline__ float sat448(float x) { return fminf(fmaxf(x, -448.f)
 // stay in flight while the current one is multiplied: fetch_raw issues the
 // loads into registers (device-memory words, unconverted), convert_raw turns
 // them into 16 bytes of compute-type input when the chunk is written to LDS.
-// The chunk covers channels [slice*E + ch*E/2, +E/2) (fp8: 16 channels from
-// slice*64 + ch*16) at input position (iy, ix); outside the input grid it is
+// The chunk covers channels [slice*E + ch*E/2, +E/2) at input position
+// (iy, ix); outside the input grid it is
 // zero (conv zero padding).  The loads are issued for every lane at clamped
 // addresses, and padding and edge replication are applied in convert_raw:
 // a lane-divergent branch around a load would make the next write to its
@@ -106,11 +104,6 @@ __device__ __forceinline__ Raw fetch_raw(const ConvArgs& a, const unsigned char*
   const long pos = (long)iy * a.Win + ix;
   if constexpr (LD == LD_NHWC) {
     r.a = ld16(inb + (pos * a.in_pitch + slice * E + ch * (E / 2)) * ESZ);
-  } else if constexpr (LD == LD_Q8) {
-    static_assert(PREC == P_FP8, "Q8 loader feeds FP8 convs");
-    const unsigned char* src = inb + (pos * a.in_pitch + slice * 64 + ch * 16) * 2;
-    r.a = ld16(src);
-    r.b = ld16(src + 16);
   } else if constexpr (LD == LD_F32) {
     static_assert(PREC == P_BF16, "use LD_NHWC for float32 compute");
     const float* fp = reinterpret_cast<const float*>(inb) + pos * a.in_pitch + slice * E + ch * (E / 2);
@@ -162,23 +155,10 @@ __device__ __forceinline__ Raw fetch_raw(const ConvArgs& a, const unsigned char*
 }
 
 template <int PREC, int LD>
-__device__ __forceinline__ v4u convert_raw(const Raw& r, float qinv) {
+__device__ __forceinline__ v4u convert_raw(const Raw& r) {
   v4u o;
   if constexpr (LD == LD_NHWC || LD == LD_REP) {
     o = r.a;
-  } else if constexpr (LD == LD_Q8) {
-    // 16 bf16 channels -> 16 FP8 E4M3 values of x * qinv (qinv = 448 / amax)
-    const bf16x8 b0 = __builtin_bit_cast(bf16x8, r.a), b1 = __builtin_bit_cast(bf16x8, r.b);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const bf16x8& bb = k < 2 ? b0 : b1;
-      const int s = (k & 1) * 4;
-      int w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448((float)bb[s] * qinv), sat448((float)bb[s + 1] * qinv),
-                                              0, false);
-      w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448((float)bb[s + 2] * qinv), sat448((float)bb[s + 3] * qinv),
-                                          w, true);
-      o[k] = (unsigned)w;
-    }
   } else if constexpr (LD == LD_F32) {
     const v4f u0 = __builtin_bit_cast(v4f, r.a), u1 = __builtin_bit_cast(v4f, r.b);
     const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
@@ -257,15 +237,14 @@ __device__ __forceinline__ void store_out(const ConvArgs& a, int grp, int oy, in
   }
 }
 
-// LDS rows hold one position's (or weight row's) slice: 32 bytes (bf16 /
-// f32) or 64 bytes (fp8).  Their 16-byte chunks are XOR-swizzled with the
-// row index (the two halves swap every 8 rows; the four quarters rotate
-// every 4 rows), so 16 lanes reading the same chunk of 16 consecutive rows
-// hit 64 distinct banks (no padding needed).
+// LDS rows hold one position's (or weight row's) slice: 32 bytes (16 bf16,
+// 8 f32 or 32 fp8 channels).  Their two 16-byte halves are XOR-swizzled with
+// the row index (they swap every 8 rows), so 16 lanes reading the same half
+// of 16 consecutive rows hit 64 distinct banks (no padding needed).
 template <int ROWB>
 __device__ __forceinline__ int lds_off(int row, int chunk) {
-  if constexpr (ROWB == 32) return row * 32 + ((chunk ^ ((row >> 3) & 1)) << 4);
-  else return row * 64 + ((chunk ^ ((row >> 2) & 3)) << 4);
+  static_assert(ROWB == 32, "32-byte rows");
+  return row * 32 + ((chunk ^ ((row >> 3) & 1)) << 4);
 }
 
 // Tile position (row-major index into the TH x TW tile) of element j
@@ -472,16 +451,7 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
 
   const unsigned char* wbase = reinterpret_cast<const unsigned char*>(a.wpk) + grp * a.w_gstride;
   const unsigned char* inb = reinterpret_cast<const unsigned char*>(a.in) +
-                            grp * a.in_goff * (LD == LD_F32 ? 4 : LD == LD_Q8 ? 2 : ESZ);
-  // FP8: input quantisation from the producer's amax
-  float qinv = 1.f, qscale = 1.f;
-  if constexpr (PREC == P_FP8) {
-    const float amax = __uint_as_float(ldg(a.amax_in));
-    if (amax > 0.f) {
-      qinv = 448.f / amax;
-      qscale = amax / 448.f;
-    }
-  }
+                            grp * a.in_goff * (LD == LD_F32 ? 4 : ESZ);
 
   // Staging registers for the next slice.  Written and read only through
   // fully unrolled loops with constant indices so they live in VGPRs.
@@ -514,7 +484,7 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
       else { pos = q / CH; ch = q % CH; }                                                \
       if (HCH % NT == 0 || q < HCH)                                                      \
         *reinterpret_cast<v4u*>(lds_h + lds_off<ROWB>(pos, ch)) =                        \
-            convert_raw<PREC, LD>(hraw[i], qinv);                                        \
+            convert_raw<PREC, LD>(hraw[i]);                                              \
     }                                                                                    \
     _Pragma("unroll") for (int i = 0; i < WIT; ++i) {                                    \
       const int q = tid + i * NT;                                                        \
@@ -543,23 +513,15 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
   auto compute_slice = [&]() {
     // Fragments of tap t + 1 are read from LDS into the second register set
     // before the MFMAs of tap t are issued, so LDS latency overlaps the
-    // matrix cores.  A lane's fragment is 16 bytes (bf16 / f32) or 32 bytes
-    // (fp8: chunks 2 khalf and 2 khalf + 1 of its row).
-    constexpr int FRAG = PREC == P_FP8 ? 2 : 1;
-    v4u af[2][FM][FRAG], bf[2][FN][FRAG];
+    // matrix cores.  A lane's fragment is 16 bytes: half khalf of its row.
+    v4u af[2][FM], bf[2][FN];
     auto read_frags = [&](int buf, int tap) {
       const int toff = (tap / 3) * HW + (tap % 3);
 #pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int k = 0; k < FRAG; ++k)
-          af[buf][fm][k] = lds16(lds_h + lds_off<ROWB>(arow[fm] + toff, khalf * FRAG + k));
+      for (int fm = 0; fm < FM; ++fm) af[buf][fm] = lds16(lds_h + lds_off<ROWB>(arow[fm] + toff, khalf));
 #pragma unroll
       for (int fn = 0; fn < FN; ++fn)
-#pragma unroll
-        for (int k = 0; k < FRAG; ++k)
-          bf[buf][fn][k] = lds16(lds_w + lds_off<ROWB>(tap * BN + (wn * FN + fn) * 32 + (lane & 31),
-                                                      khalf * FRAG + k));
+        bf[buf][fn] = lds16(lds_w + lds_off<ROWB>(tap * BN + (wn * FN + fn) * 32 + (lane & 31), khalf));
     };
     read_frags(0, 0);
 #pragma unroll
@@ -574,22 +536,11 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
         for (int fn = 0; fn < FN; ++fn) {
           if constexpr (PREC == P_BF16) {
             acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, af[cur][fm][0]), __builtin_bit_cast(bf16x8, bf[cur][fn][0]),
+                __builtin_bit_cast(bf16x8, af[cur][fm]), __builtin_bit_cast(bf16x8, bf[cur][fn]),
                 acc[fm][fn], 0, 0, 0);
-          } else if constexpr (PREC == P_FP8) {
-            const i32x8 fa = {(int)af[cur][fm][0].x, (int)af[cur][fm][0].y, (int)af[cur][fm][0].z,
-                              (int)af[cur][fm][0].w, (int)af[cur][fm][1].x, (int)af[cur][fm][1].y,
-                              (int)af[cur][fm][1].z, (int)af[cur][fm][1].w};
-            const i32x8 fb = {(int)bf[cur][fn][0].x, (int)bf[cur][fn][0].y, (int)bf[cur][fn][0].z,
-                              (int)bf[cur][fn][0].w, (int)bf[cur][fn][1].x, (int)bf[cur][fn][1].y,
-                              (int)bf[cur][fn][1].z, (int)bf[cur][fn][1].w};
-            // E4M3 x E4M3, block scales 2^0 (the per-tensor / per-channel
-            // scales are applied in the epilogue)
-            acc[fm][fn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa, fb, acc[fm][fn], 0, 0, 0,
-                                                                         127, 0, 127);
           } else {
-            const v4f fa = __builtin_bit_cast(v4f, af[cur][fm][0]);
-            const v4f fb = __builtin_bit_cast(v4f, bf[cur][fn][0]);
+            const v4f fa = __builtin_bit_cast(v4f, af[cur][fm]);
+            const v4f fb = __builtin_bit_cast(v4f, bf[cur][fn]);
             acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.x, fb.x, acc[fm][fn], 0, 0, 0);
             acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.y, fb.y, acc[fm][fn], 0, 0, 0);
             acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.z, fb.z, acc[fm][fn], 0, 0, 0);
@@ -609,14 +560,14 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
         const unsigned char* src = kZeroChunk;
         if (q < HCH) {
           const int row = q / CH;
-          const int c = (q % CH) ^ (ROWB == 32 ? (row >> 3) & 1 : (row >> 2) & 3);
+          const int c = (q % CH) ^ ((row >> 3) & 1);
           const int hy = row / HW, hx = row - (row / HW) * HW;
           const int iy = iy0 + hy, ix = ix0 + hx;
           if (iy >= 0 && ix >= 0 && iy < a.Hin && ix < a.Win)
             src = inb + (((long)iy * a.Win + ix) * a.in_pitch + (long)S_ * E + c * (16 / ESZ)) * ESZ;
         } else if (q < HCH + WCH) {
           const int row = (q - HCH) / CH;
-          const int c = ((q - HCH) % CH) ^ (ROWB == 32 ? (row >> 3) & 1 : (row >> 2) & 3);
+          const int c = ((q - HCH) % CH) ^ ((row >> 3) & 1);
           const int tap = row / BN, n = row - (row / BN) * BN;
           src = wbase + (((long)(S_ * 9 + tap) * a.cout + n0 + n) * ROWB + c * 16);
         }
@@ -687,14 +638,11 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn) {
       const int n = n0 + (wn * FN + fn) * 32 + (lane & 31);
-      float sc = 1.f;
-      if constexpr (PREC == P_FP8) sc = qscale * ldg(a.wscale + grp * a.cout + n);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int M = blk_pos<STRIDE, TW>(wm * FM + fm, (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3));
         const int oy = oy0 + M / TW, ox = ox0 + M % TW;
-        float v = acc[fm][fn][r];
-        if constexpr (PREC == P_FP8) v *= sc;
+        const float v = acc[fm][fn][r];
         if (oy < a.Hout && ox < a.Wout) {
           store_out<ST>(a, grp, oy, ox, n, v);
           if constexpr (ST == ST_BF16) vmax = fmaxf(vmax, fabsf(a.relu ? fmaxf(v, 0.f) : v));
@@ -707,7 +655,9 @@ conv3x3_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __re
     if (a.amax_out) {
       vmax = fmaxf(vmax, 0.f);
       for (int o = 32; o > 0; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
-      if (lane == 0) atomicMax(a.amax_out, __float_as_uint((float)(__bf16)vmax));
+      if (lane == 0)
+        atomicMax(amax_sub(a.amax_out, (blockIdx.x + gridDim.x * blockIdx.y) * (WM * WN) + wave),
+                  __float_as_uint((float)(__bf16)vmax));
     }
   }
 }
@@ -770,8 +720,16 @@ __device__ __forceinline__ void wait_vmcnt_le(int n) {
 // group-major, then tile, then channel block; each XCD takes a contiguous
 // band of them (workgroups are dispatched round-robin over the 8 XCDs), so
 // the workgroups resident on one XCD share input halos and weights in its L2.
-template <int ST, int TH, int TW, int WM, int WN, int FM, int FN, int NH, int NW, bool PERSIST>
-__global__ void __launch_bounds__(WM * WN * 64)
+//
+// F8: E4M3 operands (the input quantised beforehand, per-tensor scale amax /
+// 448; weights per output channel).  A slice is then 32 input channels, so
+// its halo and weight rows are 32 bytes as in the bf16 form and the stages,
+// swizzle and schedule are the same.  One v_mfma_scale_f32_32x32x64_f8f6f4
+// takes K = 64 = two taps x 32 channels (lanes 0-31 tap 2p, lanes 32-63 tap
+// 2p + 1; the ninth tap's partner is a zero weight row), so a slice is five
+// MFMAs per block instead of nine.  The epilogue applies the scales.
+template <int ST, int TH, int TW, int WM, int WN, int FM, int FN, int NH, int NW, bool PERSIST, bool F8 = false>
+__global__ void __launch_bounds__(WM * WN * 64, PERSIST ? 2 : 1)   // persistent: two waves per SIMD
 conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* __restrict__ work,
                     int nwork) {
   using R = Ring<TH, TW, WM, WN, FM, FN, NH, NW>;
@@ -837,8 +795,15 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
     }
   };
   const int tiles_x = (a.Wout + TW - 1) / TW;
-  const int ns = a.cin / 16;
+  constexpr int ESZ = F8 ? 1 : 2;              // bytes per element
+  const int ns = a.cin / (32 / ESZ);
   const int total = count * ns;                // slices over all items
+  // FP8: the input's dequantisation scale
+  float qscale = 1.f;
+  if constexpr (F8) {
+    const float amax = __uint_as_float(ldg(a.amax_in));
+    if (amax > 0.f) qscale = amax / 448.f;
+  }
 
   // Halo sources of the item the halo loads are on.  LDS chunk q of a stage
   // holds row q / 2, half (q & 1) ^ swizzle(row), the layout the fragment
@@ -847,7 +812,7 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
   int hstep[NIH];
   auto set_halo = [&](int tile, int grp) {
     const int oy0 = (tile / tiles_x) * TH, ox0 = (tile % tiles_x) * TW;
-    const unsigned char* inb = reinterpret_cast<const unsigned char*>(a.in) + grp * a.in_goff * 2;
+    const unsigned char* inb = reinterpret_cast<const unsigned char*>(a.in) + grp * a.in_goff * ESZ;
 #pragma unroll
     for (int j = 0; j < NIH; ++j) {
       const int q = (j * NWAVES + wave) * 64 + lane;
@@ -858,7 +823,7 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
         const int c = (q & 1) ^ ((row >> 3) & 1);
         const int iy = oy0 - 1 + row / HW, ix = ox0 - 1 + row % HW;
         if (iy >= 0 && ix >= 0 && iy < a.Hin && ix < a.Win) {
-          hsrc[j] = inb + (((long)iy * a.Win + ix) * a.in_pitch + c * 8) * 2;
+          hsrc[j] = inb + ((long)iy * a.Win + ix) * a.in_pitch * ESZ + c * 16;
           hstep[j] = 32;
         }
       }
@@ -948,7 +913,47 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
   };
   zero_acc();
 
-  auto compute_slice = [&](const unsigned char* lh, const unsigned char* lw) {
+  // F8: per lane, the halo offset of its tap in each tap pair
+  int toffp[5];
+#pragma unroll
+  for (int p = 0; p < 5; ++p) {
+    const int t = min(2 * p + khalf, 8);
+    toffp[p] = (t / 3) * HW + (t % 3);
+  }
+  auto compute_slice8 = [&](const unsigned char* lh, const unsigned char* lw) {
+    i32x8 xf[2][FM], wf[2][FN];
+    auto rd32 = [&](const unsigned char* base, int row) {
+      const v4u lo = lds16(base + lds_off<32>(row, 0)), hi = lds16(base + lds_off<32>(row, 1));
+      return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    };
+    auto read_frags = [&](int buf, int p) {
+      const int tap = min(2 * p + khalf, 8);
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn) {
+        wf[buf][fn] = rd32(lw, tap * BN + (wn * FN + fn) * 32 + (lane & 31));
+        // the ninth tap has no partner: zero weights (any halo value then
+        // contributes nothing)
+        if (p == 4 && khalf) wf[buf][fn] = i32x8{0, 0, 0, 0, 0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm) xf[buf][fm] = rd32(lh, xrow[fm] + toffp[p]);
+    };
+    read_frags(0, 0);
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+      const int cur = p & 1;
+      if (p + 1 < 5) read_frags(cur ^ 1, p + 1);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+          // E4M3 x E4M3, block scales 2^0
+          acc[fn][fm] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(wf[cur][fn], xf[cur][fm], acc[fn][fm],
+                                                                       0, 0, 0, 127, 0, 127);
+    }
+  };
+  auto compute_slice16 = [&](const unsigned char* lh, const unsigned char* lw) {
     v4u xf[2][FM], wf[2][FN];
     auto read_frags = [&](int buf, int tap) {
       const int toff = (tap / 3) * HW + (tap % 3);
@@ -972,6 +977,10 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
                                                                __builtin_bit_cast(bf16x8, xf[cur][fm]),
                                                                acc[fn][fm], 0, 0, 0);
     }
+  };
+  auto compute_slice = [&](const unsigned char* lh, const unsigned char* lw) {
+    if constexpr (F8) compute_slice8(lh, lw);
+    else compute_slice16(lh, lw);
   };
 
   // Lane l holds, per block, position (l & 31) and channels
@@ -1006,6 +1015,13 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
           float o[8];
 #pragma unroll
           for (int k = 0; k < 8; ++k) o[k] = v[8 * h + k];
+          if constexpr (F8) {
+            const float* ws = a.wscale + grp * a.cout + n;
+            const v4f s0 = ldg(reinterpret_cast<const v4f*>(ws)), s1 = ldg(reinterpret_cast<const v4f*>(ws + 4));
+            const float sc[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) o[k] *= qscale * sc[k];
+          }
           if constexpr (ST == ST_BF16 || ST == ST_F32) {
             if (a.add) {
               const float* ad = a.add + pos * a.add_pitch + n;
@@ -1112,7 +1128,9 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
     if (a.amax_out) {
       vmax = fmaxf(vmax, 0.f);
       for (int o = 32; o > 0; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
-      if (lane == 0) atomicMax(a.amax_out, __float_as_uint((float)(__bf16)vmax));
+      if (lane == 0)
+        atomicMax(amax_sub(a.amax_out, (blockIdx.x + gridDim.x * blockIdx.y) * NWAVES + wave),
+                  __float_as_uint((float)(__bf16)vmax));
     }
   }
 }
@@ -1179,14 +1197,15 @@ bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int
   if (stride == 2 || cfg == kHyperCfg)
     return cfg == kHyperCfg && stride == 2 && prec == P_F32 && loader == LD_NHWC &&
            (cin == 64 || cin == 128) && cout % 16 == 0;
+  const bool ring = (cfg >= kFirstRing && cfg <= kLastRing) || (cfg >= kFirstRing2 && cfg <= kLastRing2);
+  // FP8 synthesis convs: the ring kernel on a quantised copy of the input
+  if (prec == P_FP8) return ring && loader == LD_NHWC && stride == 1 && cin % 32 == 0;
   if (cfg >= kFirstSplitK && cfg <= kLastSplitK)
     return loader == LD_UNSHUFFLE && (prec == P_BF16 || prec == P_F32) && stride == 1 &&
            cin % (prec == P_BF16 ? 32 : 16) == 0;
   if (loader == LD_UNSHUFFLE) return false;
-  if ((cfg >= kFirstRing && cfg <= kLastRing) || (cfg >= kFirstRing2 && cfg <= kLastRing2))
-    return prec == P_BF16 && loader == LD_NHWC && stride == 1 && cin % 16 == 0;
-  if (cfg >= conv_num_cfgs()) return false;
-  return cfg >= 0 && !(prec == P_FP8 && (cfg == 5 || cfg == 6 || cfg == 8));
+  if (ring) return prec == P_BF16 && loader == LD_NHWC && stride == 1 && cin % 16 == 0;
+  return cfg >= 0 && cfg < conv_num_cfgs();
 }
 
 hipError_t set_lds_limit_once(std::atomic<uint32_t>& done, const void* kern, int bytes) {
@@ -1211,6 +1230,77 @@ __global__ void zero_u32_kernel(uint32_t* p, int n) {
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// One thread per 16 channels of one position: two 16-byte bf16 loads, one
+// 16-byte E4M3 store (a plain HBM stream).
+// The producer's amax: the maximum of its sub-slots (one wave reads them;
+// non-negative float bits order like unsigned integers), written to the
+// slot by the first workgroup.
+__device__ __forceinline__ float q8_amax(const Q8Job& j) {
+  __shared__ unsigned s_amax;
+  if (threadIdx.x < 64) {
+    unsigned v = threadIdx.x < AMAX_SPREAD ? ldg(j.amax + threadIdx.x * AMAX_STRIDE) : 0u;
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o, 64));
+    if (threadIdx.x == 0) {
+      s_amax = v;
+      if (blockIdx.x == 0) stg(j.amax_final, v);
+    }
+  }
+  __syncthreads();
+  return __uint_as_float(s_amax);
+}
+
+__device__ __forceinline__ void q8_units(const Q8Job& j, float amax, long u0, long ustep) {
+  const int per = j.C >> 4;
+  const long units = j.npos * per;
+  float qinv = 1.f;
+  if (amax > 0.f) qinv = 448.f / amax;
+  for (long u = u0; u < units; u += ustep) {
+    const long pos = u / per;
+    const int c0 = (int)(u - pos * per) * 16;
+    const v4u* src = reinterpret_cast<const v4u*>(reinterpret_cast<const __bf16*>(j.src) + pos * j.src_pitch + c0);
+    const bf16x8 b0 = __builtin_bit_cast(bf16x8, ldg(src)), b1 = __builtin_bit_cast(bf16x8, ldg(src + 1));
+    v4u o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bf16x8& bb = k < 2 ? b0 : b1;
+      const int q = (k & 1) * 4;
+      int w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448((float)bb[q] * qinv), sat448((float)bb[q + 1] * qinv), 0,
+                                              false);
+      w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448((float)bb[q + 2] * qinv), sat448((float)bb[q + 3] * qinv), w,
+                                          true);
+      o[k] = (unsigned)w;
+    }
+    stg(reinterpret_cast<v4u*>(reinterpret_cast<uint8_t*>(j.dst) + pos * j.C + c0), o);
+  }
+}
+
+__global__ void __launch_bounds__(256) q8_kernel(Q8Job j) {
+  const float amax = q8_amax(j);
+  q8_units(j, amax, (long)blockIdx.x * 256 + threadIdx.x, (long)gridDim.x * 256);
+}
+
+__global__ void __launch_bounds__(256) q8_batch_kernel(const Q8Job* __restrict__ jobs) {
+  const Q8Job j = jobs[blockIdx.y];
+  const float amax = q8_amax(j);
+  q8_units(j, amax, (long)blockIdx.x * 256 + threadIdx.x, (long)gridDim.x * 256);
+}
+
+hipError_t launch_q8(const Q8Job& j, hipStream_t s) {
+  if (j.C % 16 || j.npos < 0) return hipErrorInvalidValue;
+  const long units = j.npos * (j.C / 16);
+  if (units == 0) return hipSuccess;
+  const long blocks = std::min<long>((units + 255) / 256, 4096);
+  hipLaunchKernelGGL(q8_kernel, dim3((unsigned)blocks), dim3(256), 0, s, j);
+  return hipGetLastError();
+}
+
+hipError_t launch_q8_batch(const Q8Job* jobs, int n, long max_units, hipStream_t s) {
+  if (n <= 0 || max_units <= 0) return hipSuccess;
+  const long blocks = std::min<long>((max_units + 255) / 256, 4096);
+  hipLaunchKernelGGL(q8_batch_kernel, dim3((unsigned)blocks, (unsigned)n), dim3(256), 0, s, jobs);
   return hipGetLastError();
 }
 TileCfg conv_cfg(int c) { return kCfgs[c]; }
@@ -1254,11 +1344,11 @@ static int chip_slots(std::atomic<int>* cache, const void* kern, int threads, in
   return v;
 }
 
-template <int ST, int TH, int TW, int WM, int WN, int FM, int FN, int NH, int NW, bool PERSIST>
+template <int ST, int TH, int TW, int WM, int WN, int FM, int FN, int NH, int NW, bool PERSIST, bool F8>
 static hipError_t run_ring(const ConvArgs& a, int groups, const ConvArgs* descs, const int4* work,
                            int nwork, hipStream_t s) {
   using R = Ring<TH, TW, WM, WN, FM, FN, NH, NW>;
-  auto kern = conv3x3_ring_kernel<ST, TH, TW, WM, WN, FM, FN, NH, NW, PERSIST>;
+  auto kern = conv3x3_ring_kernel<ST, TH, TW, WM, WN, FM, FN, NH, NW, PERSIST, F8>;
   static std::atomic<uint32_t> attr_done{0};
   if (const hipError_t e = set_lds_limit_once(attr_done, reinterpret_cast<const void*>(kern), R::LDS))
     return e;
@@ -1268,7 +1358,7 @@ static hipError_t run_ring(const ConvArgs& a, int groups, const ConvArgs* descs,
     if (nwork <= 0) return hipSuccess;
     grid = dim3(((nwork + 7) / 8) * 8, 1, 1);
   } else {
-    if (a.cout % R::BN || a.cin % 16) return hipErrorInvalidValue;
+    if (a.cout % R::BN || a.cin % (F8 ? 32 : 16)) return hipErrorInvalidValue;
     const int tiles = ((a.Hout + TH - 1) / TH) * ((a.Wout + TW - 1) / TW);
     if constexpr (PERSIST) {
       static std::atomic<int> slots[32];
@@ -1310,30 +1400,24 @@ static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs
       if (cfg == kHyperCfg) return run_hyper(a, groups, d, w, nw, s);
     return hipErrorInvalidValue;
   }
+  if constexpr (PREC != P_FP8) {
   switch (cfg) {
     case 0: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 2>(a, groups, d, w, nw, s);
     case 1: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 4, 1, 1, 1>(a, groups, d, w, nw, s);
     case 2: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 3>(a, groups, d, w, nw, s);
     case 3: return run_conv<PREC, LD, ST, STRIDE, 4, 16, 2, 2, 1, 2>(a, groups, d, w, nw, s);
     case 4: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 2, 2, 2, 1>(a, groups, d, w, nw, s);
-    case 5:
-      // 128x64 per wave with fp8 staging registers does not fit the registers
-      if constexpr (PREC == P_FP8) return hipErrorNotSupported;
-      else return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 2>(a, groups, d, w, nw, s);
-    case 6:
-      // 128x96 per wave with 32-byte fp8 fragments does not fit the registers
-      if constexpr (PREC == P_FP8) return hipErrorNotSupported;
-      else return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 3>(a, groups, d, w, nw, s);
+    case 5: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 2>(a, groups, d, w, nw, s);
+    case 6: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 3>(a, groups, d, w, nw, s);
     case 7: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 2, 2, 4, 1>(a, groups, d, w, nw, s);
-    case 8:
-      if constexpr (PREC == P_FP8) return hipErrorNotSupported;
-      else return run_conv<PREC, LD, ST, STRIDE, 16, 16, 4, 2, 2, 2>(a, groups, d, w, nw, s);
+    case 8: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 4, 2, 2, 2>(a, groups, d, w, nw, s);
     case 9: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 4, 2, 2, 1>(a, groups, d, w, nw, s);
     case 20: return run_conv<PREC, LD, ST, STRIDE, 8, 16, 4, 1, 1, 2>(a, groups, d, w, nw, s);
     case 21: return run_conv<PREC, LD, ST, STRIDE, 16, 16, 4, 1, 2, 2>(a, groups, d, w, nw, s);
     case 22: return run_conv<PREC, LD, ST, STRIDE, 2, 16, 1, 1, 1, 1>(a, groups, d, w, nw, s);
     case 23: return run_conv<PREC, LD, ST, STRIDE, 4, 16, 2, 1, 1, 1>(a, groups, d, w, nw, s);
     default: break;
+  }
   }
   if constexpr (LD == LD_UNSHUFFLE && STRIDE == 1 && (PREC == P_BF16 || PREC == P_F32)) {
     switch (cfg) {
@@ -1342,24 +1426,25 @@ static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs
       default: break;
     }
   }
-  if constexpr (PREC == P_BF16 && LD == LD_NHWC && STRIDE == 1 && ST != ST_ZSYM) {
+  if constexpr ((PREC == P_BF16 || PREC == P_FP8) && LD == LD_NHWC && STRIDE == 1 && ST != ST_ZSYM) {
+    constexpr bool F8 = PREC == P_FP8;
     switch (cfg) {
-      case 10: return run_ring<ST, 16, 16, 2, 2, 4, 2, 3, 2, false>(a, groups, d, w, nw, s);
-      case 11: return run_ring<ST, 8, 16, 2, 2, 2, 2, 3, 2, false>(a, groups, d, w, nw, s);
-      case 12: return run_ring<ST, 8, 16, 2, 2, 2, 1, 3, 2, false>(a, groups, d, w, nw, s);
-      case 13: return run_ring<ST, 16, 16, 2, 2, 4, 1, 3, 2, false>(a, groups, d, w, nw, s);
-      case 14: return run_ring<ST, 16, 16, 4, 2, 2, 2, 3, 2, false>(a, groups, d, w, nw, s);
-      case 15: return run_ring<ST, 16, 16, 2, 2, 4, 3, 3, 2, false>(a, groups, d, w, nw, s);
-      case 16: return run_ring<ST, 8, 16, 2, 2, 2, 3, 3, 2, false>(a, groups, d, w, nw, s);
-      case 17: return run_ring<ST, 8, 16, 4, 1, 1, 1, 3, 2, false>(a, groups, d, w, nw, s);
-      case 18: return run_ring<ST, 16, 16, 4, 1, 2, 2, 3, 2, false>(a, groups, d, w, nw, s);
-      case 19: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 2, false>(a, groups, d, w, nw, s);
-      case 25: return run_ring<ST, 16, 16, 4, 1, 2, 2, 2, 3, true>(a, groups, d, w, nw, s);
-      case 26: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 3, true>(a, groups, d, w, nw, s);
-      case 27: return run_ring<ST, 16, 16, 4, 1, 2, 2, 2, 3, false>(a, groups, d, w, nw, s);
-      case 28: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 3, false>(a, groups, d, w, nw, s);
-      case 29: return run_ring<ST, 16, 16, 4, 1, 2, 2, 3, 2, true>(a, groups, d, w, nw, s);
-      case 30: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 2, true>(a, groups, d, w, nw, s);
+      case 10: return run_ring<ST, 16, 16, 2, 2, 4, 2, 3, 2, false, F8>(a, groups, d, w, nw, s);
+      case 11: return run_ring<ST, 8, 16, 2, 2, 2, 2, 3, 2, false, F8>(a, groups, d, w, nw, s);
+      case 12: return run_ring<ST, 8, 16, 2, 2, 2, 1, 3, 2, false, F8>(a, groups, d, w, nw, s);
+      case 13: return run_ring<ST, 16, 16, 2, 2, 4, 1, 3, 2, false, F8>(a, groups, d, w, nw, s);
+      case 14: return run_ring<ST, 16, 16, 4, 2, 2, 2, 3, 2, false, F8>(a, groups, d, w, nw, s);
+      case 15: return run_ring<ST, 16, 16, 2, 2, 4, 3, 3, 2, false, F8>(a, groups, d, w, nw, s);
+      case 16: return run_ring<ST, 8, 16, 2, 2, 2, 3, 3, 2, false, F8>(a, groups, d, w, nw, s);
+      case 17: return run_ring<ST, 8, 16, 4, 1, 1, 1, 3, 2, false, F8>(a, groups, d, w, nw, s);
+      case 18: return run_ring<ST, 16, 16, 4, 1, 2, 2, 3, 2, false, F8>(a, groups, d, w, nw, s);
+      case 19: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 2, false, F8>(a, groups, d, w, nw, s);
+      case 25: return run_ring<ST, 16, 16, 4, 1, 2, 2, 2, 3, true, F8>(a, groups, d, w, nw, s);
+      case 26: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 3, true, F8>(a, groups, d, w, nw, s);
+      case 27: return run_ring<ST, 16, 16, 4, 1, 2, 2, 2, 3, false, F8>(a, groups, d, w, nw, s);
+      case 28: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 3, false, F8>(a, groups, d, w, nw, s);
+      case 29: return run_ring<ST, 16, 16, 4, 1, 2, 2, 3, 2, true, F8>(a, groups, d, w, nw, s);
+      case 30: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 2, true, F8>(a, groups, d, w, nw, s);
       default: break;
     }
   }
@@ -1383,9 +1468,9 @@ static hipError_t dispatch(int prec, int loader, int store, int stride, int cfg,
   // entropy parameters: float32 weights as three bf16 parts (exact products)
   UFVC_CONV(P_BF16, LD_UP2, ST_F32, 1)
   UFVC_CONV(P_BF16, LD_REP, ST_F32, 1)
-  // fp8 synthesis
-  UFVC_CONV(P_FP8, LD_Q8, ST_BF16, 1)
-  UFVC_CONV(P_FP8, LD_Q8, ST_SHUFFLE, 1)
+  // fp8 synthesis (input quantised beforehand)
+  UFVC_CONV(P_FP8, LD_NHWC, ST_BF16, 1)
+  UFVC_CONV(P_FP8, LD_NHWC, ST_SHUFFLE, 1)
   // float32 everything, plus the hyper prior
   UFVC_CONV(P_F32, LD_UNSHUFFLE, ST_F32, 1)
   UFVC_CONV(P_F32, LD_NHWC, ST_F32, 1)

@@ -30,6 +30,7 @@ struct Workspace {
   void* big0 = nullptr;           // [h][w][T C]
   void* big1 = nullptr;
   float* side = nullptr;          // temporal models: [h][w][2C], a conv of the context
+  uint8_t* q8 = nullptr;          // FP8 synthesis: a layer's quantised input, [h][w][T C]
 };
 
 struct RansWs {
@@ -105,10 +106,12 @@ static const char* kStageNames[S_COUNT] = {
 
 
 namespace ufvc {
-inline int default_cfg(int cout, long npos, int stride = 1, int loader = -1) {
+inline int default_cfg(int cout, long npos, int stride = 1, int loader = -1, int prec = -1) {
   if (stride == 2) return kHyperCfg;
   // the patchify loader runs split over K (its only configurations)
   if (loader == LD_UNSHUFFLE) return 31;
+  // FP8 convs run on the ring kernel only (16x16 or 8x16 tiles, 64 channels)
+  if (prec == P_FP8) return npos >= 16384 ? 18 : 19;
   if (cout % 128 == 0) return npos >= 16384 ? 5 : 0;
   if (cout % 192 == 0) return 2;
   if (cout % 64 == 0) return 4;
@@ -123,8 +126,15 @@ inline int act_elem_size(int prec) { return prec == UFVC_FP32 ? 4 : 2; }
 inline int conv_prec(int prec) { return prec == UFVC_FP32 ? P_F32 : P_BF16; }
 // d2, d3 and the frame heads; d1 (which dequantises the latent) stays at conv_prec
 inline int synth_prec(int prec) { return prec == UFVC_BF16_FP8 ? P_FP8 : conv_prec(prec); }
-// amax slots of the fp8 synthesis chain: outputs of d1, d2, d3, k1, k2
+// amax slots of the fp8 synthesis chain: outputs of d1, d2, d3, k1, k2.
+// Per context (or batch chunk) AMAX_WORDS words: the N_AMAX slots, then each
+// slot's sub-slots, which its producer's waves fill and the quantise pass
+// that consumes the slot reduces into it.
 constexpr int N_AMAX = 8;
+constexpr int AMAX_WORDS = N_AMAX * (1 + AMAX_SPREAD * AMAX_STRIDE);
+inline uint32_t* amax_spread(uint32_t* base, int k) {
+  return base + N_AMAX + (size_t)k * AMAX_SPREAD * AMAX_STRIDE;
+}
 
 inline int nseg_of(long n, int sl) { return n == 0 ? 0 : (int)((n + (1L << sl) - 1) >> sl); }
 inline size_t slot_bytes(int sl) { return (size_t)SEG_STATE_BYTES + 2 * ((size_t)1 << sl); }
