@@ -1177,6 +1177,12 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
 //   takes these and only these, so its results never depend on the choice):
 //     31 = 8x16 tile,  64 channels, 2 groups of 2x1 waves of 64x64
 //     32 = 8x16 tile, 128 channels, 2 groups of 2x2 waves of 64x64
+//   ring kernel with one slice of lookahead per stream and small stages, so
+//   that three (33, 34) or four (35, 36) workgroups share a CU:
+//     33 = 8x16 tile,  64 channels, 4x1 waves of 32x64
+//     34 = 8x16 tile,  64 channels, 4x1 waves of 32x64; P
+//     35 = 16x16 tile, 32 channels, 4x1 waves of 64x32
+//     36 = 16x16 tile, 32 channels, 4x1 waves of 64x32; P
 static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 16, 128},
                                 {8, 16, 64},  {16, 16, 128}, {16, 16, 192}, {16, 16, 64},
                                 {16, 16, 128}, {16, 16, 64},
@@ -1187,9 +1193,10 @@ static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 1
                                 {1, 16, 16},
                                 {16, 16, 64}, {8, 16, 64}, {16, 16, 64}, {8, 16, 64},
                                 {16, 16, 64}, {8, 16, 64},
-                                {8, 16, 64}, {8, 16, 128}};
+                                {8, 16, 64}, {8, 16, 128},
+                                {8, 16, 64}, {8, 16, 64}, {16, 16, 32}, {16, 16, 32}};
 constexpr int kFirstRing = 10, kLastRing = 19, kFirstRing2 = 25, kLastRing2 = 30;
-constexpr int kFirstSplitK = 31, kLastSplitK = 32;
+constexpr int kFirstSplitK = 31, kLastSplitK = 32, kFirstRing3 = 33, kLastRing3 = 36;
 int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int cfg) {
   // stride 2 (the hyper conv) has the one configuration, so its results
@@ -1197,7 +1204,8 @@ bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int
   if (stride == 2 || cfg == kHyperCfg)
     return cfg == kHyperCfg && stride == 2 && prec == P_F32 && loader == LD_NHWC &&
            (cin == 64 || cin == 128) && cout % 16 == 0;
-  const bool ring = (cfg >= kFirstRing && cfg <= kLastRing) || (cfg >= kFirstRing2 && cfg <= kLastRing2);
+  const bool ring = (cfg >= kFirstRing && cfg <= kLastRing) || (cfg >= kFirstRing2 && cfg <= kLastRing2) ||
+                    (cfg >= kFirstRing3 && cfg <= kLastRing3);
   // FP8 synthesis convs: the ring kernel on a quantised copy of the input
   if (prec == P_FP8) return ring && loader == LD_NHWC && stride == 1 && cin % 32 == 0;
   if (cfg >= kFirstSplitK && cfg <= kLastSplitK)
@@ -1445,6 +1453,10 @@ static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs
       case 28: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 3, false, F8>(a, groups, d, w, nw, s);
       case 29: return run_ring<ST, 16, 16, 4, 1, 2, 2, 3, 2, true, F8>(a, groups, d, w, nw, s);
       case 30: return run_ring<ST, 8, 16, 4, 1, 1, 2, 3, 2, true, F8>(a, groups, d, w, nw, s);
+      case 33: return run_ring<ST, 8, 16, 4, 1, 1, 2, 2, 2, false, F8>(a, groups, d, w, nw, s);
+      case 34: return run_ring<ST, 8, 16, 4, 1, 1, 2, 2, 2, true, F8>(a, groups, d, w, nw, s);
+      case 35: return run_ring<ST, 16, 16, 4, 1, 2, 1, 2, 2, false, F8>(a, groups, d, w, nw, s);
+      case 36: return run_ring<ST, 16, 16, 4, 1, 2, 1, 2, 2, true, F8>(a, groups, d, w, nw, s);
       default: break;
     }
   }
