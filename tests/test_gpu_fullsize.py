@@ -228,3 +228,29 @@ def test_fullsize_4k_whole_chunk_bf16():
     (err, ps), _ = run_chunk("bf16", fr, w, H4, W4, "4K", 0x0800_2160)
     _CACHE.pop("4K", None)
     assert ps >= 40 and err <= 0.1
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16_fp8"])
+def test_every_tile_configuration_at_1080p(prec):
+    """Each tile configuration, forced on every layer that supports it at the
+    full 1080p T = 8 shape, gives the default configuration's stream and
+    frames bit for bit.  At this size the persistent ring forms' workgroups
+    each walk several work items with the slice pipeline running across item
+    boundaries (thousands of items over the few hundred resident
+    workgroups), which the small shapes of the parity tests do not reach."""
+    u = pkg()
+    say(f"every tile configuration at 1080p: {prec}")
+    fr = torch.from_numpy(video_chunk(T, H, W, 16, seed=3)).cuda()
+    c = u.Codec(T, C, stand_in_weights(T, C), precision=prec, seg_log2=12, seg_log2_z=10, model_tag=5)
+    try:
+        bs, n = c.encode(fr)
+        ref_bs = bs[:n].clone()
+        ref_fr = c.decode(bs, n, H, W).clone()
+        for cfg in range(u.lib.ufvc_num_tile_configs()):
+            c.force_tile_config(cfg)
+            bs, n = c.encode(fr)
+            assert n == ref_bs.numel() and torch.equal(bs[:n], ref_bs), cfg
+            assert torch.equal(c.decode(ref_bs, n, H, W), ref_fr), cfg
+        say(f"  {u.lib.ufvc_num_tile_configs()} configurations identical")
+    finally:
+        c.close()
