@@ -315,8 +315,9 @@ int ufvc_dcblock_run(ufvc_dcblock* b, const uint16_t* x, uint16_t* y, int h, int
  * tile configuration, instead of one launch per chunk and stage.  All models
  * must share C, precision and segment sizes.  Per batch composition (the
  * list of (model, H, W)) the object keeps a device arena and fixed-address
- * work lists; with use_graph the decode of a composition is captured once
- * into a hipGraph and replayed.  Results are bitwise identical to the
+ * work lists; with use_graph the decode of a composition is captured into
+ * a hipGraph when the composition recurs (its first decode runs eagerly) and
+ * replayed from then on.  Results are bitwise identical to the
  * single-chunk calls.  Calls on one batch object must use one stream. */
 typedef struct ufvc_batch ufvc_batch;
 typedef struct {
@@ -359,9 +360,9 @@ int ufvc_batch_stats(ufvc_batch* b, uint64_t* stats, int n);
  * stream (default priority) and a batch object; whenever a lane is free it
  * forms the next batch from the queue in arrival order: the head request's
  * kind, then further queued requests of that kind, up to `max_batch`, while
- * (a) the chunks' working arena fits the lane's share of the HBM budget
- * (hbm_budget / lanes) and (b) the HBM footprint of all admitted, unfinished
- * requests stays within hbm_budget.  A request's footprint is its working
+ * (a) the chunks' working arena fits the lane's arena and (b) the HBM
+ * footprint of all admitted, unfinished requests stays within hbm_budget
+ * less the lanes' descriptor slabs.  A request's footprint is its working
  * arena plus its own device buffers (input and output).  Batches of
  * different lanes run concurrently on the device, so requests that arrive
  * while others are on the GPU join the next batch as lanes and memory free
@@ -376,9 +377,11 @@ int ufvc_batch_stats(ufvc_batch* b, uint64_t* stats, int n);
  * had finished. */
 typedef struct ufvc_server ufvc_server;
 typedef struct {
-  size_t hbm_budget;    /* bytes; 0 selects 64 GiB.  Each lane's working arena
-                           (hbm_budget / lanes) is allocated at creation, so
-                           nothing grows on the request path */
+  size_t hbm_budget;    /* bytes; 0 selects 64 GiB.  Each lane's share
+                           (hbm_budget / lanes) is allocated at creation: a
+                           slab for batch plans' descriptors (1/16 of the share,
+                           at most 64 MiB) and the working arena (the rest), so
+                           nothing is allocated on the request path */
   int lanes;            /* 1..8 concurrent batches */
   int max_batch;        /* 1..64 chunks per batch */
   int use_graph;        /* decode batches replay a captured hipGraph */
@@ -420,7 +423,8 @@ int ufvc_server_poll(ufvc_server* s, ufvc_completion* out, int max, int timeout_
 /* stats[0] requests queued, [1] in flight, [2] completed, [3] batches run,
  * [4] peak admitted footprint (bytes), [5] HBM budget (bytes), [6] batch
  * plans built so far (all lanes; a plan is built for each new batch
- * composition, cached up to 32 per lane), [7] lane arena bytes allocated. */
+ * composition, cached up to 32 per lane), [7] device bytes reserved for
+ * the lanes at creation (arenas and descriptor slabs: the budget). */
 int ufvc_server_stats(ufvc_server* s, uint64_t* stats, int n);
 /* Finishes every queued and in-flight request, then frees the server
  * (unpolled completions are dropped). */

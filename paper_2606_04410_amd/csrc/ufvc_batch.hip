@@ -59,6 +59,8 @@ struct ufvc_batch {
     bool owns_arena = true;        // false: the batch object's shared arena
     // descriptor blob (device) and its host mirror
     uint8_t* dblob = nullptr;
+    size_t blob_bytes = 0;         // dblob's size
+    bool blob_pooled = false;      // dblob lies in the batch object's slab
     std::vector<uint8_t> hblob;
     size_t off_conv = 0, off_work = 0, off_epi_e = 0, off_epi_d = 0, off_epi_work = 0,
            off_encseg = 0, off_comp = 0, off_compmap = 0, off_parse = 0, off_decz = 0, off_decy = 0,
@@ -73,7 +75,7 @@ struct ufvc_batch {
     // call-varying descriptor indices (in units of the descriptor tables)
     std::vector<int> a1_desc, k3_desc;
     // decode graph
-    bool graph_ok = false;
+    uint64_t decodes = 0;          // decode calls so far (the graph is captured from the second)
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     uint64_t last_use = 0;         // LRU stamp
@@ -100,6 +102,14 @@ struct ufvc_batch {
   size_t arena_cap = 0;
   uint8_t* shared = nullptr;
   size_t shared_bytes = 0;
+  // descriptor-blob slab (reserved with the arena): plans' descriptor blobs
+  // are carved from it first-fit (offset -> bytes of each free range), so a
+  // new batch composition allocates nothing on the request path; a blob
+  // that does not fit even after evicting every other plan gets its own
+  // allocation
+  uint8_t* blob_slab = nullptr;
+  size_t blob_cap = 0;
+  std::map<size_t, size_t> blob_free;
 };
 
 namespace {
@@ -107,12 +117,69 @@ namespace {
 template <class T>
 T* at(uint8_t* base, size_t off) { return reinterpret_cast<T*>(base + off); }
 
-void free_plan(ufvc_batch::Plan* p) {
+void free_plan(ufvc_batch* b, ufvc_batch::Plan* p) {
   if (!p) return;
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->arena && p->owns_arena) (void)hipFree(p->arena);
-  if (p->dblob) (void)hipFree(p->dblob);
+  if (p->dblob && !p->blob_pooled) (void)hipFree(p->dblob);
+  if (p->dblob && p->blob_pooled) {
+    // back to the slab's free ranges, merged with its neighbours
+    size_t off = (size_t)(p->dblob - b->blob_slab), len = p->blob_bytes;
+    auto nx = b->blob_free.lower_bound(off);
+    if (nx != b->blob_free.end() && off + len == nx->first) {
+      len += nx->second;
+      nx = b->blob_free.erase(nx);
+    }
+    if (nx != b->blob_free.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        pv->second += len;
+        return;
+      }
+    }
+    b->blob_free[off] = len;
+  }
+}
+
+// Drops the least recently used plan, after its last call on stream s has
+// finished with its descriptors and graph.
+hipError_t evict_lru(ufvc_batch* b, hipStream_t s) {
+  auto lru = b->plans.begin();
+  for (auto j = b->plans.begin(); j != b->plans.end(); ++j)
+    if (j->second->last_use < lru->second->last_use) lru = j;
+  const hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  if (b->last_plan == lru->second.get()) b->last_plan = nullptr;
+  free_plan(b, lru->second.get());
+  b->plans.erase(lru);
+  b->plans_evicted += 1;
+  return hipSuccess;
+}
+
+// Device memory for a plan's descriptor blob: first fit in the slab,
+// evicting least recently used plans while none fits; otherwise (no slab,
+// or a blob larger than what the slab can free) an allocation of its own.
+int alloc_blob(ufvc_batch* b, ufvc_batch::Plan& P, size_t bytes, hipStream_t s) {
+  bytes = align_up(bytes);
+  P.blob_bytes = bytes;
+  if (b->blob_slab && bytes <= b->blob_cap) {
+    for (;;) {
+      for (auto it = b->blob_free.begin(); it != b->blob_free.end(); ++it) {
+        if (it->second < bytes) continue;
+        const size_t off = it->first, rest = it->second - bytes;
+        b->blob_free.erase(it);
+        if (rest) b->blob_free[off + bytes] = rest;
+        P.dblob = b->blob_slab + off;
+        P.blob_pooled = true;
+        return UFVC_OK;
+      }
+      if (b->plans.empty()) break;
+      CK(evict_lru(b, s));
+    }
+  }
+  if (hipMalloc(&P.dblob, bytes) != hipSuccess) return UFVC_E_NOMEM;
+  return UFVC_OK;
 }
 
 ConvArgs conv_of(int Hin, int Win, int Hout, int Wout, const Layer& L) {
@@ -197,7 +264,7 @@ int plan_arena(ufvc_batch* b, ufvc_batch::Plan& P) {
   if (P.arena_bytes > b->arena_cap) return UFVC_E_NOSPC;
   if (P.arena_bytes > b->shared_bytes) {
     (void)hipDeviceSynchronize();
-    for (auto& kv : b->plans) free_plan(kv.second.get());
+    for (auto& kv : b->plans) free_plan(b, kv.second.get());
     b->plans.clear();
     if (b->shared) (void)hipFree(b->shared);
     b->shared = nullptr;
@@ -211,7 +278,7 @@ int plan_arena(ufvc_batch* b, ufvc_batch::Plan& P) {
   return UFVC_OK;
 }
 
-int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan& P) {
+int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan& P, hipStream_t s) {
   ufvc_ctx* m0 = b->models[0];
   const int C = m0->cfg.C;
   const int sl = m0->cfg.seg_log2, slz = m0->cfg.seg_log2_z;
@@ -490,7 +557,7 @@ int build_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, ufvc_batch::Plan&
   P.off_result = place(8 * (size_t)n);
   if (q8) P.off_q8 = place(sizeof(Q8Job) * 5 * (size_t)n);
   P.hblob.assign(bo, 0);
-  if (hipMalloc(&P.dblob, bo) != hipSuccess) return UFVC_E_NOMEM;
+  if (const int rc = alloc_blob(b, P, bo, s)) return rc;
   uint8_t* H = P.hblob.data();
   uint8_t* D = P.dblob;
   uint32_t* dstatus = at<uint32_t>(D, P.off_status);
@@ -656,16 +723,7 @@ int get_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, hipStream_t s, ufvc
   }
   // bounded cache: the least recently used plan goes (after its last call on
   // this stream has finished with its descriptors and graph)
-  if (b->plans.size() >= kMaxPlans) {
-    auto lru = b->plans.begin();
-    for (auto j = b->plans.begin(); j != b->plans.end(); ++j)
-      if (j->second->last_use < lru->second->last_use) lru = j;
-    CK(hipStreamSynchronize(s));
-    if (b->last_plan == lru->second.get()) b->last_plan = nullptr;
-    free_plan(lru->second.get());
-    b->plans.erase(lru);
-    b->plans_evicted += 1;
-  }
+  if (b->plans.size() >= kMaxPlans) CK(evict_lru(b, s));
   // tuning runs single-chunk calls on the shared model contexts, and plans
   // read their tuning maps: one plan build at a time across batch objects
   static std::mutex build_mu;
@@ -675,9 +733,9 @@ int get_plan(ufvc_batch* b, const ufvc_chunk* chunks, int n, hipStream_t s, ufvc
   std::unique_ptr<ufvc_batch::Plan> P(new (std::nothrow) ufvc_batch::Plan());
   if (!P) return UFVC_E_NOMEM;
   P->key = key;
-  rc = build_plan(b, chunks, n, *P);
+  rc = build_plan(b, chunks, n, *P, s);
   if (rc) {
-    free_plan(P.get());
+    free_plan(b, P.get());
     return rc;
   }
   if (b->host_cap < n) {
@@ -706,10 +764,23 @@ int batch_set_arena_cap(ufvc_batch* b, size_t cap) {
   return UFVC_OK;
 }
 
-int batch_reserve_arena(ufvc_batch* b) {
-  if (!b || !b->arena_cap || b->shared) return UFVC_E_INVAL;
+int batch_reserve_arena(ufvc_batch* b, int max_batch, size_t blob_bytes) {
+  if (!b || !b->arena_cap || b->shared || b->blob_slab || max_batch < 1) return UFVC_E_INVAL;
   if (hipMalloc(&b->shared, b->arena_cap) != hipSuccess) return UFVC_E_NOMEM;
   b->shared_bytes = b->arena_cap;
+  blob_bytes = blob_bytes / ALIGN * ALIGN;
+  if (blob_bytes) {
+    if (hipMalloc(&b->blob_slab, blob_bytes) != hipSuccess) return UFVC_E_NOMEM;
+    b->blob_cap = blob_bytes;
+    b->blob_free[0] = blob_bytes;
+    // pinned staging for any blob the slab can hold
+    if (hipHostMalloc(&b->staging, blob_bytes) != hipSuccess) return UFVC_E_NOMEM;
+    b->staging_bytes = blob_bytes;
+  }
+  if (hipHostMalloc(&b->results_host, 8 * (size_t)max_batch) != hipSuccess ||
+      hipHostMalloc(&b->status_host, 4 * (size_t)max_batch) != hipSuccess)
+    return UFVC_E_NOMEM;
+  b->host_cap = max_batch;
   return UFVC_OK;
 }
 
@@ -754,7 +825,7 @@ int ufvc_batch_set_policy(ufvc_batch* b, int policy) {
   if (!b || (policy != 0 && policy != 1)) return UFVC_E_INVAL;
   if (policy == b->policy) return UFVC_OK;
   CK(hipDeviceSynchronize());
-  for (auto& kv : b->plans) free_plan(kv.second.get());
+  for (auto& kv : b->plans) free_plan(b, kv.second.get());
   b->plans.clear();
   b->last_plan = nullptr;
   b->policy = policy;
@@ -775,8 +846,9 @@ int ufvc_batch_stats(ufvc_batch* b, uint64_t* stats, int n) {
 void ufvc_batch_destroy(ufvc_batch* b) {
   if (!b) return;
   (void)hipDeviceSynchronize();
-  for (auto& kv : b->plans) free_plan(kv.second.get());
+  for (auto& kv : b->plans) free_plan(b, kv.second.get());
   if (b->shared) (void)hipFree(b->shared);
+  if (b->blob_slab) (void)hipFree(b->blob_slab);
   if (b->staging) (void)hipHostFree(b->staging);
   if (b->results_host) (void)hipHostFree(b->results_host);
   if (b->status_host) (void)hipHostFree(b->status_host);
@@ -827,7 +899,11 @@ int ufvc_decode_batch(ufvc_batch* b, ufvc_chunk* chunks, int n, int use_graph, v
   if (rc) return rc;
   rc = upload(b, *P, chunks, n, false, s);
   if (rc) return rc;
-  if (!use_graph) {
+  // a composition's first decode runs eagerly; the graph is captured when it
+  // recurs, so one-off compositions (common in serving) never pay the
+  // capture and instantiation on the request path
+  const bool first = P->decodes++ == 0;
+  if (!use_graph || (first && !P->gexec)) {
     CK(run_decode(b, *P, s));
     return UFVC_OK;
   }

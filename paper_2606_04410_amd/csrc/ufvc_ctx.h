@@ -189,6 +189,10 @@ int batch_set_arena_cap(ufvc_batch* b, size_t cap);
 size_t batch_chunk_footprint(ufvc_ctx* c, int H, int W);
 // Shared-arena mode: allocates the whole capped arena now, so it never grows
 // (or drops plans) on a request path.
-int batch_reserve_arena(ufvc_batch* b);
+// Reserves the arena (capped by batch_set_arena_cap), a slab of blob_bytes
+// for plans' descriptor blobs with pinned staging of that size, and host
+// result arrays for max_batch chunks, so that the batch object's calls
+// allocate nothing for compositions whose descriptors fit the slab.
+int batch_reserve_arena(ufvc_batch* b, int max_batch, size_t blob_bytes);
 // Plans built so far by a batch object.
 uint64_t batch_plans_built(const ufvc_batch* b);

@@ -37,7 +37,9 @@ struct ufvc_server {
   };
   std::vector<ufvc_ctx*> models;
   ufvc_server_config cfg{};
-  size_t lane_cap = 0;
+  size_t lane_cap = 0;      // a lane's arena
+  size_t blob_cap = 0;      // a lane's descriptor-blob slab
+  size_t req_budget = 0;    // the budget less the lanes' slabs: admitted request footprints
   int device = 0;
   std::vector<Lane> lanes;
   std::mutex mu;
@@ -85,7 +87,7 @@ std::vector<ufvc_server::Req> take_batch(ufvc_server* S, int li) {
       ++it;
       continue;
     }
-    if (arena + it->arena > S->lane_cap || S->in_flight_bytes + foot + it->footprint > S->cfg.hbm_budget) {
+    if (arena + it->arena > S->lane_cap || S->in_flight_bytes + foot + it->footprint > S->req_budget) {
       if (out.empty()) return out;   // the oldest request waits for memory
       break;
     }
@@ -201,7 +203,12 @@ int ufvc_server_create(ufvc_ctx* const* models, int n_models, const ufvc_server_
   S->models.assign(models, models + n_models);
   S->cfg = *cfg;
   if (!S->cfg.hbm_budget) S->cfg.hbm_budget = kDefaultBudget;
-  S->lane_cap = S->cfg.hbm_budget / (size_t)S->cfg.lanes;
+  // each lane's share of the budget: a descriptor-blob slab (1/16 of the
+  // share, at most 64 MiB), the rest its arena
+  const size_t share = S->cfg.hbm_budget / (size_t)S->cfg.lanes;
+  S->blob_cap = std::min<size_t>(share / 16, 64ull << 20) & ~(size_t)4095;
+  S->lane_cap = share - S->blob_cap;
+  S->req_budget = S->cfg.hbm_budget - S->blob_cap * (size_t)S->cfg.lanes;
   S->device = models[0]->device;
   S->t0 = std::chrono::steady_clock::now();
   S->lanes.resize(cfg->lanes);
@@ -213,9 +220,10 @@ int ufvc_server_create(ufvc_ctx* const* models, int n_models, const ufvc_server_
     }
     if ((rc = ufvc_batch_create(models, n_models, &L.batch)) != UFVC_OK) break;
     if ((rc = batch_set_arena_cap(L.batch, S->lane_cap)) != UFVC_OK) break;
-    // the lane's whole share now: no arena growth (nor plan loss) on the
+    // the lane's whole share now (arena, descriptor slab, staging, host
+    // result arrays): no allocation, arena growth or plan loss on the
     // request path
-    if ((rc = batch_reserve_arena(L.batch)) != UFVC_OK) break;
+    if ((rc = batch_reserve_arena(L.batch, S->cfg.max_batch, S->blob_cap)) != UFVC_OK) break;
   }
   if (rc != UFVC_OK) {
     for (auto& L : S->lanes) {
@@ -247,7 +255,7 @@ int ufvc_server_submit(ufvc_server* S, const ufvc_request* req, uint64_t* ticket
     if (!r.frames_out || !r.bitstream || r.len < 28 || r.len > 0xFFFFFFF0ull) return UFVC_E_INVAL;
     io = frame_bytes + r.len;
   }
-  if (arena > S->lane_cap || arena + io > S->cfg.hbm_budget) return UFVC_E_NOSPC;
+  if (arena > S->lane_cap || arena + io > S->req_budget) return UFVC_E_NOSPC;
   ufvc_server::Req q;
   q.r = r;
   q.arena = arena;
@@ -283,7 +291,8 @@ int ufvc_server_stats(ufvc_server* S, uint64_t* stats, int n) {
   uint64_t built = 0;
   for (const auto& L : S->lanes) built += batch_plans_built(L.batch);
   const uint64_t v[8] = {S->queue.size(), S->n_in_flight, S->n_completed, S->n_batches,
-                         S->peak_bytes, S->cfg.hbm_budget, built, S->lane_cap * S->lanes.size()};
+                         S->peak_bytes, S->cfg.hbm_budget, built,
+                         (S->lane_cap + S->blob_cap) * S->lanes.size()};
   for (int i = 0; i < n && i < 8; ++i) stats[i] = v[i];
   return UFVC_OK;
 }
