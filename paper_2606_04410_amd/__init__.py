@@ -13,6 +13,15 @@ import os
 
 import numpy as np
 
+try:
+    # PyTorch carries its own HIP runtime; loaded first, it is the one the
+    # library binds to as well, so torch's device memory and streams and the
+    # library's calls share one runtime whichever module the caller imports
+    # first.
+    import torch  # noqa: F401
+except ImportError:  # the library alone (host-side calls, symbol checks)
+    pass
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libufvc.so")
 
