@@ -212,6 +212,12 @@ void add_stage(ufvc_batch::Plan& P, ConvStage& st, std::vector<ConvArgs>& descs,
     for (int i : kv.second) {
       const ConvArgs& a = per_chunk[i];
       const int tiles = ((a.Hout + t.th - 1) / t.th) * ((a.Wout + t.tw - 1) / t.tw);
+      if (kv.first == kParamsCfg0 || kv.first == kParamsCfg1) {
+        // the entropy-parameter kernel: channel blocks of a tile adjacent
+        for (int tile = 0; tile < tiles; ++tile)
+          for (int n0 = 0; n0 < a.cout; n0 += t.bn) work.push_back(make_int4(st.desc0 + i, tile, n0, 0));
+        continue;
+      }
       for (int g = 0; g < groups[i]; ++g)
         for (int n0 = 0; n0 < a.cout; n0 += t.bn)
           for (int tile = 0; tile < tiles; ++tile) work.push_back(make_int4(st.desc0 + i, tile, n0, g));

@@ -215,6 +215,45 @@ static int upload_split_layer(Layer& L, const float* W, int cout, int cin) {
   return upload_layer(L, {parts.data()}, cout, 3 * cin, P_BF16);
 }
 
+// Entropy-parameter conv weights for params_up2_kernel.  Over up2(z_hat),
+// output (2qy + py, 2qx + px) reads z_hat rows qy - 1 + py + r (r = 0, 1),
+// row r collecting kernel rows first[py][r] .. last[py][r] (py = 0: r = 0 <-
+// dy 0, r = 1 <- dy 1, 2; py = 1: r = 0 <- dy 0, 1, r = 1 <- dy 2), columns
+// likewise.  Per class (py, px) and 2x2 tap (r, q) the summed weight (in
+// double) is split into three bf16 parts; layout [class][tap][part][cout][cin]
+// with cin = 32.
+static int upload_params_layer(Layer& L, const float* W, int cout, int cin) {
+  if (cin != 32 || cout % 64) return UFVC_E_UNSUPPORTED;
+  static const int first[2][2] = {{0, 1}, {0, 2}}, last[2][2] = {{0, 2}, {1, 2}};   // [parity][r]
+  std::vector<__bf16> pk((size_t)4 * 4 * 3 * cout * cin);
+  for (int cls = 0; cls < 4; ++cls) {
+    const int py = cls >> 1, px = cls & 1;
+    for (int t = 0; t < 4; ++t) {
+      const int r = t >> 1, q = t & 1;
+      for (int n = 0; n < cout; ++n)
+        for (int ci = 0; ci < cin; ++ci) {
+          double w = 0.0;
+          for (int dy = first[py][r]; dy <= last[py][r]; ++dy)
+            for (int dx = first[px][q]; dx <= last[px][q]; ++dx) w += (double)W[((size_t)n * cin + ci) * 9 + dy * 3 + dx];
+          const double h = (double)(float)(__bf16)(float)w;
+          const double m = (double)(float)(__bf16)(float)(w - h);
+          const double l = (double)(float)(__bf16)(float)(w - h - m);
+          const double part[3] = {h, m, l};
+          for (int p = 0; p < 3; ++p)
+            pk[((((size_t)cls * 4 + t) * 3 + p) * cout + n) * cin + ci] = (__bf16)(float)part[p];
+        }
+    }
+  }
+  if (hipMalloc(&L.w, pk.size() * 2) != hipSuccess) return UFVC_E_NOMEM;
+  CK(hipMemcpy(L.w, pk.data(), pk.size() * 2, hipMemcpyHostToDevice));
+  L.gstride = (long)pk.size() * 2;
+  L.cin = cin;
+  L.cout = cout;
+  L.groups = 1;
+  L.prec = P_BF16;
+  return UFVC_OK;
+}
+
 // Hyper conv weights for hyper_conv_kernel: OIHW float32 [cout][cin][3][3]
 // to [tap][cin / 4][cout][4] (four consecutive input channels per 16 bytes).
 static int upload_hyper_layer(Layer& L, const float* W, int cout, int cin) {
@@ -543,7 +582,7 @@ int ufvc_create(const ufvc_config* cfg, const float* weights, size_t n_weights, 
   if (!rc) rc = upload_layer(c->a2, {wa2}, C, C, cp);
   if (!rc) rc = upload_layer(c->a3, {wa3}, C, C, cp);
   if (!rc) rc = upload_hyper_layer(c->h, wh, ZC, C);
-  if (!rc) rc = upload_split_layer(c->p, wp, 2 * C, ZC);
+  if (!rc) rc = upload_params_layer(c->p, wp, 2 * C, ZC);
   if (!rc) rc = upload_layer(c->d1, {wd1}, C, C, cp);
   if (!rc) rc = upload_layer(c->d2, {wd2}, C, C, sp);
   if (!rc) rc = upload_layer(c->d3, {wd3}, C, C, sp);

@@ -63,8 +63,8 @@ enum Loader {
   LD_NHWC = 0,       // activation tensor, channels innermost, compute type
   LD_UNSHUFFLE = 1,  // float32 frames [T][3][H][W], pixel-unshuffle x8 + replicate pad
   LD_DEQUANT = 2,    // y_hat = (sym - 32) + mu from uint8 symbols and float32 mu
-  LD_UP2 = 3,        // nearest x2 upsampling of uint8 z symbols (value sym - 32), bf16;
-                     // input channel c is symbol channel c mod in_pitch
+  LD_UP2 = 3,        // nearest x2 upsampling of uint8 z symbols (value sym - 32): the
+                     // entropy-parameter conv (params_up2_kernel, its own configurations)
   LD_F32 = 4,        // float32 tensor, channels innermost, feeding a bf16 conv
   LD_REP = 6         // bf16 tensor, channels innermost; input channel c is tensor channel
                      // c mod in_pitch (the split-weight convs over a bf16 input)
@@ -126,6 +126,9 @@ hipError_t launch_conv_batch(int prec, int loader, int store, int stride, int cf
 // Tile configurations: output rows x cols per workgroup and channel tile.
 struct TileCfg { int th, tw, bn; };
 constexpr int kHyperCfg = 24;   // the stride-2 hyper conv's configuration (its own kernel)
+// the entropy-parameter conv's two configurations (its own kernel; 4 x 16 or
+// 4 x 24 hyper-latent positions, i.e. 8 x 32 or 8 x 48 outputs, 64 channels)
+constexpr int kParamsCfg0 = 37, kParamsCfg1 = 38;
 int conv_num_cfgs();
 TileCfg conv_cfg(int cfg);
 // false for tile configurations a layer cannot use (precision, loader,

@@ -143,13 +143,8 @@ __device__ __forceinline__ Raw fetch_raw(const ConvArgs& a, const unsigned char*
     static_assert(PREC == P_BF16, "the repeating loader feeds bf16 split-weight convs");
     const int c0 = (slice * E + ch * (E / 2)) % (int)a.in_pitch;
     r.a = ld16(inb + (pos * a.in_pitch + c0) * ESZ);
-  } else {  // LD_UP2: input channel c reads symbol channel c mod in_pitch
-    static_assert(PREC == P_BF16, "up2 loader feeds the bf16 split-weight conv");
-    const int c0 = (slice * E + ch * (E / 2)) % (int)a.in_pitch;
-    const int wz = (a.Win + 1) >> 1;
-    const unsigned char* sp = reinterpret_cast<const unsigned char*>(a.in) +
-                              ((long)(iy >> 1) * wz + (ix >> 1)) * a.in_pitch + c0;
-    r.c = ldg(reinterpret_cast<const v2u*>(sp));
+  } else {
+    static_assert(LD == LD_NHWC, "loader without a first-family form");
   }
   return r;
 }
@@ -200,15 +195,6 @@ __device__ __forceinline__ v4u convert_raw(const Raw& r) {
       f[3] = (float)((int)(sb >> 24) - 32) + m.w;
       o = __builtin_bit_cast(v4u, f);
     }
-  } else {  // LD_UP2: symbols -32..32 are exact in bf16
-    const v2u sb = r.c;
-    float v[8];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      v[k] = (float)((int)((sb.x >> (8 * k)) & 255) - 32);
-      v[4 + k] = (float)((int)((sb.y >> (8 * k)) & 255) - 32);
-    }
-    o = cvt8(v);
   }
   return r.ok ? o : zero16();
 }
@@ -370,6 +356,156 @@ hyper_conv_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4* _
   for (int r = 0; r < 4; ++r) {
     const int px = ox0 + 4 * g + r;
     if (px < a.Wout) store_out<ST_ZSYM>(a, 0, oy, px, n0 + (lane & 15), acc[r]);
+  }
+}
+
+// ------------------------------------------- entropy-parameter conv ----
+// The entropy parameters are a 3x3 conv (zero padding 1) over the nearest x2
+// upsampling of z_hat (Sec. 3.4).  Output (2qy + py, 2qx + px) reads z_hat
+// rows qy - 1 + py + r, r in {0, 1}: for py = 0, r = 0 collects kernel row 0
+// and r = 1 kernel rows 1 and 2; for py = 1, r = 0 collects rows 0 and 1 and
+// r = 1 row 2 (columns likewise).  The latent always has even height and
+// width, so the upsampling is never cropped and every output parity class
+// (py, px) is a 2x2 conv over z_hat with summed weights: 4 taps instead of 9.
+// The host sums each class's weights in double and splits them into three
+// bf16 parts; products with the symbols (integers -32..32, exact in bf16) are
+// exact and the sums float32.
+//
+// A workgroup takes a 4 x 8FM tile of z_hat positions and 64 output channels;
+// wave w computes class (py, px) = (w / 2, w % 2) as FM blocks of 32 positions
+// (4 rows x 8 columns) on v_mfma_f32_32x32x16_bf16 with the weights as the
+// first operand, so a lane ends with 16 channels of one position.  K order:
+// tap, 16-channel half, weight part, then the MFMA's own.  Both operands are
+// L2-resident and come straight from device memory, D K steps ahead.
+// Weights: [class][tap][part][cout][32 channels] bf16.
+template <int FM>
+__global__ void __launch_bounds__(256) params_up2_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs,
+                                                         const int4* __restrict__ work, int nwork) {
+  constexpr int ZTW = 8 * FM;                  // z_hat columns per tile
+  constexpr int NS = 8, D = 2;                 // K steps (4 taps x 2 halves), lookahead
+  ConvArgs a;
+  int tile, n0;
+  // Workgroups are dispatched round-robin over the 8 XCDs; each XCD takes a
+  // contiguous band of items, numbered tile-major with the channel block
+  // fastest, so the four blocks of a tile (a position's 256 channels of P)
+  // are written from one L2 at about the same time.
+  if (descs) {
+    const int per = (nwork + 7) >> 3;
+    const int wi = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (wi >= nwork) return;
+    const int4 w = work[wi];
+    a = descs[w.x];
+    tile = w.y;
+    n0 = w.z;
+  } else {
+    a = a0;
+    const int nt = ((a.Hout + 7) / 8) * ((a.Wout + 2 * ZTW - 1) / (2 * ZTW));
+    const int nb = a.cout / 64;
+    const int per = (nt + 7) >> 3;
+    const int L = blockIdx.x >> 3;
+    tile = (blockIdx.x & 7) * per + L / nb;
+    if (tile >= nt) return;
+    n0 = (L % nb) * 64;
+  }
+  const int lane = threadIdx.x & 63;
+  const int cls = threadIdx.x >> 6;
+  const int py = cls >> 1, px = cls & 1;
+  const int kh = lane >> 5;                    // channels 8kh..8kh+7 of a half
+  const int j = lane & 31;
+  const int hz = a.Hout >> 1, wz = a.Wout >> 1;
+  const int tiles_x = (wz + ZTW - 1) / ZTW;
+  const int qy = (tile / tiles_x) * 4 + (j >> 3);
+  const int qx0 = (tile % tiles_x) * ZTW + (j & 7);
+  const unsigned char* __restrict__ zs = static_cast<const unsigned char*>(a.in);
+  const __bf16* __restrict__ wl =
+      static_cast<const __bf16*>(a.wpk) + ((long)cls * 12 * a.cout + n0 + j) * 32 + kh * 8;
+
+  v4u wa[NS][6];                               // [step][part * 2 + fn]
+  v2u zb[NS][FM];
+  bool zok[NS][FM];
+  auto load = [&](int k) {
+    const int t = k >> 1, half = k & 1;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int fn = 0; fn < 2; ++fn)
+        wa[k][p * 2 + fn] = ld16(wl + ((long)(t * 3 + p) * a.cout + fn * 32) * 32 + half * 16);
+    const int zy = qy - 1 + py + (t >> 1);
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm) {
+      const int zx = qx0 + fm * 8 - 1 + px + (t & 1);
+      zok[k][fm] = zy >= 0 && zy < hz && zx >= 0 && zx < wz;
+      const long zpos = (long)min(max(zy, 0), hz - 1) * wz + min(max(zx, 0), wz - 1);
+      zb[k][fm] = ldg(reinterpret_cast<const v2u*>(zs + zpos * a.in_pitch + half * 16 + kh * 8));
+    }
+  };
+  f32x16 acc[FM][2];
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < 2; ++fn)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[fm][fn][r] = 0.f;
+#pragma unroll
+  for (int k = 0; k < D; ++k) load(k);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    if (k + D < NS) load(k + D);
+    // keep the prefetch ahead of this step's multiplications
+    __builtin_amdgcn_sched_barrier(0);
+    bf16x8 xb[FM];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm) {
+      const v2u v = zb[k][fm];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        xb[fm][i] = (__bf16)(float)((int)((v.x >> (8 * i)) & 255u) - 32);
+        xb[fm][4 + i] = (__bf16)(float)((int)((v.y >> (8 * i)) & 255u) - 32);
+      }
+      if (!zok[k][fm]) xb[fm] = bf16x8{};
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int fn = 0; fn < 2; ++fn)
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+          acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, wa[k][p * 2 + fn]),
+                                                               xb[fm], acc[fm][fn], 0, 0, 0);
+  }
+  // Register r of a lane holds channel 8 (r / 4) + 4 kh + r % 4 of position
+  // j.  A block's 32 positions x 64 channels pass through LDS (rows of 64
+  // floats padded by 4) and leave as 16-byte stores of which 16 consecutive
+  // lanes cover one position's 256 contiguous bytes: whole 128-byte lines
+  // instead of 32-byte pieces of 32 lines per store.
+  constexpr int RS = 68;
+  __shared__ __attribute__((aligned(16))) float tbuf[4][32 * RS];
+  float* tb = tbuf[cls];
+  const int qy0 = (tile / tiles_x) * 4, qxt = (tile % tiles_x) * ZTW;
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm) {
+#pragma unroll
+    for (int fn = 0; fn < 2; ++fn)
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        *reinterpret_cast<v4f*>(tb + j * RS + fn * 32 + 8 * g + 4 * kh) =
+            v4f{acc[fm][fn][4 * g], acc[fm][fn][4 * g + 1], acc[fm][fn][4 * g + 2], acc[fm][fn][4 * g + 3]};
+    // (a wave's LDS accesses complete in order; this only pins the code order)
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int pp = it * 4 + (lane >> 4);
+      const v4f v = *reinterpret_cast<const v4f*>(tb + pp * RS + (lane & 15) * 4);
+      const int zy = qy0 + (pp >> 3), zx = qxt + fm * 8 + (pp & 7);
+      if (zy < hz && zx < wz) {
+        const long pos = (long)(2 * zy + py) * a.Wout + 2 * zx + px;
+        const int n = n0 + (lane & 15) * 4;
+        v4f o = v;
+        if (a.add) o += ldg(reinterpret_cast<const v4f*>(a.add + pos * a.add_pitch + n));
+        stg(reinterpret_cast<v4f*>(static_cast<float*>(a.out) + pos * a.out_pitch + n), o);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -1183,6 +1319,10 @@ conv3x3_ring_kernel(ConvArgs a0, const ConvArgs* __restrict__ descs, const int4*
 //     34 = 8x16 tile,  64 channels, 4x1 waves of 32x64; P
 //     35 = 16x16 tile, 32 channels, 4x1 waves of 64x32
 //     36 = 16x16 tile, 32 channels, 4x1 waves of 64x32; P
+//   params_up2_kernel (the entropy-parameter conv over up2(z_hat), and
+//   nothing else; output tile, i.e. twice the hyper-latent tile):
+//     37 = 8x32 tile,  64 channels, one wave per output parity class
+//     38 = 8x48 tile,  64 channels, one wave per output parity class
 static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 16, 128},
                                 {8, 16, 64},  {16, 16, 128}, {16, 16, 192}, {16, 16, 64},
                                 {16, 16, 128}, {16, 16, 64},
@@ -1194,7 +1334,8 @@ static const TileCfg kCfgs[] = {{8, 16, 128}, {8, 16, 32},  {8, 16, 192},  {4, 1
                                 {16, 16, 64}, {8, 16, 64}, {16, 16, 64}, {8, 16, 64},
                                 {16, 16, 64}, {8, 16, 64},
                                 {8, 16, 64}, {8, 16, 128},
-                                {8, 16, 64}, {8, 16, 64}, {16, 16, 32}, {16, 16, 32}};
+                                {8, 16, 64}, {8, 16, 64}, {16, 16, 32}, {16, 16, 32},
+                                {8, 32, 64}, {8, 48, 64}};
 constexpr int kFirstRing = 10, kLastRing = 19, kFirstRing2 = 25, kLastRing2 = 30;
 constexpr int kFirstSplitK = 31, kLastSplitK = 32, kFirstRing3 = 33, kLastRing3 = 36;
 int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
@@ -1204,6 +1345,11 @@ bool conv_cfg_supported(int prec, int loader, int stride, int cin, int cout, int
   if (stride == 2 || cfg == kHyperCfg)
     return cfg == kHyperCfg && stride == 2 && prec == P_F32 && loader == LD_NHWC &&
            (cin == 64 || cin == 128) && cout % 16 == 0;
+  // the entropy-parameter conv over up2(z_hat) has its own kernel, whose two
+  // configurations sum in the same order
+  const bool params = cfg == kParamsCfg0 || cfg == kParamsCfg1;
+  if (loader == LD_UP2 || params)
+    return params && loader == LD_UP2 && prec == P_BF16 && stride == 1 && cin == 32 && cout % 64 == 0;
   const bool ring = (cfg >= kFirstRing && cfg <= kLastRing) || (cfg >= kFirstRing2 && cfg <= kLastRing2) ||
                     (cfg >= kFirstRing3 && cfg <= kLastRing3);
   // FP8 synthesis convs: the ring kernel on a quantised copy of the input
@@ -1399,6 +1545,27 @@ static hipError_t run_hyper(const ConvArgs& a, int groups, const ConvArgs* descs
   return hipGetLastError();
 }
 
+template <int FM>
+static hipError_t run_params(const ConvArgs& a, const ConvArgs* descs, const int4* work, int nwork,
+                             hipStream_t s) {
+  dim3 grid;
+  if (descs) {
+    if (nwork <= 0) return hipSuccess;
+    grid = dim3(((nwork + 7) / 8) * 8, 1, 1);
+  } else {
+    // even latent (never a cropped upsampling), 32 symbol channels, 64-channel
+    // output blocks, no activation
+    if (((a.Hout | a.Wout) & 1) || a.Hin != a.Hout || a.Win != a.Wout || a.cin != 32 || a.in_pitch != 32 ||
+        a.cout <= 0 || a.cout % 64 || a.relu)
+      return hipErrorInvalidValue;
+    const int tiles = ((a.Hout + 7) / 8) * ((a.Wout + 16 * FM - 1) / (16 * FM));
+    if (tiles == 0) return hipSuccess;
+    grid = dim3(((tiles + 7) / 8) * 8 * (a.cout / 64), 1, 1);
+  }
+  hipLaunchKernelGGL(params_up2_kernel<FM>, grid, dim3(256), 0, s, a, descs, work, nwork);
+  return hipGetLastError();
+}
+
 template <int PREC, int LD, int ST, int STRIDE>
 static hipError_t run_cfg(int cfg, const ConvArgs& a, int groups, const ConvArgs* d,
                           const int4* w, int nw, hipStream_t s) {
@@ -1478,8 +1645,13 @@ static hipError_t dispatch(int prec, int loader, int store, int stride, int cfg,
   UFVC_CONV(P_BF16, LD_NHWC, ST_SHUFFLE, 1)
   UFVC_CONV(P_BF16, LD_F32, ST_BF16, 1)
   // entropy parameters: float32 weights as three bf16 parts (exact products)
-  UFVC_CONV(P_BF16, LD_UP2, ST_F32, 1)
   UFVC_CONV(P_BF16, LD_REP, ST_F32, 1)
+  if (loader == LD_UP2) {
+    if (prec != P_BF16 || store != ST_F32 || stride != 1) return hipErrorInvalidValue;
+    if (cfg == kParamsCfg0) return run_params<2>(a, d, w, nw, s);
+    if (cfg == kParamsCfg1) return run_params<3>(a, d, w, nw, s);
+    return hipErrorInvalidValue;
+  }
   // fp8 synthesis (input quantised beforehand)
   UFVC_CONV(P_FP8, LD_NHWC, ST_BF16, 1)
   UFVC_CONV(P_FP8, LD_NHWC, ST_SHUFFLE, 1)

@@ -108,6 +108,7 @@ static const char* kStageNames[S_COUNT] = {
 namespace ufvc {
 inline int default_cfg(int cout, long npos, int stride = 1, int loader = -1, int prec = -1) {
   if (stride == 2) return kHyperCfg;
+  if (loader == LD_UP2) return kParamsCfg0;
   // the patchify loader runs split over K (its only configurations)
   if (loader == LD_UNSHUFFLE) return 31;
   // FP8 convs run on the ring kernel only (16x16 or 8x16 tiles, 64 channels)
