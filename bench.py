@@ -39,27 +39,27 @@ PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
 # copies in the same run, per tile configuration index.  They hold only for
 # the conv sources they were taken with: bench reports them while the SHA-256
 # of ufvc_conv.hip followed by ufvc_common.h still matches, and null otherwise.
-TRAFFIC_SHA256 = "d8646b1f881db71a33991fc9451e13a1f89cabb13b5c9b9d349a424c96c6d618"
+TRAFFIC_SHA256 = "a8980a151be0ef47c99be958c8be53f52f8443a650c624de9fd941f1477e416b"
 TRAFFIC = {  # (stage, tile configuration): (read bytes, write bytes)
-    ("a1_conv", 31): (251.13e6, 8.36e6),
-    ("a1_conv", 32): (251.1e6, 8.36e6),
-    ("k3_conv", 12): (103.41e6, 199.07e6),
-    ("k3_conv", 13): (117.09e6, 199.07e6),
-    ("k3_conv", 15): (116.09e6, 199.07e6),
+    ("a1_conv", 31): (251.15e6, 8.36e6),
+    ("a1_conv", 32): (251.12e6, 8.36e6),
+    ("k3_conv", 12): (103.35e6, 199.07e6),
+    ("k3_conv", 13): (115.67e6, 199.07e6),
+    ("k3_conv", 15): (116.07e6, 199.07e6),
     ("k3_conv", 16): (102.59e6, 199.07e6),
-    ("k3_conv", 17): (102.37e6, 199.07e6),
-    ("k3_conv", 18): (115.11e6, 199.07e6),
-    ("k3_conv", 19): (103.71e6, 199.07e6),
-    ("k3_conv", 25): (83.57e6, 199.1e6),
-    ("k3_conv", 26): (74.6e6, 199.07e6),
-    ("k3_conv", 27): (114.26e6, 199.07e6),
-    ("k3_conv", 28): (103.29e6, 199.07e6),
-    ("k3_conv", 29): (84.42e6, 199.12e6),
-    ("k3_conv", 30): (73.06e6, 199.07e6),
-    ("k3_conv", 33): (102.39e6, 199.07e6),
-    ("k3_conv", 34): (77.01e6, 199.07e6),
-    ("k3_conv", 35): (102.97e6, 199.08e6),
-    ("k3_conv", 36): (79.15e6, 199.27e6),
+    ("k3_conv", 17): (102.39e6, 199.07e6),
+    ("k3_conv", 18): (115.12e6, 199.07e6),
+    ("k3_conv", 19): (103.49e6, 199.07e6),
+    ("k3_conv", 25): (82.98e6, 199.1e6),
+    ("k3_conv", 26): (74.58e6, 199.07e6),
+    ("k3_conv", 27): (115.15e6, 199.07e6),
+    ("k3_conv", 28): (103.25e6, 199.07e6),
+    ("k3_conv", 29): (84.16e6, 199.11e6),
+    ("k3_conv", 30): (72.97e6, 199.07e6),
+    ("k3_conv", 33): (102.4e6, 199.07e6),
+    ("k3_conv", 34): (76.81e6, 199.07e6),
+    ("k3_conv", 35): (102.98e6, 199.07e6),
+    ("k3_conv", 36): (78.94e6, 199.27e6),
 }
 
 
