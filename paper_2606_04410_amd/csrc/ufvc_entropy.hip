@@ -424,54 +424,18 @@ __device__ unsigned long long block_exclusive_scan(unsigned long long run, unsig
   return before + inc - run;
 }
 
-// Container assembly, step 1, one block per chunk: every segment's byte
-// count from its word count, their exclusive prefix sum (thread t owns the
-// contiguous run of segments [t K, t K + K), K = ceil(n_seg / blockDim); one
-// block scan of the run sums), the segments' byte offsets in the container,
-// the total size, and the header and segment table.  When the container does
-// not fit the capacity nothing is written to the output.
-__global__ void __launch_bounds__(256)
-compact_scan_kernel(CompDesc d0, const CompDesc* __restrict__ descs) {
-  __shared__ unsigned long long s_wave[4];
-  const CompDesc d = descs ? descs[blockIdx.x] : d0;
-  const SegInfo* __restrict__ info = d.info;
-  const int nseg = d.n_seg_z + d.n_seg_y;
-  const size_t h0 = (d.with_header ? 28u : 0u) + 4u * (size_t)nseg;
-  const int K = (nseg + (int)blockDim.x - 1) / (int)blockDim.x;
-  const int r0 = min((int)threadIdx.x * K, nseg), r1 = min(r0 + K, nseg);
-  unsigned long long run = 0;
-  for (int i = r0; i < r1; ++i) run += seg_bytes_of(info[i]);
-  unsigned long long all = 0;
-  unsigned long long off = h0 + block_exclusive_scan(run, s_wave, &all);
-  const unsigned long long total = h0 + all;
-  if (threadIdx.x == 0) d.result[0] = total;
-  if (total > d.capacity) return;
-  uint8_t* __restrict__ out = d.out;
-  uint32_t* tab = reinterpret_cast<uint32_t*>(out + (d.with_header ? 28 : 0));
-  for (int i = r0; i < r1; ++i) {
-    const uint32_t sb = seg_bytes_of(info[i]);
-    d.seg_off[i] = (uint32_t)off;
-    tab[i] = sb;
-    off += sb;
-  }
-  if (d.with_header && threadIdx.x == 0) {
-    const HeaderFields hf = d.hf;
-    uint32_t* h = reinterpret_cast<uint32_t*>(out);
-    h[0] = 0x31564655u;  // "UFV1"
-    h[1] = (uint32_t)hf.T | ((uint32_t)hf.C << 16);
-    h[2] = (uint32_t)hf.H | ((uint32_t)hf.W << 16);
-    h[3] = (uint32_t)hf.seg_log2 | ((uint32_t)hf.seg_log2_z << 8) | ((uint32_t)hf.k_z << 16) |
-           ((uint32_t)hf.flags << 24);
-    h[4] = hf.model_tag;
-    h[5] = (uint32_t)d.n_seg_z;
-    h[6] = (uint32_t)d.n_seg_y;
-  }
-}
-
-// Container assembly, step 2, one block per segment: the 32 final states,
-// then the words, at the offset step 1 computed.
+// Container assembly, one block per segment.  Every block sums the byte
+// counts of all segments and of those before its own (thread t owns the
+// contiguous run [t K, t K + K), K = ceil(n_seg / blockDim); one block scan
+// of the run sums, read back at the block's own segment), which gives the
+// total size, checked against the capacity, and its segment's byte offset;
+// block 0 also writes the header, the segment table and the size.  When the
+// container does not fit the capacity nothing is written to the output.
+// Then the block copies its segment: the 32 final states, then the words.
 __global__ void __launch_bounds__(256)
 compact_kernel(CompDesc d0, const CompDesc* __restrict__ descs, const int2* __restrict__ map) {
+  __shared__ unsigned long long s_wave[4];
+  __shared__ unsigned long long s_run_before[256];
   int b = blockIdx.x;
   CompDesc d;
   if (descs) {
@@ -481,12 +445,54 @@ compact_kernel(CompDesc d0, const CompDesc* __restrict__ descs, const int2* __re
   } else {
     d = d0;
   }
+  const SegInfo* __restrict__ info = d.info;
   const int n_seg_z = d.n_seg_z;
-  if (b >= n_seg_z + d.n_seg_y || ldg(d.result) > d.capacity) return;
-  const SegInfo si = d.info[b];
+  const int nseg = n_seg_z + d.n_seg_y;
+  if (b >= max(nseg, 1)) return;   // (an empty stream still gets block 0: the header)
+  const size_t h0 = (d.with_header ? 28u : 0u) + 4u * (size_t)nseg;
+  const int K = (nseg + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int r0 = min((int)threadIdx.x * K, nseg), r1 = min(r0 + K, nseg);
+  unsigned long long run = 0;
+  for (int i = r0; i < r1; ++i) run += seg_bytes_of(info[i]);
+  unsigned long long all = 0;
+  const unsigned long long before = block_exclusive_scan(run, s_wave, &all);
+  s_run_before[threadIdx.x] = before;
+  __syncthreads();
+  const unsigned long long total = h0 + all;
+  if (total > d.capacity) {
+    if (b == 0 && threadIdx.x == 0) d.result[0] = total;
+    return;
+  }
+  uint8_t* __restrict__ out = d.out;
+  if (b == 0) {
+    // the size, the segment table and the header
+    if (threadIdx.x == 0) d.result[0] = total;
+    uint32_t* tab = reinterpret_cast<uint32_t*>(out + (d.with_header ? 28 : 0));
+    for (int i = r0; i < r1; ++i) tab[i] = seg_bytes_of(info[i]);
+    if (d.with_header && threadIdx.x == 0) {
+      const HeaderFields hf = d.hf;
+      uint32_t* h = reinterpret_cast<uint32_t*>(out);
+      h[0] = 0x31564655u;  // "UFV1"
+      h[1] = (uint32_t)hf.T | ((uint32_t)hf.C << 16);
+      h[2] = (uint32_t)hf.H | ((uint32_t)hf.W << 16);
+      h[3] = (uint32_t)hf.seg_log2 | ((uint32_t)hf.seg_log2_z << 8) | ((uint32_t)hf.k_z << 16) |
+             ((uint32_t)hf.flags << 24);
+      h[4] = hf.model_tag;
+      h[5] = (uint32_t)d.n_seg_z;
+      h[6] = (uint32_t)d.n_seg_y;
+    }
+  }
+  if (b >= nseg) return;
+  // this segment's offset: the runs before its owner's, then the owner's
+  // own segments before it (a handful of cache hits)
+  const int owner = b / K;
+  unsigned long long off = h0 + s_run_before[owner];
+  for (int i = owner * K; i < b; ++i) off += seg_bytes_of(info[i]);
+  if (threadIdx.x == 0) d.seg_off[b] = (uint32_t)off;
+  const SegInfo si = info[b];
   const uint8_t* src = b < n_seg_z ? d.scratch_z + (size_t)b * d.slot_z
                                    : d.scratch_y + (size_t)(b - n_seg_z) * d.slot_y;
-  uint8_t* dst = d.out + ldg(d.seg_off + b);
+  uint8_t* dst = out + off;
   if (threadIdx.x < LANES)
     reinterpret_cast<uint32_t*>(dst)[threadIdx.x] = reinterpret_cast<const uint32_t*>(src)[threadIdx.x];
   // words in pairs: 4-byte stores (dst is 4-byte aligned: every segment's
@@ -520,19 +526,16 @@ hipError_t launch_compact(const uint8_t* scratch, size_t slot_bytes_z, size_t sl
   d.capacity = capacity;
   d.result = result;
   d.seg_off = seg_off;
-  hipLaunchKernelGGL(compact_scan_kernel, dim3(1), dim3(256), 0, s, d, (const CompDesc*)nullptr);
-  if (nseg > 0)
-    hipLaunchKernelGGL(compact_kernel, dim3(nseg), dim3(256), 0, s, d, (const CompDesc*)nullptr,
-                       (const int2*)nullptr);
+  hipLaunchKernelGGL(compact_kernel, dim3(nseg > 0 ? nseg : 1), dim3(256), 0, s, d, (const CompDesc*)nullptr,
+                     (const int2*)nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_compact_batch(const CompDesc* d, int nchunks, const int2* map, int nblocks,
                                 hipStream_t s) {
-  if (nchunks <= 0) return hipSuccess;
+  if (nchunks <= 0 || nblocks <= 0) return hipSuccess;
   CompDesc none{};
-  hipLaunchKernelGGL(compact_scan_kernel, dim3(nchunks), dim3(256), 0, s, none, d);
-  if (nblocks > 0) hipLaunchKernelGGL(compact_kernel, dim3(nblocks), dim3(256), 0, s, none, d, map);
+  hipLaunchKernelGGL(compact_kernel, dim3(nblocks), dim3(256), 0, s, none, d, map);
   return hipGetLastError();
 }
 
